@@ -1,0 +1,490 @@
+"""Pins for the CPU oracle: each test ties an oracle function to something other
+than itself (a textbook routine, a closed form, an invariant the paper's
+algorithm implies, a published test vector, or brute force on a tiny input).
+
+Paper references: Sec. 2.1 Eq. 1 (k-NN), Sec. 2.2 Eq. 2 and Steps 1-4 (beam
+search), Sec. 3.1.2 (I(u) and the staged search), Sec. 3.2.2 (ghost staging),
+Sec. 3.3.2 / Sec. 4 (direction table and selection), Sec. 5.1 (Recall@k).
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import breadth_first_order, connected_components
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def f32_order(D64, k):
+    """Brute force order by (f32(dist), id) from float64 squared distances (numpy)."""
+    D32 = D64.astype(np.float32)
+    n = D32.shape[1]
+    return np.stack([np.lexsort((np.arange(n), row))[:k] for row in D32])
+
+
+def small(n=400, d=16, C=4, sigma=0.3, seed=1):
+    return synth.mixture_small(n, d, C, sigma, seed)
+
+
+# ---------------------------------------------------------------------------
+# Random numbers
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_vector():
+    vals = [int(x) for x in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) if not x.startswith("#")]
+    seed, expect = vals[0], vals[1:]
+    assert [oracle.splitmix(seed, i + 1) for i in range(5)] == expect
+
+
+def test_keyed_order_is_permutation_and_partition_covers():
+    perm = oracle.keyed_order(123, 1000)
+    assert sorted(perm.tolist()) == list(range(1000))
+    assert not np.array_equal(perm, np.arange(1000))
+    parts = oracle.partition(1001, 4, 5)
+    allids = np.concatenate(parts)
+    assert sorted(allids.tolist()) == list(range(1001))
+    assert [len(p) for p in parts] == [(s + 1) * 1001 // 4 - s * 1001 // 4 for s in range(4)]
+    assert np.array_equal(oracle.partition(50, 1, 5)[0], np.arange(50))
+
+
+def test_ghost_sample_uniform_without_replacement():
+    g = oracle.ghost_sample(10000, 500, 9, 0)
+    assert len(np.unique(g)) == 500 and np.all(np.diff(g.astype(np.int64)) > 0) and g.max() < 10000
+    # roughly uniform: counts per decile within 5 sigma of 50
+    h = np.histogram(g, bins=10, range=(0, 10000))[0]
+    assert np.all(np.abs(h - 50) < 5 * np.sqrt(50))
+
+
+# ---------------------------------------------------------------------------
+# Eq. 2 (squared) and Eq. 1
+# ---------------------------------------------------------------------------
+def test_distance_matches_float64_textbook_then_rounded():
+    X = small(50, 37)
+    q = small(1, 37, seed=2)[0]
+    for v in range(50):
+        ref = np.float32(((q.astype(np.float64) - X[v].astype(np.float64)) ** 2).sum())
+        assert oracle.dist(X, q, v) == float(ref)
+
+
+def test_distance_u8_exact():
+    rng = np.random.default_rng(0)
+    X = rng.integers(0, 256, (20, 128)).astype(np.uint8)
+    q = rng.integers(0, 256, 128).astype(np.uint8)
+    for v in range(20):
+        assert oracle.dist(X, q, v) == float(((q.astype(np.int64) - X[v].astype(np.int64)) ** 2).sum())
+    # the largest possible value fits int32
+    X0 = np.zeros((1, 128), np.uint8)
+    q255 = np.full(128, 255, np.uint8)
+    assert oracle.dist(X0, q255, 0) == 255 * 255 * 128
+
+
+@pytest.mark.parametrize("k", [1, 7, 30])
+def test_exact_knn_equals_numpy_brute_force(k):
+    X = small(300, 24)
+    Q = small(40, 24, seed=2)
+    ids, ds = oracle.knn(X, Q, k)
+    _, D = oracle.brute_force_numpy(X, Q, k)
+    assert np.array_equal(ids, f32_order(D, k))
+    assert np.array_equal(ds.astype(np.float32), np.take_along_axis(D, ids.astype(np.int64), 1).astype(np.float32))
+
+
+def test_exact_knn_u8_ties_broken_by_id():
+    rng = np.random.default_rng(3)
+    X = rng.integers(0, 4, (200, 8)).astype(np.uint8)  # many exact ties
+    Q = rng.integers(0, 4, (10, 8)).astype(np.uint8)
+    ids, ds = oracle.knn(X, Q, 20)
+    D = ((Q[:, None, :].astype(np.int64) - X[None].astype(np.int64)) ** 2).sum(-1)
+    for i in range(10):
+        assert ids[i].tolist() == np.lexsort((np.arange(200), D[i]))[:20].tolist()
+
+
+def test_knn_exclude_self():
+    X = small(100, 8)
+    ids, _ = oracle.knn(X, X, 5, exclude_self=True)
+    assert not np.any(ids == np.arange(100)[:, None])
+
+
+def test_recall_closed_form():
+    gt = np.array([[1, 2, 3, 4], [5, 6, 7, 8]])
+    ann = np.array([[4, 3, 9, 9], [5, 6, 7, 8]])
+    assert oracle.recall(gt, ann, 4) == (2 + 4) / 8
+
+
+# ---------------------------------------------------------------------------
+# Graph: k-NN lists pruned to a fixed degree (reverse-merge rule)
+# ---------------------------------------------------------------------------
+def test_prune_rule_properties():
+    X = small(300, 12)
+    deg, K0 = 8, 16
+    knn_ids, knn_d = oracle.knn(X, X, K0, exclude_self=True)
+    G = oracle.prune(X, knn_ids, knn_d, deg)
+    half = (deg + 1) // 2
+    rev = [set() for _ in range(300)]
+    for v in range(300):
+        for u in knn_ids[v, :half]:
+            rev[u].add(v)
+    for u in range(300):
+        row = G[u].tolist()
+        assert len(set(row)) == deg and u not in row
+        dd = [oracle.dist(X, X[u], v) for v in row]
+        assert all((dd[i], row[i]) < (dd[i + 1], row[i + 1]) for i in range(deg - 1))
+        F = set(knn_ids[u, :half].tolist())
+        assert F <= set(row)
+        # reverse candidates (nearest first) come before the k-NN tail
+        rc = sorted(rev[u] - F, key=lambda v: (oracle.dist(X, X[u], v), v))
+        expect = list(F) + rc[: deg - half]
+        tail = [v for v in knn_ids[u, half:].tolist() if v not in set(expect)]
+        expect = expect + tail[: deg - len(expect)]
+        assert set(row) == set(expect)
+
+
+# ---------------------------------------------------------------------------
+# Direction table (Sec. 3.3.2 (a)) and query sign bits
+# ---------------------------------------------------------------------------
+def test_sign_table_unit_vectors():
+    d = 70  # W = 3, with pad bits
+    X = np.zeros((d + 1, d), np.float32)
+    for i in range(d):
+        X[i + 1, i] = 1.0
+    G = np.array([[i + 1 for i in range(d)]] + [[0] * d for _ in range(d)], np.uint32)
+    S = oracle.sign_table(X, G)
+    W = (d + 31) // 32
+    assert S.shape == (d + 1, d, W)
+    for j in range(d):  # edge 0 -> e_j: exactly bit j set
+        expect = np.zeros(W, np.uint32)
+        expect[j // 32] = np.uint32(1 << (j % 32))
+        assert np.array_equal(S[0, j], expect)
+    for u in range(1, d + 1):  # edge e_i -> 0: no coordinate grows
+        assert not S[u].any()
+
+
+def test_sign_table_reverse_edge_complement_and_popcount():
+    X = small(200, 40)
+    G = oracle.build_graph(X, 8)
+    S = oracle.sign_table(X, G)
+    W = 2
+    valid = np.array([0xFFFFFFFF, (1 << 8) - 1], np.uint32)
+    pairs = 0
+    for u in range(200):
+        for j, v in enumerate(G[u]):
+            cnt = sum(bin(int(w)).count("1") for w in S[u, j])
+            assert cnt == int((X[v] > X[u]).sum())
+            assert (S[u, j] & ~valid).sum() == 0  # pad bits stay zero
+            back = np.where(G[v] == u)[0]
+            if len(back):
+                pairs += 1
+                neq = X[v] != X[u]
+                x = S[u, j] ^ S[v, back[0]]
+                assert sum(bin(int(w)).count("1") for w in x) == int(neq.sum())
+    assert pairs > 0
+
+
+# ---------------------------------------------------------------------------
+# Beam search
+# ---------------------------------------------------------------------------
+def reachable_from(G, starts):
+    n = G.shape[0]
+    A = csr_matrix((np.ones(G.size), (np.repeat(np.arange(n), G.shape[1]), G.ravel().astype(np.int64))), shape=(n, n))
+    seen = set()
+    for s in starts:
+        if s not in seen:
+            seen |= set(breadth_first_order(A, int(s), directed=True, return_predecessors=False).tolist())
+    return np.array(sorted(seen))
+
+
+def init_ids(seed, shard, qkey, n_init, n):
+    st = int(oracle.lib().orc_stream_main(seed, shard))
+    return [oracle.splitmix(st, qkey * n_init + j + 1) % n for j in range(n_init)]
+
+
+def test_pin1_exhaustive_search_is_brute_force_over_reachable():
+    X = small(300, 16, C=3)
+    Q = small(25, 16, C=3, seed=2)
+    ix = oracle.build_index(X, deg=8, dgs=False)
+    G = ix.shards[0]["graph"]
+    ids, ds, ctr = oracle.search(ix, Q, k=10, l=300, T=400, n_init=4)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    for i in range(25):
+        reach = reachable_from(G, init_ids(6, 0, i, 4, 300))
+        sub = D[i, reach].astype(np.float32)
+        order = reach[np.lexsort((reach, sub))][:10]
+        assert ids[i, : len(order)].tolist() == order.tolist()
+        assert np.all(ds[i] == np.sort(ds[i]))
+
+
+def test_pin1_connected_graph_full_brute_force():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((250, 10)).astype(np.float32)  # one blob: connected k-NN graph
+    Q = rng.standard_normal((20, 10)).astype(np.float32)
+    ix = oracle.build_index(X, deg=10, dgs=False)
+    G = ix.shards[0]["graph"]
+    n_cc = connected_components(csr_matrix((np.ones(G.size), (np.repeat(np.arange(250), 10), G.ravel().astype(np.int64))),
+                                           shape=(250, 250)), directed=True, connection="strong")[0]
+    assert n_cc == 1
+    ids, ds, _ = oracle.search(ix, Q, k=10, l=250, T=300)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    assert np.array_equal(ids, f32_order(D, 10))
+
+
+def test_pin2_outputs_sorted_and_distances_recomputed():
+    X = small(500, 20)
+    Q = small(30, 20, seed=2)
+    ix = oracle.build_index(X, deg=8, dgs=True, ghost_ratio=0.05, deg_g=8)
+    for kw in [dict(), dict(dgs_on=True), dict(entry="ghost_graph"), dict(entry="ghost_dense", dgs_on=True, r=2)]:
+        ids, ds, _ = oracle.search(ix, Q, k=10, l=32, T=40, **kw)
+        for i in range(30):
+            keys = [(float(ds[i, j]), int(ids[i, j])) for j in range(10)]
+            assert keys == sorted(keys)
+            for j in range(10):
+                ref = np.float32(((Q[i].astype(np.float64) - X[ids[i, j]].astype(np.float64)) ** 2).sum())
+                assert ds[i, j] == ref
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(dgs_on=True), dict(r=2), dict(dgs_on=True, r=3, entry="ghost_graph")])
+def test_pin4_visited_policy_does_not_change_results(kw):
+    X = small(800, 16, C=6)
+    Q = small(40, 16, C=6, seed=2)
+    ix = oracle.build_index(X, deg=12, dgs=True, ghost_ratio=0.05, deg_g=8)
+    base = oracle.search(ix, Q, k=10, l=24, T=60, **kw)
+    for pol in ("forget_each_iter", "small_hash"):
+        other = oracle.search(ix, Q, k=10, l=24, T=60, visited=pol, **kw)
+        assert np.array_equal(base[0], other[0]) and np.array_equal(base[1], other[1])
+        # expansions and iterations are identical; only the distance count may grow
+        assert np.array_equal(base[2][:, 1:4], other[2][:, 1:4])
+        assert np.all(other[2][:, 0] >= base[2][:, 0])
+        assert other[2][:, 0].sum() > base[2][:, 0].sum()
+
+
+def test_pin5_special_cases_reduce_to_plain():
+    X = small(600, 16, C=5)
+    Q = small(30, 16, C=5, seed=2)
+    ix = oracle.build_index(X, deg=10, dgs=True)
+    plain = oracle.search(ix, Q, k=10, l=32, T=50)
+    for kw in [dict(dgs_on=True, discard=0.0), dict(dgs_on=True, cooldown=1.0), dict(ppe_on=False)]:
+        o = oracle.search(ix, Q, k=10, l=32, T=50, **kw)
+        assert np.array_equal(plain[0], o[0]) and np.array_equal(plain[1], o[1])
+        assert np.array_equal(plain[2][:, :3], o[2][:, :3])
+    # DGS on with discard > 0 really changes the work done
+    o = oracle.search(ix, Q, k=10, l=32, T=50, dgs_on=True)
+    assert o[2][:, 3].sum() > 0
+
+
+def test_pin5_dense_ghost_over_all_nodes_is_brute_force():
+    X = small(200, 12, C=4)
+    Q = small(20, 12, C=4, seed=2)
+    ix = oracle.build_index(X, deg=8, dgs=False, ghost_R=200, deg_g=8)
+    assert np.array_equal(ix.shards[0]["g_map"], np.arange(200))
+    ids, ds, ctr = oracle.search(ix, Q, k=10, l=40, T=0, entry="ghost_dense", t_seeds=40)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    assert np.array_equal(ids, f32_order(D, 10))
+    assert np.all(ctr[:, 4] == 200)
+
+
+def test_pin13_dgs_worked_example_shape():
+    """Sec. 3.3.2 example: visiting node 5 with n = 2 keeps the two neighbours that
+    point toward the query (9 and 6); sorting gives 9, 6, 5; r = 1 next picks 9."""
+    X = np.zeros((12, 2), np.float32)
+    X[5] = [0.0, 0.0]
+    X[9] = [2.0, 2.0]   # toward the query, nearest to it
+    X[6] = [1.0, 1.5]   # toward the query
+    X[2] = [-1.0, -1.0] # away
+    X[3] = [-0.5, 1.0]  # mixed
+    for i, v in enumerate([0, 1, 4, 7, 8, 10, 11]):
+        X[v] = [-5.0 - i, -5.0]
+    q = np.array([[3.0, 3.0]], np.float32)
+    G = np.zeros((12, 4), np.uint32)
+    G[5] = [2, 3, 6, 9]
+    for u in range(12):
+        if u != 5:
+            G[u] = [5, 2, 3, 6] if u != 5 else G[u]
+    G[9] = [5, 6, 2, 3]
+    ix = oracle.build_index(X, deg=4, dgs=True, graph=G)
+    S = ix.shards[0]["sign"]
+    assert S[5, 3, 0] == 0b11 and S[5, 2, 0] == 0b11 and S[5, 0, 0] == 0
+    ids, ds, ctr = oracle.search(ix, q, k=3, l=3, T=1, entry="seeds", seeds=np.array([[5]]),
+                                 dgs_on=True, discard=0.5, cooldown=0.0, n_init=1)
+    assert ids[0].tolist() == [9, 6, 5]
+    assert ctr[0, 0] == 3 and ctr[0, 3] == 2 and ctr[0, 1] == 1
+    # second iteration expands node 9 (the first fresh entry); its DGS picks are
+    # already visited or pointing away, so nothing new enters.
+    ids2, _, ctr2 = oracle.search(ix, q, k=3, l=3, T=2, entry="seeds", seeds=np.array([[5]]),
+                                  dgs_on=True, discard=0.5, cooldown=0.0, n_init=1)
+    assert ids2[0].tolist() == [9, 6, 5] and ctr2[0, 1] == 2
+
+
+def test_dgs_cooldown_and_forced_cooldown_counts():
+    X = small(400, 16, C=3)
+    Q = small(10, 16, C=3, seed=2)
+    ix = oracle.build_index(X, deg=8, dgs=True)
+    T = 40
+    _, _, c = oracle.search(ix, Q, k=5, l=16, T=T, dgs_on=True, discard=0.5, cooldown=0.3)
+    n_dgs_iters = T - int(np.ceil(0.3 * T))
+    # every DGS-phase expansion skips exactly floor(0.5 * 8) = 4 slots
+    assert np.all(c[:, 3] % 4 == 0) and np.all(c[:, 3] <= 4 * n_dgs_iters)
+
+
+def test_random_discard_ablation_differs_from_dgs():
+    X = small(800, 32, C=5)
+    Q = small(40, 32, C=5, seed=2)
+    ix = oracle.build_index(X, deg=12, dgs=True)
+    a = oracle.search(ix, Q, k=10, l=32, T=60, dgs_on=True)
+    b = oracle.search(ix, Q, k=10, l=32, T=60, dgs_on=True, random_discard=True)
+    assert not np.array_equal(a[0], b[0])
+    assert np.array_equal(a[2][:, 3] > 0, b[2][:, 3] > 0)
+
+
+# ---------------------------------------------------------------------------
+# Path extension over shards (Sec. 3.1.2)
+# ---------------------------------------------------------------------------
+def test_pin7_inter_shard_map_is_brute_force_1nn():
+    X = small(400, 12, C=3)
+    ix = oracle.build_index(X, deg=8, S=3, dgs=False)
+    for s in range(3):
+        A = ix.shards[s]["orig_base"]
+        B = ix.shards[(s + 1) % 3]["orig_base"]
+        _, D = oracle.brute_force_numpy(B, A, 1)
+        assert np.array_equal(ix.shards[s]["next"], f32_order(D, 1)[:, 0])
+
+
+def test_ppe_exhaustive_stages_merge_to_global_brute_force():
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((360, 8)).astype(np.float32)
+    Q = rng.standard_normal((15, 8)).astype(np.float32)
+    ix = oracle.build_index(X, deg=10, S=3, dgs=False)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    for ppe in (True, False):
+        ids, ds, ctr = oracle.search(ix, Q, k=10, l=120, T=200, ppe_on=ppe)
+        assert np.array_equal(ids, f32_order(D, 10))
+
+
+def test_ppe_handoff_chain_with_zero_iterations():
+    """With T = 0 each stage only evaluates its seeds: stage 0 the random start
+    nodes, stage t the single node I(z) handed over (f = 1). The merged result is
+    the chain z0, I(z0), I(I(z0)) ... in global ids, sorted."""
+    X = small(300, 8, C=3)
+    Q = small(6, 8, C=3, seed=2)
+    S = 3
+    ix = oracle.build_index(X, deg=8, S=S, dgs=False)
+    ids, ds, ctr = oracle.search(ix, Q, k=3, l=8, T=0, n_init=1)
+    for i in range(6):
+        s0 = i % S
+        sh = ix.shards[s0]
+        starts = init_ids(6, s0, i, 1, sh["n"])
+        dd = [(oracle.dist(sh["orig_base"], Q[i], v), v) for v in set(starts)]
+        z = min(dd)[1]
+        chain = [(float(np.float32(min(dd)[0])), int(sh["gmap"][z]))]
+        s = s0
+        for _ in range(S - 1):
+            z = int(ix.shards[s]["next"][z])
+            s = (s + 1) % S
+            chain.append((float(np.float32(oracle.dist(ix.shards[s]["orig_base"], Q[i], z))), int(ix.shards[s]["gmap"][z])))
+        chain.sort()
+        assert ids[i].tolist() == [c[1] for c in chain]
+        assert ctr[i, 2] == 0
+
+
+# ---------------------------------------------------------------------------
+# Number formats and low-precision traversal
+# ---------------------------------------------------------------------------
+def test_pin8_fp8_decode_all_codes_vs_torch():
+    torch = pytest.importorskip("torch")
+    codes = np.arange(256, dtype=np.uint8)
+    ours = oracle.fp8_decode(codes)
+    ref = torch.from_numpy(codes).view(torch.float8_e4m3fn).float().numpy()
+    same = (ours == ref) | (np.isnan(ours) & np.isnan(ref))
+    assert same.all()
+    assert np.nanmax(ours) == 448.0 and np.isnan(ours[0x7F]) and np.isnan(ours[0xFF])
+
+
+def test_pin8_f16_decode_all_codes_vs_numpy():
+    codes = np.arange(65536, dtype=np.uint32).astype(np.uint16)
+    ours = oracle.f16_decode(codes)
+    ref = codes.view(np.float16).astype(np.float32)
+    assert ((ours == ref) | (np.isnan(ours) & np.isnan(ref))).all()
+
+
+def test_pin8_encoders_round_to_nearest_even():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.standard_normal(3000) * 50, rng.standard_normal(2000) * 1e-2,
+                        rng.uniform(-447, 447, 1000)]).astype(np.float32)
+    ours = oracle.fp8_encode(x)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(ours, ref)
+    # exact midpoints between consecutive codes go to the even code
+    vals = oracle.fp8_decode(np.arange(127, dtype=np.uint8)).astype(np.float64)
+    mids = ((vals[:-1] + vals[1:]) / 2).astype(np.float32)
+    enc = oracle.fp8_encode(mids)
+    assert np.all(enc % 2 == 0)
+    assert oracle.fp8_encode(np.array([1e6, -1e6], np.float32)).tolist() == [126, 254]  # saturate
+    h = oracle.f16_encode(x)
+    assert np.array_equal(h, x.astype(np.float16).view(np.uint16))
+
+
+def test_quantize_scale_and_error_bound():
+    X = small(50, 64)
+    X[3] = 0
+    codes, scale = oracle.quantize(X, "fp8")
+    assert scale[3] == 1.0 and not codes[3].any()
+    xt = oracle.dequantize(codes, scale, "fp8")
+    mx = np.abs(X).max(1)
+    # the largest element maps to +-448 exactly
+    for v in range(50):
+        if v != 3:
+            assert np.abs(oracle.fp8_decode(codes[v])).max() == 448.0
+    # e4m3 relative rounding error <= 2^-4 in the normal range, absolute 2^-10 * s below it
+    err = np.abs(xt - X)
+    bound = np.maximum(np.abs(X) * 2.0 ** -4, (scale[:, None] * 2.0 ** -10)) * 1.0001 + 1e-12
+    assert np.all(err <= bound)
+    c16, s16 = oracle.quantize(X, "f16")
+    assert np.all(s16 == 1.0) and np.array_equal(c16, X.astype(np.float16).view(np.uint16))
+
+
+def test_low_precision_rerank_exhaustive_matches_f32_brute_force():
+    X = small(300, 32, C=3)
+    Q = small(20, 32, C=3, seed=2)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    exact = f32_order(D, 10)
+    for store in ("f16", "fp8"):
+        ix = oracle.build_index(X, deg=10, dgs=False, store=store)
+        assert ix.shards[0]["codes"].dtype == (np.uint16 if store == "f16" else np.uint8)
+        ids, ds, ctr = oracle.search(ix, Q, k=10, l=300, T=400, n_init=300)
+        # traversal top-40 under the low-precision distance, reranked in f32
+        xt = oracle.dequantize(ix.shards[0]["codes"], ix.shards[0]["scale"], store)
+        _, Dl = oracle.brute_force_numpy(xt, Q, 40)
+        for i in range(20):
+            top40 = f32_order(Dl[i:i + 1], 40)[0]
+            sub = D[i, top40].astype(np.float32)
+            expect = top40[np.lexsort((top40, sub))][:10]
+            assert ids[i].tolist() == expect.tolist()
+            assert np.all(ds[i] == D[i, ids[i]].astype(np.float32))
+        assert np.all(ctr[:, 6] == 40)
+        assert oracle.recall(exact, ids, 10) >= 0.9
+
+
+def test_u8_search_exact_int_distances():
+    rng = np.random.default_rng(4)
+    Xf = synth.mixture_small(400, 32, 3, 0.3, 1)
+    X = synth.to_u8(Xf)
+    Q = synth.to_u8(synth.mixture_small(10, 32, 3, 0.3, 2))
+    ix = oracle.build_index(X, deg=8, dgs=True)
+    ids, ds, _ = oracle.search(ix, Q, k=5, l=32, T=40, dgs_on=True)
+    assert ds.dtype == np.int32
+    for i in range(10):
+        for j in range(5):
+            assert ds[i, j] == int(((Q[i].astype(np.int64) - X[ids[i, j]].astype(np.int64)) ** 2).sum())
+
+
+def test_degenerate_inputs():
+    X = small(60, 8)
+    ix = oracle.build_index(X, deg=4, dgs=True)
+    ids, ds, ctr = oracle.search(ix, np.zeros((0, 8), np.float32), k=3, l=8, T=5)
+    assert ids.shape == (0, 3)
+    # k == l, T == 0 (initial candidates only)
+    ids, ds, ctr = oracle.search(ix, X[:3], k=8, l=8, T=0)
+    assert np.all(ctr[:, 2] == 0) and np.all(ds[:, 0] >= 0)
+    with pytest.raises(ValueError):
+        oracle.search(ix, X[:3], k=9, l=8, T=5)
