@@ -1,0 +1,213 @@
+/*
+ * miann — MI355X-native graph beam search (PathWeaver, arXiv 2507.17094).
+ *
+ * C-ABI of the native library libmiann.so. All entry points take plain
+ * pointers and sizes. "device" pointers are HIP device (HBM) addresses on the
+ * current device; "host" pointers are ordinary process memory. Streams are
+ * hipStream_t passed as void* (NULL = the default stream).
+ *
+ * Conventions for every entry point
+ *   - Returns a miann_status; never aborts. On failure, miann_last_error()
+ *     returns a thread-local message naming the entry point and the cause.
+ *   - Arguments are validated before anything is launched; a failed call
+ *     enqueues no work and changes no output.
+ *   - Asynchronous: miann_search only enqueues work on `stream` and returns.
+ *     A device fault surfaces as MIANN_EDEVICE from a later call.
+ *   - Ownership: the caller owns queries and output buffers; an index owns
+ *     every array it holds (copied or built), and frees them in
+ *     miann_index_free.
+ *
+ * Distances are SQUARED L2, sum_i (q_i - x_i)^2 (Sec. 2.2 Eq. 2 without the
+ * square root; the order is the same). Float data: the sum of (q_i - x_i)^2
+ * is accumulated in double precision and rounded once to float. uint8 data:
+ * exact int32. Every ordering is by the key (distance, id) ascending.
+ */
+#ifndef MIANN_H
+#define MIANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MIANN_OK = 0,
+  MIANN_EINVAL = 1,      /* an argument is out of range or inconsistent */
+  MIANN_ENOMEM = 2,      /* device or host allocation failed */
+  MIANN_EDEVICE = 3,     /* a HIP call or an earlier kernel failed */
+  MIANN_ESTATE = 4,      /* the object is not in a state that allows the call */
+  MIANN_EUNSUPPORTED = 5 /* a valid combination that this build does not implement */
+} miann_status;
+
+/* Element types. F32 and U8 are input (original) types; F16 and FP8E4M3
+ * (OCP E4M3 "fn": bias 7, max 448, no infinities) are storage types for the
+ * traversal, with one float scale per vector. */
+typedef enum { MIANN_F32 = 0, MIANN_F16 = 1, MIANN_FP8E4M3 = 2, MIANN_U8 = 3 } miann_dtype;
+
+/* How the first stage of a search is seeded. */
+typedef enum {
+  MIANN_ENTRY_RANDOM = 0,      /* n_init random nodes (Sec. 2.2 Step 2) */
+  MIANN_ENTRY_GHOST_GRAPH = 1, /* beam search on the ghost graph (Sec. 3.2.2) */
+  MIANN_ENTRY_GHOST_DENSE = 2, /* exact top-t over all ghost nodes, MFMA distances */
+  MIANN_ENTRY_SEEDS = 3        /* caller-provided seed ids (e.g. a learned predictor) */
+} miann_entry;
+
+typedef struct miann_index miann_index; /* opaque, library-owned */
+
+/* Counter slots written per query when a counters buffer is given. */
+enum {
+  MIANN_CTR_NDIST = 0,       /* distance evaluations on the main graphs */
+  MIANN_CTR_NEXP = 1,        /* parent expansions */
+  MIANN_CTR_ITERS = 2,       /* search iterations, summed over stages */
+  MIANN_CTR_DGS_SKIPPED = 3, /* neighbour slots skipped by the direction filter */
+  MIANN_CTR_NDIST_GHOST = 4, /* distance evaluations in the ghost stage */
+  MIANN_CTR_NEXP_GHOST = 5,  /* expansions in the ghost stage */
+  MIANN_CTR_NRERANK = 6,     /* FP32 rerank evaluations (low-precision stores) */
+  MIANN_CTR_RESERVED = 7,
+  MIANN_NCTR = 8
+};
+
+/* ------------------------------------------------------------------------ */
+/* Index construction                                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t degree;      /* out-degree of every graph row, 2..64 */
+  int32_t knn_k0;      /* neighbours kept by the exact k-NN before pruning; 0 = 2*degree */
+  int32_t num_shards;  /* S >= 1 resident shards (Sec. 3.1.2); S = 1 keeps the input order */
+  int32_t store_dtype; /* traversal storage: MIANN_F32/F16/FP8E4M3 for float input, MIANN_U8 for u8 */
+  int32_t dgs_table;   /* nonzero: build the direction sign table (Sec. 3.3.2 (a)) */
+  int32_t reserved;
+  uint64_t seed;       /* partition seed */
+} miann_build_params;
+
+/* Builds an index from `n` base vectors of dimension `d` on the device:
+ * random partition into S shards, exact K0-NN per shard by MFMA distance tiles
+ * with fused top-K selection, pruning to `degree` (nearest half of the K0
+ * list, then reverse neighbours, then the rest of the K0 list; each row sorted
+ * by (distance, id)), the direction sign table, the inter-shard map
+ * I(u) = argmin over shard (s+1) mod S of dist(u, w) (Sec. 3.1.2), and the
+ * low-precision store if requested.
+ *   base_dev : device, [n][d] row-major, in_dtype MIANN_F32 or MIANN_U8; read only,
+ *              not retained (the index keeps its own permuted copy).
+ *   Requires n >= S * (degree + 1), n < 2^30, 1 <= d <= 4096.
+ * Synchronises `stream` before returning. *out receives a new index. */
+miann_status miann_build_graph(const void* base_dev, int64_t n, int32_t d, int32_t in_dtype,
+                               const miann_build_params* bp, void* stream, miann_index** out);
+
+/* Builds the ghost shard of every shard (Sec. 3.2.2): samples `num_ghost` nodes
+ * per shard (or round(ratio * n_s) when num_ghost == 0) uniformly without
+ * replacement, copies their vectors, builds their own exact-k-NN graph of
+ * `ghost_degree`, and maps each ghost to the node it copies. Replaces any
+ * earlier ghost shard. Synchronises `stream`. */
+miann_status miann_build_ghost(miann_index* idx, double ratio, int64_t num_ghost, int32_t ghost_degree,
+                               uint64_t seed, void* stream);
+
+/* One shard handed to miann_index_import. All pointers are device pointers,
+ * copied by the call (the caller keeps ownership). */
+typedef struct {
+  int64_t n;                  /* nodes in this shard */
+  const void* vectors;        /* [n][d] originals, in_dtype */
+  const uint32_t* graph;      /* [n][degree] local neighbour ids, 0xFFFFFFFF = no edge */
+  const uint32_t* global_ids; /* [n] local -> global id; NULL = identity */
+  const uint32_t* next_map;   /* [n] I_s(u): local id in shard (s+1) mod S; NULL allowed when S = 1 */
+  int64_t n_ghost;            /* ghost nodes R (0 = none) */
+  const uint32_t* ghost_ids;  /* [R] local ids of the ghost nodes (sorted) */
+  const uint32_t* ghost_graph;/* [R][ghost_degree] ghost-local neighbour ids */
+} miann_shard_desc;
+
+/* Creates an index from caller-built graphs (for example the output of an
+ * external builder). The library quantises the store and builds the sign
+ * table itself. Synchronises `stream`. */
+miann_status miann_index_import(const miann_shard_desc* shards, int32_t num_shards, int32_t d, int32_t in_dtype,
+                                int32_t store_dtype, int32_t degree, int32_t ghost_degree, int32_t dgs_table,
+                                void* stream, miann_index** out);
+
+/* Read-only views of an index's device arrays (owned by the index; valid
+ * until miann_index_free or miann_build_ghost). */
+typedef struct {
+  int64_t n, n_ghost;
+  int32_t d, d_pad;       /* d_pad = stored row length in elements (rows padded with zeros) */
+  int32_t degree, ghost_degree, W; /* W = ceil(d / 32) sign words per edge */
+  int32_t store_dtype, in_dtype;
+  const void* store;      /* [n][d_pad] traversal codes */
+  const float* scale;     /* [n] per-vector scales (F16/FP8) or NULL */
+  const void* originals;  /* [n][d_pad] F32/U8 originals (the store itself when not quantised) */
+  const uint32_t* graph;  /* [n][degree] */
+  const uint32_t* sign;   /* [n][W][degree] (word-major per node) or NULL */
+  const uint32_t* global_ids; /* [n] */
+  const uint32_t* next_map;   /* [n] or NULL */
+  const uint32_t* ghost_ids;  /* [R] local ids */
+  const uint32_t* ghost_graph;/* [R][ghost_degree] */
+} miann_shard_view;
+
+miann_status miann_index_shard(const miann_index* idx, int32_t shard, miann_shard_view* out);
+miann_status miann_index_info(const miann_index* idx, int32_t* num_shards, int64_t* n_total, int32_t* d,
+                              int32_t* degree, int32_t* store_dtype);
+void miann_index_free(miann_index* idx);
+
+/* ------------------------------------------------------------------------ */
+/* Search                                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t search_width;     /* r: parents expanded per iteration (Sec. 2.2 Step 4); r * degree <= 64 */
+  int32_t n_init;           /* random initial candidates (Step 2); 0 = degree; <= 4096 */
+  int32_t entry;            /* miann_entry for the first stage */
+  int32_t ghost_itopk;      /* l_g, priority-queue length in the ghost stage (<= 64) */
+  int32_t ghost_iters;      /* T_g, iterations of the ghost stage */
+  int32_t t_seeds;          /* ghost results handed to the main graph; 0 = min(l_g, itopk); <= 64 */
+  int32_t dgs;              /* direction-guided selection on (Sec. 3.3.2) */
+  int32_t discard_permille; /* rho * 1000: floor(rho * degree) slots skipped per DGS expansion */
+  int32_t cooldown_permille;/* c * 1000: the last ceil(c * T) iterations run without DGS */
+  int32_t random_discard;   /* ablation: skip random slots instead of the direction ranking */
+  int32_t ppe;              /* 1: path extension between shards; 0: independent (naive) shards */
+  int32_t forward_f;        /* results handed to the next shard (<= 16) */
+  int32_t rerank_mult;      /* low-precision stores: FP32 rerank of the first min(m * k, itopk) */
+  int32_t stop_on_no_change;/* also stop when an iteration inserts nothing into p */
+  int32_t hash_log2;        /* visited-hash slots per query = 2^hash_log2 (0 = automatic, 8..13) */
+  int32_t n_seeds;          /* entries per query in seeds_dev (MIANN_ENTRY_SEEDS) */
+  uint64_t seed;            /* random-stream seed */
+  const uint64_t* qkeys;    /* device [nq] query keys (index within a request), NULL = row index */
+  const uint32_t* seeds;    /* device [nq][n_seeds] local ids in each query's start shard */
+  const int32_t* max_iters_per_query; /* device [nq] per-query T, NULL = max_iters */
+} miann_search_params;
+
+/* Fills the documented defaults: r = 1, n_init = degree, random entry,
+ * l_g = 32, T_g = 8, t = min(l_g, itopk), DGS off, rho = 0.5, c = 0.3,
+ * path extension on, f = 1, rerank x4, automatic hash, seed 6. */
+void miann_search_params_default(miann_search_params* sp);
+
+/* Batched beam search (Sec. 2.2; Sec. 3.1.2 for S > 1 shards; Sec. 3.2.2 ghost
+ * entry; Sec. 3.3.2 direction-guided selection).
+ *   queries_dev : device [nq][d], F32 for float indices, U8 for u8 indices.
+ *   k, itopk    : 1 <= k <= itopk <= 512; low-precision stores need itopk >= rerank_mult * k
+ *                 unless rerank_mult * k is capped by itopk.
+ *   max_iters   : T >= 0 iterations per stage.
+ *   ids_dev     : device [nq][k] global ids, 0xFFFFFFFF where fewer than k were found.
+ *   dists_dev   : device [nq][k] float (or int32 for u8), +inf / INT32_MAX padding.
+ *   counters_dev: device [nq][MIANN_NCTR] int64, or NULL.
+ * nq = 0 is a no-op. Enqueues on `stream` and returns. Results depend only on
+ * (index, query, its key, params), not on the batch it is in. */
+miann_status miann_search(const miann_index* idx, const void* queries_dev, int64_t nq, int32_t k, int32_t itopk,
+                          int32_t max_iters, const miann_search_params* sp, uint32_t* ids_dev, void* dists_dev,
+                          int64_t* counters_dev, void* stream);
+
+/* Exact k nearest neighbours of each query over all shards (Sec. 2.1 Eq. 1),
+ * by MFMA distance tiles with fused selection and direct-form rescoring.
+ * Same layouts as miann_search. k <= 256. Enqueues on `stream`. */
+miann_status miann_exact_knn(const miann_index* idx, const void* queries_dev, int64_t nq, int32_t k,
+                             uint32_t* ids_dev, void* dists_dev, void* stream);
+
+/* Thread-local text of the last error (empty string if none). */
+const char* miann_last_error(void);
+
+/* Library version string. */
+const char* miann_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIANN_H */

@@ -641,7 +641,8 @@ static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint6
         uint64_t rk[1024];
         if (cfg->random_discard) {
           uint64_t h1 = orc_splitmix(stream, qkey + 1);
-          for (int j = 0; j < deg; j++) rk[j] = orc_mix64(h1 ^ (((uint64_t)u << 8) | (uint64_t)j));
+          /* random rank key: the top 24 bits of a SplitMix64 output per (query, parent, slot) */
+          for (int j = 0; j < deg; j++) rk[j] = orc_mix64(h1 ^ (((uint64_t)u << 8) | (uint64_t)j)) >> 40;
         } else {
           uint32_t qs[64];
           for (int w = 0; w < g->W; w++) qs[w] = 0;

@@ -1,0 +1,287 @@
+"""miann: MI355X-native graph beam search (PathWeaver, arXiv 2507.17094).
+
+Thin Python binding over the C-ABI of ``libmiann.so`` (``include/miann.h``).
+It only marshals arguments: torch tensors provide device memory and the HIP
+stream, and every step of the search runs in the library's HIP kernels. There
+is no CPU fallback: without the built library on a GPU machine, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmiann.so")
+
+F32, F16, FP8E4M3, U8 = 0, 1, 2, 3
+DTYPE_CODES = {"f32": F32, "f16": F16, "fp8": FP8E4M3, "u8": U8}
+ENTRY_RANDOM, ENTRY_GHOST_GRAPH, ENTRY_GHOST_DENSE, ENTRY_SEEDS = 0, 1, 2, 3
+ENTRY_CODES = {"random": 0, "ghost_graph": 1, "ghost_dense": 2, "seeds": 3}
+NCTR = 8
+NONE_ID = 0xFFFFFFFF
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED"}
+
+EXPORTS = [
+    "miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard", "miann_index_info",
+    "miann_index_free", "miann_search_params_default", "miann_search", "miann_exact_knn", "miann_last_error",
+    "miann_version",
+]
+
+
+class MiannError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("knn_k0", C.c_int32), ("num_shards", C.c_int32),
+                ("store_dtype", C.c_int32), ("dgs_table", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class ShardDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("vectors", C.c_void_p), ("graph", C.c_void_p), ("global_ids", C.c_void_p),
+                ("next_map", C.c_void_p), ("n_ghost", C.c_int64), ("ghost_ids", C.c_void_p),
+                ("ghost_graph", C.c_void_p)]
+
+
+class ShardView(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_ghost", C.c_int64), ("d", C.c_int32), ("d_pad", C.c_int32),
+                ("degree", C.c_int32), ("ghost_degree", C.c_int32), ("W", C.c_int32),
+                ("store_dtype", C.c_int32), ("in_dtype", C.c_int32),
+                ("store", C.c_void_p), ("scale", C.c_void_p), ("originals", C.c_void_p), ("graph", C.c_void_p),
+                ("sign", C.c_void_p), ("global_ids", C.c_void_p), ("next_map", C.c_void_p),
+                ("ghost_ids", C.c_void_p), ("ghost_graph", C.c_void_p)]
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("search_width", C.c_int32), ("n_init", C.c_int32), ("entry", C.c_int32),
+                ("ghost_itopk", C.c_int32), ("ghost_iters", C.c_int32), ("t_seeds", C.c_int32),
+                ("dgs", C.c_int32), ("discard_permille", C.c_int32), ("cooldown_permille", C.c_int32),
+                ("random_discard", C.c_int32), ("ppe", C.c_int32), ("forward_f", C.c_int32),
+                ("rerank_mult", C.c_int32), ("stop_on_no_change", C.c_int32), ("hash_log2", C.c_int32),
+                ("n_seeds", C.c_int32), ("seed", C.c_uint64), ("qkeys", C.c_void_p), ("seeds", C.c_void_p),
+                ("max_iters_per_query", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Loads libmiann.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MiannError(3, f"{LIB_PATH} is missing: build it with paper_2507_17094_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    i32, i64, u64, vp = C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
+    L.miann_build_graph.argtypes = [vp, i64, i32, i32, C.POINTER(BuildParams), vp, C.POINTER(vp)]
+    L.miann_build_ghost.argtypes = [vp, C.c_double, i64, i32, u64, vp]
+    L.miann_index_import.argtypes = [C.POINTER(ShardDesc), i32, i32, i32, i32, i32, i32, i32, vp, C.POINTER(vp)]
+    L.miann_index_shard.argtypes = [vp, i32, C.POINTER(ShardView)]
+    L.miann_index_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.miann_index_free.argtypes = [vp]
+    L.miann_index_free.restype = None
+    L.miann_search_params_default.argtypes = [C.POINTER(SearchParams)]
+    L.miann_search_params_default.restype = None
+    L.miann_search.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
+    L.miann_exact_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    L.miann_last_error.restype = C.c_char_p
+    L.miann_version.restype = C.c_char_p
+    for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
+              "miann_index_info", "miann_search", "miann_exact_knn"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise MiannError(rc, load().miann_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _require_cuda(t, name):
+    if t is not None and not t.is_cuda:
+        raise MiannError(1, f"{name} must be a device tensor")
+
+
+@dataclass
+class SearchOptions:
+    """Python mirror of miann_search_params (see include/miann.h)."""
+    search_width: int = 1
+    n_init: int = 0
+    entry: str = "random"
+    ghost_itopk: int = 32
+    ghost_iters: int = 8
+    t_seeds: int = 0
+    dgs: bool = False
+    discard: float = 0.5
+    cooldown: float = 0.3
+    random_discard: bool = False
+    ppe: bool = True
+    forward_f: int = 1
+    rerank_mult: int = 4
+    stop_on_no_change: bool = False
+    hash_log2: int = 0
+    seed: int = 6
+
+    def cstruct(self, qkeys=None, seeds=None, max_iters_per_query=None) -> SearchParams:
+        p = SearchParams()
+        load().miann_search_params_default(C.byref(p))
+        p.search_width = self.search_width
+        p.n_init = self.n_init
+        p.entry = ENTRY_CODES[self.entry] if isinstance(self.entry, str) else int(self.entry)
+        p.ghost_itopk = self.ghost_itopk
+        p.ghost_iters = self.ghost_iters
+        p.t_seeds = self.t_seeds
+        p.dgs = int(bool(self.dgs))
+        p.discard_permille = int(round(self.discard * 1000))
+        p.cooldown_permille = int(round(self.cooldown * 1000))
+        p.random_discard = int(bool(self.random_discard))
+        p.ppe = int(bool(self.ppe))
+        p.forward_f = self.forward_f
+        p.rerank_mult = self.rerank_mult
+        p.stop_on_no_change = int(bool(self.stop_on_no_change))
+        p.hash_log2 = self.hash_log2
+        p.seed = self.seed & (2**64 - 1)
+        p.qkeys = _ptr(qkeys)
+        if seeds is not None:
+            p.seeds = _ptr(seeds)
+            p.n_seeds = seeds.shape[1]
+        p.max_iters_per_query = _ptr(max_iters_per_query)
+        return p
+
+
+class Index:
+    """An index owned by the native library (freed with the object)."""
+
+    def __init__(self, handle: int, in_dtype: int):
+        self._h = C.c_void_p(handle)
+        self.in_dtype = in_dtype
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.miann_index_free(self._h)
+            self._h = C.c_void_p(0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        S, n, d, deg, st = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().miann_index_info(self._h, C.byref(S), C.byref(n), C.byref(d), C.byref(deg), C.byref(st)))
+        return dict(num_shards=S.value, n=n.value, d=d.value, degree=deg.value, store_dtype=st.value)
+
+    def shard(self, s: int) -> ShardView:
+        v = ShardView()
+        _check(load().miann_index_shard(self._h, s, C.byref(v)))
+        return v
+
+    # -- build ------------------------------------------------------------
+    @staticmethod
+    def build(base, degree: int, num_shards: int = 1, store: str | None = None, dgs_table: bool = True,
+              knn_k0: int = 0, seed: int = 5, stream=None) -> "Index":
+        torch = _torch()
+        _require_cuda(base, "base")
+        base = base.contiguous()
+        in_dt = U8 if base.dtype == torch.uint8 else F32
+        st = DTYPE_CODES[store] if store else in_dt
+        bp = BuildParams(degree, knn_k0, num_shards, st, int(bool(dgs_table)), 0, seed & (2**64 - 1))
+        h = C.c_void_p()
+        _check(load().miann_build_graph(base.data_ptr(), base.shape[0], base.shape[1], in_dt, C.byref(bp),
+                                        _stream_ptr(stream), C.byref(h)))
+        return Index(h.value, in_dt)
+
+    @staticmethod
+    def import_shards(shards: list, d: int, in_dtype: str = "f32", store: str | None = None, degree: int = 32,
+                      ghost_degree: int = 0, dgs_table: bool = True, stream=None) -> "Index":
+        """shards: list of dicts with device tensors vectors, graph, [global_ids, next_map, ghost_ids, ghost_graph]."""
+        arr = (ShardDesc * len(shards))()
+        for i, sh in enumerate(shards):
+            for k_, v in sh.items():
+                if hasattr(v, "is_cuda"):
+                    _require_cuda(v, k_)
+            arr[i].n = sh["vectors"].shape[0]
+            arr[i].vectors = sh["vectors"].data_ptr()
+            arr[i].graph = sh["graph"].data_ptr()
+            arr[i].global_ids = _ptr(sh.get("global_ids"))
+            arr[i].next_map = _ptr(sh.get("next_map"))
+            gi = sh.get("ghost_ids")
+            arr[i].n_ghost = 0 if gi is None else gi.shape[0]
+            arr[i].ghost_ids = _ptr(gi)
+            arr[i].ghost_graph = _ptr(sh.get("ghost_graph"))
+        in_dt = DTYPE_CODES[in_dtype]
+        st = DTYPE_CODES[store] if store else in_dt
+        h = C.c_void_p()
+        _check(load().miann_index_import(arr, len(shards), d, in_dt, st, degree, ghost_degree, int(bool(dgs_table)),
+                                         _stream_ptr(stream), C.byref(h)))
+        return Index(h.value, in_dt)
+
+    def build_ghost(self, ratio: float = 0.0, num_ghost: int = 0, ghost_degree: int = 32, seed: int = 5,
+                    stream=None) -> None:
+        _check(load().miann_build_ghost(self._h, float(ratio), int(num_ghost), ghost_degree, seed & (2**64 - 1),
+                                        _stream_ptr(stream)))
+
+    # -- search -----------------------------------------------------------
+    def search(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None,
+               qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None):
+        """Returns (ids [nq,k] int32 view of uint32, dists [nq,k] float32|int32[, counters [nq,8] int64])."""
+        torch = _torch()
+        for n_, t_ in (("queries", queries), ("qkeys", qkeys), ("seeds", seeds), ("max_iters_per_query", max_iters_per_query)):
+            _require_cuda(t_, n_)
+        nq = queries.shape[0]
+        opts = opts or SearchOptions()
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+            dists = torch.empty((nq, k), dtype=torch.int32 if self.in_dtype == U8 else torch.float32,
+                                device=queries.device)
+        else:
+            ids, dists = out
+        ctr = torch.empty((nq, NCTR), dtype=torch.int64, device=queries.device) if counters else None
+        p = opts.cstruct(qkeys, seeds, max_iters_per_query)
+        _check(load().miann_search(self._h, queries.data_ptr(), nq, k, itopk, max_iters, C.byref(p), ids.data_ptr(),
+                                   dists.data_ptr(), _ptr(ctr), _stream_ptr(stream)))
+        return (ids, dists, ctr) if counters else (ids, dists)
+
+    def exact_knn(self, queries, k: int, stream=None):
+        torch = _torch()
+        _require_cuda(queries, "queries")
+        nq = queries.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        dists = torch.empty((nq, k), dtype=torch.int32 if self.in_dtype == U8 else torch.float32, device=queries.device)
+        _check(load().miann_exact_knn(self._h, queries.data_ptr(), nq, k, ids.data_ptr(), dists.data_ptr(),
+                                      _stream_ptr(stream)))
+        return ids, dists
+
+
+def as_u32(t):
+    """int32 tensor holding uint32 ids -> numpy uint32."""
+    return t.cpu().numpy().view("uint32")
+
+
+def version() -> str:
+    return load().miann_version().decode()

@@ -1,0 +1,194 @@
+// Device-side building blocks shared by the miann kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace miann {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kIdMask = 0x3FFFFFFFu;  // ids fit in 30 bits; 2 bits hold the entry flag
+constexpr uint64_t kDummy = ~0ull;         // sorts after every real key
+
+// Entry flags of the priority queue p.
+constexpr uint32_t kFresh = 0;    // not expanded yet
+constexpr uint32_t kPartial = 1;  // expanded with some neighbour slots skipped (direction filter)
+constexpr uint32_t kDone = 2;     // fully expanded
+
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_FP8 = 2, DT_U8 = 3 };
+
+// Keys order entries by (distance, id). Distances are non-negative, so the
+// IEEE bit pattern of a float (or the value of a non-negative int32) orders
+// like the number. Layout: dist bits << 32 | id << 2 | flag.
+__device__ __forceinline__ uint64_t make_key(uint32_t dist_bits, uint32_t id, uint32_t flag) {
+  return ((uint64_t)dist_bits << 32) | ((uint64_t)((id & kIdMask) << 2)) | flag;
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return ((uint32_t)k) >> 2; }
+__device__ __forceinline__ uint32_t key_flag(uint64_t k) { return ((uint32_t)k) & 3u; }
+__device__ __forceinline__ uint32_t key_dist(uint64_t k) { return (uint32_t)(k >> 32); }
+__device__ __forceinline__ uint64_t key_noflag(uint64_t k) { return k >> 2; }
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) as a counter-based generator:
+// output(ctr) = mix(seed + ctr * 0x9E3779B97F4A7C15).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t sm_at(uint64_t seed, uint64_t ctr) {
+  return sm_mix(seed + ctr * 0x9E3779B97F4A7C15ull);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders this wave's LDS accesses: the LDS executes one wave's operations in
+// issue order, so only compiler reordering must be prevented.
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src, 64); }
+__device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m, 64); }
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = shfl_u32((uint32_t)v, src), hi = shfl_u32((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
+  return __longlong_as_double((long long)shfl_xor_u64((uint64_t)__double_as_longlong(v), m));
+}
+__device__ __forceinline__ int shfl_xor_i32(int v, int m) { return __shfl_xor(v, m, 64); }
+
+// Number of set lanes of `mask` below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Bitonic sort of one u64 key per lane, ascending in segments of SEG lanes
+// (SEG a power of two, 2..64).
+template <int SEG>
+__device__ __forceinline__ uint64_t bitonic_sort_u64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= SEG; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      uint64_t other = shfl_xor_u64(key, j);
+      bool up = (k == SEG) || ((lane & k) == 0);
+      bool lower = (lane & j) == 0;
+      uint64_t mn = other < key ? other : key;
+      uint64_t mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+template <int SEG>
+__device__ __forceinline__ uint32_t bitonic_sort_u32(uint32_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= SEG; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      uint32_t other = shfl_xor_u32(key, j);
+      bool up = (k == SEG) || ((lane & k) == 0);
+      bool lower = (lane & j) == 0;
+      uint32_t mn = other < key ? other : key;
+      uint32_t mx = other < key ? key : other;
+      key = (lower == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// Runtime-segment dispatch (seg in {2,4,...,64}).
+__device__ __forceinline__ uint32_t bitonic_sort_u32_seg(uint32_t key, int seg) {
+  switch (seg) {
+    case 2: return bitonic_sort_u32<2>(key);
+    case 4: return bitonic_sort_u32<4>(key);
+    case 8: return bitonic_sort_u32<8>(key);
+    case 16: return bitonic_sort_u32<16>(key);
+    case 32: return bitonic_sort_u32<32>(key);
+    default: return bitonic_sort_u32<64>(key);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float f16_bits_to_f32(uint32_t h) {
+  _Float16 v = __builtin_bit_cast(_Float16, (uint16_t)h);
+  return (float)v;
+}
+
+// OCP FP8 E4M3 ("fn") -> float. gfx950's conversion instruction implements the
+// OCP encoding; the search's distance parity with the CPU oracle checks it.
+__device__ __forceinline__ void fp8x4_to_f32(uint32_t w, float* out) {
+  auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  out[0] = lo[0];
+  out[1] = lo[1];
+  out[2] = hi[0];
+  out[3] = hi[1];
+}
+
+template <int DT>
+struct Fmt;
+template <>
+struct Fmt<DT_F32> { static constexpr int esize = 4; static constexpr int per16 = 4; };
+template <>
+struct Fmt<DT_F16> { static constexpr int esize = 2; static constexpr int per16 = 8; };
+template <>
+struct Fmt<DT_FP8> { static constexpr int esize = 1; static constexpr int per16 = 16; };
+template <>
+struct Fmt<DT_U8> { static constexpr int esize = 1; static constexpr int per16 = 16; };
+
+// Decode one 16-byte chunk into floats (traversal values before the scale).
+template <int DT>
+__device__ __forceinline__ void decode16(const uint4& c, float* out) {
+  if constexpr (DT == DT_F32) {
+    out[0] = __uint_as_float(c.x); out[1] = __uint_as_float(c.y);
+    out[2] = __uint_as_float(c.z); out[3] = __uint_as_float(c.w);
+  } else if constexpr (DT == DT_F16) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      out[2 * i] = f16_bits_to_f32(w[i] & 0xFFFFu);
+      out[2 * i + 1] = f16_bits_to_f32(w[i] >> 16);
+    }
+  } else if constexpr (DT == DT_FP8) {
+    fp8x4_to_f32(c.x, out); fp8x4_to_f32(c.y, out + 4);
+    fp8x4_to_f32(c.z, out + 8); fp8x4_to_f32(c.w, out + 12);
+  } else {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 16; i++) out[i] = (float)((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+  }
+}
+
+// Element i of a stored row (used for scalar, per-element access).
+template <int DT>
+__device__ __forceinline__ float load_elem(const void* row, int i) {
+  if constexpr (DT == DT_F32) return ((const float*)row)[i];
+  else if constexpr (DT == DT_F16) return f16_bits_to_f32(((const uint16_t*)row)[i]);
+  else if constexpr (DT == DT_FP8) {
+    uint32_t b = ((const uint8_t*)row)[i];
+    float o[4];
+    fp8x4_to_f32(b, o);
+    return o[0];
+  } else return (float)((const uint8_t*)row)[i];
+}
+
+}  // namespace miann

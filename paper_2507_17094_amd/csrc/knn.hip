@@ -1,0 +1,715 @@
+// Dense distance tiles on the MFMA units with fused top-K selection.
+//
+// Work that really is a dense contraction -- queries x ghost nodes for the
+// dense ghost entry, the exact k-NN of a shard against itself during graph
+// construction, the inter-shard 1-NN map I(u) (Sec. 3.1.2), and exact ground
+// truth (Sec. 2.1 Eq. 1) -- runs here. A 256-thread workgroup owns 64 query
+// rows; each step computes a 64 x 64 tile of |q|^2 + |x|^2 - 2 q.x with
+// v_mfma_f32_32x32x2_f32 (one 32 x 32 block per wave), and each wave then
+// filters 16 rows of the tile against that row's current K'-th best key and
+// merges survivors into the row's sorted list in LDS. The selected K' = K + 16
+// candidates are rescored in direct form (double accumulation, exactly like the
+// search kernel), sorted by (dist, id) and cut to K, so the result is the exact
+// top-K unless the GEMM-form error exceeds the distance gap across 16 ranks.
+#include <hipcub/hipcub.hpp>
+
+#include "common.hpp"
+#include "knn.hpp"
+
+namespace miann {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int TQ = 64;   // query rows per workgroup
+constexpr int TX = 64;   // base rows per step
+constexpr int KC = 32;   // k-chunk (floats) staged in LDS
+constexpr int BSTR = KC + 1;
+constexpr int DSTR = TX + 1;
+
+__global__ void fill_cnt_kernel(int* c) { *c = 0; }
+
+__global__ void pad_u8_kernel(const uint8_t* __restrict__ q, int64_t nq, int d, int dp, uint8_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nq * dp) return;
+  const int64_t r = i / dp;
+  const int c = (int)(i % dp);
+  out[i] = c < d ? q[r * d + c] : 0;
+}
+
+// Merge sorted candidate keys (one per lane, kDummy = none; keys unique) into
+// the sorted list L[0..n). ck: 64-entry scratch.
+__device__ void merge_list(uint64_t* L, int n, uint64_t c, uint64_t* ck) {
+  const int lane = lane_id();
+  const bool real = c != kDummy;
+  int pos = 0;
+  if (real) {
+    int step = 1;
+    while (step * 2 <= n) step <<= 1;
+    for (; step > 0; step >>= 1)
+      if (pos + step <= n && L[pos + step - 1] < c) pos += step;
+  } else {
+    pos = n;
+  }
+  const uint64_t vm = __ballot(real && pos < n);
+  if (vm == 0) return;
+  const int nv = __popcll(vm);
+  const int rank = lanes_below(vm);
+  if (real && pos < n) ck[rank] = c;
+  wsync();
+  uint64_t pv[4];
+  int np[4];
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    const int i = lane + 64 * m;
+    np[m] = -1;
+    pv[m] = kDummy;
+    if (i < n) {
+      pv[m] = L[i];
+      int p = 0;
+      int step = 1;
+      while (step * 2 <= nv) step <<= 1;
+      for (; step > 0; step >>= 1)
+        if (p + step <= nv && ck[p + step - 1] < pv[m]) p += step;
+      np[m] = i + p;
+    }
+  }
+  wsync();
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    const int i = lane + 64 * m;
+    if (np[m] >= 0 && np[m] < n && np[m] != i) L[np[m]] = pv[m];
+  }
+  if (real && pos < n && pos + rank < n) L[pos + rank] = c;
+  wsync();
+}
+
+template <typename TIN>
+__global__ __launch_bounds__(256) void tile_select_kernel(const TIN* __restrict__ A, const float* __restrict__ an,
+                                                          int64_t na, const int* __restrict__ na_dev,
+                                                          const uint32_t* __restrict__ qlist,
+                                                          const TIN* __restrict__ B, const float* __restrict__ bn,
+                                                          int64_t nb, int dpf, int kp, int exclude_self,
+                                                          uint64_t* __restrict__ out) {
+  extern __shared__ __align__(16) char smem[];
+  const int ASTR = dpf + 1;
+  float* As = (float*)smem;
+  float* Bs = As + TQ * ASTR;
+  float* Dt = Bs + TX * BSTR;
+  uint64_t* lists = (uint64_t*)(((uintptr_t)(Dt + TQ * DSTR) + 15) & ~(uintptr_t)15);
+  uint64_t* thr = lists + (size_t)TQ * kp;
+  uint64_t* cks = thr + TQ;
+  float* anl = (float*)(cks + 4 * 64);
+  int64_t* qrow = (int64_t*)(((uintptr_t)(anl + TQ) + 7) & ~(uintptr_t)7);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_rows = na_dev ? (int64_t)*na_dev : na;
+  const int64_t r0 = (int64_t)blockIdx.x * TQ;
+  if (r0 >= n_rows) return;
+
+  for (int r = tid; r < TQ; r += 256) {
+    const int64_t gr = r0 + r;
+    qrow[r] = gr < n_rows ? (qlist ? (int64_t)qlist[gr] : gr) : -1;
+  }
+  __syncthreads();
+  for (int e = tid; e < TQ * dpf; e += 256) {
+    const int r = e / dpf, c = e % dpf;
+    const int64_t q = qrow[r];
+    As[r * ASTR + c] = q >= 0 ? (float)A[q * dpf + c] : 0.f;
+  }
+  for (int r = tid; r < TQ; r += 256) anl[r] = qrow[r] >= 0 ? an[qrow[r]] : 0.f;
+  for (int e = tid; e < TQ * kp; e += 256) lists[e] = kDummy;
+  for (int r = tid; r < TQ; r += 256) thr[r] = kDummy;
+  __syncthreads();
+
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 31, lk = lane >> 5;
+  uint64_t* ck = cks + wave * 64;
+
+  for (int64_t j0 = 0; j0 < nb; j0 += TX) {
+    floatx16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.f;
+    for (int kc = 0; kc < dpf; kc += KC) {
+      __syncthreads();
+      for (int e = tid; e < TX * KC; e += 256) {
+        const int r = e / KC, c = e % KC;
+        const int64_t gb = j0 + r;
+        Bs[r * BSTR + c] = gb < nb ? (float)B[gb * dpf + kc + c] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < KC; kk += 2) {
+        const float av = As[(wr + li) * ASTR + kc + kk + lk];
+        const float bv = Bs[(wc + li) * BSTR + kk + lk];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const int row = wr + 8 * (j >> 2) + 4 * lk + (j & 3);
+      const int col = wc + li;
+      const int64_t gb = j0 + col;
+      float dv = INFINITY;
+      if (gb < nb && qrow[row] >= 0 && !(exclude_self && qrow[row] == gb)) {
+        dv = anl[row] + bn[gb] - 2.f * acc[j];
+        dv = dv < 0.f ? 0.f : dv;
+      }
+      Dt[row * DSTR + col] = dv;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < TQ / 4; rr++) {
+      const int row = wave * (TQ / 4) + rr;
+      if (qrow[row] < 0) continue;
+      const float dv = Dt[row * DSTR + lane];
+      const uint64_t key = dv < INFINITY ? (((uint64_t)__float_as_uint(dv) << 32) | (uint64_t)(j0 + lane)) : kDummy;
+      const bool pass = key < thr[row];
+      if (__ballot(pass) == 0) continue;
+      uint64_t c = pass ? key : kDummy;
+      c = bitonic_sort_u64<64>(c);
+      merge_list(lists + (size_t)row * kp, kp, c, ck);
+      if (lane == 0) thr[row] = lists[(size_t)row * kp + kp - 1];
+      wsync();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < TQ * kp; e += 256) {
+    const int r = e / kp;
+    const int64_t gr = r0 + r;
+    if (gr < n_rows) out[gr * kp + (e % kp)] = lists[e];
+  }
+}
+
+// Row norms |x|^2 in f32 (GEMM-form selection only).
+template <typename TIN>
+__global__ void norms_kernel(const TIN* __restrict__ X, int64_t n, int dpf, float* __restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < dpf; i += 64) {
+    const double x = (double)X[v * dpf + i];
+    s += x * x;
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += shfl_xor_f64(s, o);
+  if (lane == 0) out[v] = (float)s;
+}
+
+// Direct-form rescoring of K' candidates per row, sort, keep k.
+// Base rows in representation DT ([nb][bpad] codes (+scale)); query rows are
+// f32 ([.][bpad]) for float bases or u8 ([.][bpad]) for u8 bases.
+template <int DT>
+__global__ __launch_bounds__(256) void rescore_kernel(const uint64_t* __restrict__ cand, int64_t nrows,
+                                                      const int* __restrict__ nrows_dev, int kp,
+                                                      const uint32_t* __restrict__ qlist, const void* __restrict__ Q,
+                                                      const void* __restrict__ Bv, const float* __restrict__ bscale,
+                                                      int bpad, int k, uint64_t* __restrict__ out) {
+  extern __shared__ __align__(16) char smem[];
+  constexpr int P16 = Fmt<DT>::per16;
+  constexpr int ESZ = Fmt<DT>::esize;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, team = lane >> 3, tl = lane & 7;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows;
+  if (r >= n_rows) return;
+  int np2 = 1;
+  while (np2 < kp) np2 <<= 1;
+  uint64_t* buf = (uint64_t*)smem + (size_t)wave * np2;
+  const int64_t qi = qlist ? (int64_t)qlist[r] : r;
+  const int row16 = bpad * ESZ / 16;
+  for (int c0 = 0; c0 < kp; c0 += 8) {
+    const int ci = c0 + team;
+    const uint64_t key = ci < kp ? cand[r * kp + ci] : kDummy;
+    const bool ok = key != kDummy;
+    const uint32_t id = ok ? (uint32_t)key : 0u;
+    const uint4* brow = (const uint4*)((const char*)Bv + (size_t)id * bpad * ESZ);
+    uint32_t dbits = 0;
+    if constexpr (DT == DT_U8) {
+      const uint4* qrow = (const uint4*)((const uint8_t*)Q + (size_t)qi * bpad);
+      int acc = 0;
+      if (ok)
+        for (int c = tl; c < row16; c += 8) {
+          const uint4 xb = brow[c], qb = qrow[c];
+          const uint32_t xw[4] = {xb.x, xb.y, xb.z, xb.w}, qw[4] = {qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+          for (int e = 0; e < 16; e++) {
+            const int t = (int)((qw[e >> 2] >> (8 * (e & 3))) & 0xFF) - (int)((xw[e >> 2] >> (8 * (e & 3))) & 0xFF);
+            acc += t * t;
+          }
+        }
+      acc += shfl_xor_i32(acc, 1);
+      acc += shfl_xor_i32(acc, 2);
+      acc += shfl_xor_i32(acc, 4);
+      dbits = (uint32_t)acc;
+    } else {
+      const float* qrow = (const float*)Q + (size_t)qi * bpad;
+      const float s = (DT == DT_F16 || DT == DT_FP8) ? (ok ? bscale[id] : 0.f) : 1.f;
+      double acc = 0.0;
+      if (ok)
+        for (int c = tl; c < row16; c += 8) {
+          float x[P16];
+          decode16<DT>(brow[c], x);
+#pragma unroll
+          for (int e = 0; e < P16; e++) {
+            const float xe = (DT == DT_F16 || DT == DT_FP8) ? s * x[e] : x[e];
+            const double t = (double)qrow[c * P16 + e] - (double)xe;
+            acc = __builtin_fma(t, t, acc);
+          }
+        }
+      acc += shfl_xor_f64(acc, 1);
+      acc += shfl_xor_f64(acc, 2);
+      acc += shfl_xor_f64(acc, 4);
+      dbits = __float_as_uint((float)acc);
+    }
+    if (tl == 0 && ci < kp) buf[ci] = ok ? (((uint64_t)dbits << 32) | id) : kDummy;
+  }
+  for (int i = kp + lane; i < np2; i += 64) buf[i] = kDummy;
+  wsync();
+  for (int kk = 2; kk <= np2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < np2; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = buf[i], y = buf[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { buf[i] = y; buf[ixj] = x; }
+        }
+      }
+      wsync();
+    }
+  for (int i = lane; i < k; i += 64) out[qi * k + i] = i < kp ? buf[i] : kDummy;
+}
+
+// f32 copy of (f32 | u8) query rows, padded.
+__global__ void queries_f32_kernel(const void* __restrict__ q, int q_dt, int64_t nq, int d, int dpf,
+                                   float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nq * dpf) return;
+  const int64_t r = i / dpf;
+  const int c = (int)(i % dpf);
+  float v = 0.f;
+  if (c < d) v = q_dt == DT_U8 ? (float)((const uint8_t*)q)[r * d + c] : ((const float*)q)[r * d + c];
+  out[i] = v;
+}
+
+hipError_t queries_to_f32(const void* q, int q_dt, int64_t nq, int d, int dpf, float* out, hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  const int64_t tot = nq * dpf;
+  hipLaunchKernelGGL(queries_f32_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, q, q_dt, nq, d, dpf,
+                     out);
+  return hipGetLastError();
+}
+
+__global__ void dequant_kernel(const void* __restrict__ store, const float* __restrict__ scale, int dt, int64_t n,
+                               int d_pad, int dpf, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * dpf) return;
+  const int64_t r = i / dpf;
+  const int c = (int)(i % dpf);
+  float v = 0.f;
+  if (c < d_pad) {
+    const void* row = (const char*)store + (size_t)r * d_pad * (dt == DT_F32 ? 4 : dt == DT_F16 ? 2 : 1);
+    switch (dt) {
+      case DT_F32: v = load_elem<DT_F32>(row, c); break;
+      case DT_F16: v = scale[r] * load_elem<DT_F16>(row, c); break;
+      case DT_FP8: v = scale[r] * load_elem<DT_FP8>(row, c); break;
+      default: v = load_elem<DT_U8>(row, c); break;
+    }
+  }
+  out[i] = v;
+}
+
+hipError_t dequant_rows(const void* store, const float* scale, int dt, int64_t n, int d_pad, int dpf, float* out,
+                        hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t tot = n * dpf;
+  hipLaunchKernelGGL(dequant_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, store, scale, dt, n, d_pad,
+                     dpf, out);
+  return hipGetLastError();
+}
+
+static size_t tile_lds(int dpf, int kp) {
+  size_t b = (size_t)TQ * (dpf + 1) * 4 + (size_t)TX * BSTR * 4 + (size_t)TQ * DSTR * 4 + 16;
+  b += (size_t)TQ * kp * 8 + TQ * 8 + 4 * 64 * 8 + TQ * 4 + 8 + TQ * 8;
+  return b;
+}
+
+template <typename TIN>
+static hipError_t launch_tiles(const TIN* A, const float* an, int64_t na, const int* na_dev, const uint32_t* qlist,
+                               const TIN* B, const float* bn, int64_t nb, int dpf, int kp, int exclude_self,
+                               uint64_t* out, hipStream_t st) {
+  const size_t lds = tile_lds(dpf, kp);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static bool set = false;
+  if (!set) {
+    hipFuncSetAttribute((const void*)tile_select_kernel<TIN>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    set = true;
+  }
+  hipLaunchKernelGGL(tile_select_kernel<TIN>, dim3((unsigned)((na + TQ - 1) / TQ)), dim3(256), lds, st, A, an, na,
+                     na_dev, qlist, B, bn, nb, dpf, kp, exclude_self, out);
+  return hipGetLastError();
+}
+
+static hipError_t launch_rescore(int dt, const uint64_t* cand, int64_t nrows, const int* nrows_dev, int kp,
+                                 const uint32_t* qlist, const void* Q, const void* Bv, const float* bscale, int bpad,
+                                 int k, uint64_t* out, hipStream_t st) {
+  int np2 = 1;
+  while (np2 < kp) np2 <<= 1;
+  const size_t lds = (size_t)4 * np2 * 8;
+  dim3 g((unsigned)((nrows + 3) / 4)), b(256);
+  switch (dt) {
+    case DT_F32:
+      hipLaunchKernelGGL(rescore_kernel<DT_F32>, g, b, lds, st, cand, nrows, nrows_dev, kp, qlist, Q, Bv, bscale, bpad, k, out);
+      break;
+    case DT_F16:
+      hipLaunchKernelGGL(rescore_kernel<DT_F16>, g, b, lds, st, cand, nrows, nrows_dev, kp, qlist, Q, Bv, bscale, bpad, k, out);
+      break;
+    case DT_FP8:
+      hipLaunchKernelGGL(rescore_kernel<DT_FP8>, g, b, lds, st, cand, nrows, nrows_dev, kp, qlist, Q, Bv, bscale, bpad, k, out);
+      break;
+    default:
+      hipLaunchKernelGGL(rescore_kernel<DT_U8>, g, b, lds, st, cand, nrows, nrows_dev, kp, qlist, Q, Bv, bscale, bpad, k, out);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t nb, int dpf, int d, int raw_dt,
+                     const void* A_raw, int a_raw_pad, const void* B_raw, const float* B_scale, int b_raw_pad, int k,
+                     int exclude_self, const uint32_t* qlist, uint64_t* out, hipStream_t st) {
+  (void)d;
+  (void)a_raw_pad;
+  if (na == 0) return hipSuccess;
+  int kp = k + 16;
+  if (kp > nb - (exclude_self ? 1 : 0)) kp = (int)nb - (exclude_self ? 1 : 0);
+  if (kp < k) kp = k;
+  float *an = nullptr, *bn = nullptr;
+  uint64_t* cand = nullptr;
+  hipError_t e = hipMallocAsync(&an, (size_t)na * 4, st);
+  if (e == hipSuccess) e = hipMallocAsync(&bn, (size_t)nb * 4, st);
+  if (e == hipSuccess) e = hipMallocAsync(&cand, (size_t)na * kp * 8, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((na + 3) / 4)), dim3(256), 0, st, A_f32, na, dpf, an);
+    hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, B_f32, nb, dpf, bn);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = launch_tiles<float>(A_f32, an, na, nullptr, nullptr, B_f32, bn, nb, dpf, kp, exclude_self, cand, st);
+  // rows of `cand` are indexed by position; rescoring reads query row qlist[r] (or r)
+  if (e == hipSuccess) e = launch_rescore(raw_dt, cand, na, nullptr, kp, qlist, A_raw, B_raw, B_scale, b_raw_pad, k, out, st);
+  if (an) hipFreeAsync(an, st);
+  if (bn) hipFreeAsync(bn, st);
+  if (cand) hipFreeAsync(cand, st);
+  return e;
+}
+
+__global__ void shard_qlist_kernel(int64_t nq, const uint64_t* __restrict__ qkeys, int S, int shard, int all,
+                                   uint32_t* __restrict__ list, int* __restrict__ count) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  const uint64_t key = qkeys ? qkeys[q] : (uint64_t)q;
+  if (all || (int)(key % (uint64_t)S) == shard) list[atomicAdd(count, 1)] = (uint32_t)q;
+}
+
+__global__ void dense_out_kernel(const uint64_t* __restrict__ best, const uint32_t* __restrict__ list,
+                                 const int* __restrict__ count, int t, const uint32_t* __restrict__ g_map, int S,
+                                 int shard, uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = i / t;
+  const int j = (int)(i % t);
+  if (r >= *count) return;
+  const uint32_t q = list[r];
+  const uint64_t key = best[(size_t)q * t + j];
+  out[((size_t)q * S + shard) * t + j] = key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | g_map[(uint32_t)key]);
+}
+
+hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, const uint64_t* qkeys, int S, int shard,
+                       int ppe, const float* g_f32, const void* g_store, const float* g_scale, const uint32_t* g_map,
+                       int64_t R, int d_pad, int d_pad_f32, int t, uint64_t* out, hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  const int qdt = store_dt == DT_U8 ? DT_U8 : DT_F32;
+  int kp = t + 16;
+  if (kp > R) kp = (int)R;
+  if (kp < t) kp = t;
+  char* buf = nullptr;
+  const size_t sz_list = ((size_t)nq * 4 + 255) & ~(size_t)255;
+  const size_t sz_cnt = 256;
+  const size_t sz_qf = ((size_t)nq * d_pad_f32 * 4 + 255) & ~(size_t)255;
+  const size_t sz_qraw = ((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4) + 255) & ~(size_t)255;
+  const size_t sz_qn = ((size_t)nq * 4 + 255) & ~(size_t)255;
+  const size_t sz_gn = ((size_t)R * 4 + 255) & ~(size_t)255;
+  const size_t sz_cand = ((size_t)nq * kp * 8 + 255) & ~(size_t)255;
+  const size_t sz_best = (size_t)nq * t * 8;
+  const size_t total = sz_list + sz_cnt + sz_qf + sz_qraw + sz_qn + sz_gn + sz_cand + sz_best;
+  hipError_t e = hipMallocAsync((void**)&buf, total, st);
+  if (e != hipSuccess) return e;
+  char* p = buf;
+  uint32_t* list = (uint32_t*)p; p += sz_list;
+  int* cnt = (int*)p; p += sz_cnt;
+  float* qf = (float*)p; p += sz_qf;
+  void* qraw = p; p += sz_qraw;
+  float* qn = (float*)p; p += sz_qn;
+  float* gn = (float*)p; p += sz_gn;
+  uint64_t* cand = (uint64_t*)p; p += sz_cand;
+  uint64_t* best = (uint64_t*)p;
+  hipLaunchKernelGGL(fill_cnt_kernel, dim3(1), dim3(1), 0, st, cnt);
+  hipLaunchKernelGGL(shard_qlist_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, qkeys, S, shard,
+                     ppe ? 0 : 1, list, cnt);
+  e = queries_to_f32(queries, qdt, nq, d, d_pad_f32, qf, st);
+  if (e == hipSuccess) {
+    if (qdt == DT_U8) {
+      hipLaunchKernelGGL(pad_u8_kernel, dim3((unsigned)((nq * d_pad + 255) / 256)), dim3(256), 0, st,
+                         (const uint8_t*)queries, nq, d, d_pad, (uint8_t*)qraw);
+    } else {
+      e = queries_to_f32(queries, DT_F32, nq, d, d_pad, (float*)qraw, st);
+    }
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qf, nq, d_pad_f32, qn);
+    hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, g_f32, R, d_pad_f32, gn);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = launch_tiles<float>(qf, qn, nq, cnt, list, g_f32, gn, R, d_pad_f32, kp, 0, cand, st);
+  if (e == hipSuccess)
+    e = launch_rescore(store_dt, cand, nq, cnt, kp, list, qraw, g_store, g_scale, d_pad, t, best, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(dense_out_kernel, dim3((unsigned)((nq * t + 255) / 256)), dim3(256), 0, st, best, list, cnt, t,
+                       g_map, S, shard, out);
+    e = hipGetLastError();
+  }
+  hipFreeAsync(buf, st);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Graph pruning: nearest ceil(deg/2) of the K0 list, then reverse neighbours
+// (nearest first), then the rest of the K0 list; duplicates skipped; the row
+// is finally sorted by (dist, id).
+// ---------------------------------------------------------------------------
+__global__ void rev_count_kernel(const uint64_t* __restrict__ knn, int64_t n, int K0, int h, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * h) return;
+  const int64_t v = i / h;
+  const int j = (int)(i % h);
+  atomicAdd(&cnt[(uint32_t)knn[v * K0 + j]], 1);
+}
+
+__global__ void rev_fill_kernel(const uint64_t* __restrict__ knn, int64_t n, int K0, int h,
+                                const int64_t* __restrict__ off, int* __restrict__ fill, uint64_t* __restrict__ rev) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * h) return;
+  const int64_t v = i / h;
+  const int j = (int)(i % h);
+  const uint64_t key = knn[v * K0 + j];
+  const uint32_t u = (uint32_t)key;
+  const int pos = atomicAdd(&fill[u], 1);
+  rev[off[u] + pos] = (key & 0xFFFFFFFF00000000ull) | (uint32_t)v;
+}
+
+__global__ __launch_bounds__(256) void prune_kernel(const uint64_t* __restrict__ knn, int64_t n, int K0, int deg,
+                                                    int h, const int64_t* __restrict__ off,
+                                                    const uint64_t* __restrict__ rev, uint32_t* __restrict__ graph) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + wave;
+  if (u >= n) return;
+  const int LMAX = 64 + 64 + 256;
+  uint64_t* seq = (uint64_t*)smem + (size_t)wave * (LMAX + 64);
+  // smallest 64 reverse keys, sorted
+  uint64_t best = kDummy;
+  const int64_t b0 = off[u], b1 = off[u + 1];
+  for (int64_t c0 = b0; c0 < b1; c0 += 64) {
+    uint64_t x = c0 + lane < b1 ? rev[c0 + lane] : kDummy;
+    x = bitonic_sort_u64<64>(x);
+    // merge two sorted 64-lists, keep the lower 64: pair best[i] with x[63 - i]
+    const uint64_t xr = shfl_u64(x, 63 - lane);
+    best = xr < best ? xr : best;
+    best = bitonic_sort_u64<64>(best);
+  }
+  int L = 0;
+  for (int j = lane; j < h; j += 64) seq[j] = knn[u * K0 + j];
+  L = h;
+  const int nrev = (int)((b1 - b0) < 64 ? (b1 - b0) : 64);
+  if (lane < nrev) seq[L + lane] = best;
+  L += nrev;
+  for (int j = lane; j < K0 - h; j += 64) seq[L + j] = knn[u * K0 + h + j];
+  L += K0 - h;
+  wsync();
+  // first occurrence of each id, in priority order; keep the first deg
+  uint64_t* rowbuf = seq + LMAX;
+  int taken = 0;
+  for (int c0 = 0; c0 < L && taken < deg; c0 += 64) {
+    const int i = c0 + lane;
+    bool ok = false;
+    uint64_t key = kDummy;
+    if (i < L) {
+      key = seq[i];
+      ok = key != kDummy;
+      const uint32_t id = (uint32_t)key;
+      for (int j = 0; j < i && ok; j++)
+        if ((uint32_t)seq[j] == id) ok = false;
+    }
+    const uint64_t m = __ballot(ok);
+    const int pos = taken + lanes_below(m);
+    if (ok && pos < deg) rowbuf[pos] = key;
+    taken += __popcll(m);
+  }
+  wsync();
+  uint64_t rowkey = lane < deg && lane < taken ? rowbuf[lane] : kDummy;
+  rowkey = lane < deg ? rowkey : kDummy;
+  rowkey = bitonic_sort_u64<64>(rowkey);
+  if (lane < deg) graph[u * deg + lane] = rowkey == kDummy ? kNone : (uint32_t)rowkey;
+}
+
+__global__ void zero_i32_kernel(int* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void widen_kernel(const int* __restrict__ c, int64_t n, int64_t* __restrict__ o) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) o[i] = c[i];
+}
+
+hipError_t prune_graph(const uint64_t* knn, int64_t n, int K0, int deg, uint32_t* graph, hipStream_t st) {
+  const int h = (deg + 1) / 2;
+  int* cnt = nullptr;
+  int* fill = nullptr;
+  int64_t* off = nullptr;
+  uint64_t* rev = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  const int64_t nh = n * h;
+  hipError_t e = hipMallocAsync((void**)&cnt, (size_t)(n + 1) * 4, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&fill, (size_t)(n + 1) * 4, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&off, (size_t)(n + 1) * 8, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&rev, (size_t)(nh ? nh : 1) * 8, st);
+  if (e != hipSuccess) return e;
+  const unsigned gn = (unsigned)((n + 1 + 255) / 256);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(gn), dim3(256), 0, st, cnt, n + 1);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(gn), dim3(256), 0, st, fill, n + 1);
+  hipLaunchKernelGGL(rev_count_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, knn, n, K0, h, cnt);
+  // exclusive prefix over n + 1 counts (the last count is 0) -> off[0..n]
+  int64_t* cnt64 = nullptr;
+  e = hipMallocAsync((void**)&cnt64, (size_t)(n + 1) * 8, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(widen_kernel, dim3(gn), dim3(256), 0, st, cnt, n + 1, cnt64);
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt64, off, (int)(n + 1), st);
+  }
+  if (e == hipSuccess) e = hipMallocAsync(&tmp, tmp_bytes ? tmp_bytes : 16, st);
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt64, off, (int)(n + 1), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(rev_fill_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, knn, n, K0, h, off, fill,
+                       rev);
+    const size_t lds = (size_t)4 * (64 + 64 + 256 + 64) * 8;
+    hipLaunchKernelGGL(prune_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, st, knn, n, K0, deg, h, off, rev,
+                       graph);
+    e = hipGetLastError();
+  }
+  hipFreeAsync(cnt, st);
+  hipFreeAsync(fill, st);
+  hipFreeAsync(off, st);
+  hipFreeAsync(rev, st);
+  if (cnt64) hipFreeAsync(cnt64, st);
+  if (tmp) hipFreeAsync(tmp, st);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Seeded orders and small conversions.
+// ---------------------------------------------------------------------------
+__global__ void sm_keys_kernel(uint64_t seed, int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = sm_at(seed, (uint64_t)i + 1);
+  ids[i] = (uint32_t)i;
+}
+
+hipError_t keyed_order(uint64_t seed, int64_t n, uint32_t* out, hipStream_t st) {
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  uint32_t* v0 = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  hipError_t e = hipMallocAsync((void**)&k0, (size_t)n * 8, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&k1, (size_t)n * 8, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&v0, (size_t)n * 4, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sm_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, n, k0, v0);
+  // radix sort is stable and the ids enter in increasing order: ties in the key keep id order
+  e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, k1, v0, out, (int)n, 0, 64, st);
+  if (e == hipSuccess) e = hipMallocAsync(&tmp, tb ? tb : 16, st);
+  if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, k1, v0, out, (int)n, 0, 64, st);
+  hipFreeAsync(k0, st);
+  hipFreeAsync(k1, st);
+  hipFreeAsync(v0, st);
+  if (tmp) hipFreeAsync(tmp, st);
+  return e;
+}
+
+hipError_t sort_u32(uint32_t* v, int64_t n, hipStream_t st) {
+  uint32_t* o = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  hipError_t e = hipMallocAsync((void**)&o, (size_t)n * 4, st);
+  if (e != hipSuccess) return e;
+  e = hipcub::DeviceRadixSort::SortKeys(nullptr, tb, v, o, (int)n, 0, 32, st);
+  if (e == hipSuccess) e = hipMallocAsync(&tmp, tb ? tb : 16, st);
+  if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortKeys(tmp, tb, v, o, (int)n, 0, 32, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(v, o, (size_t)n * 4, hipMemcpyDeviceToDevice, st);
+  hipFreeAsync(o, st);
+  if (tmp) hipFreeAsync(tmp, st);
+  return e;
+}
+
+__global__ void keys_out_kernel(const uint64_t* __restrict__ keys, int64_t total, const uint32_t* __restrict__ gmap,
+                                int is_u8, uint32_t* __restrict__ ids, void* __restrict__ dists) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t k = keys[i];
+  const bool ok = k != kDummy;
+  ids[i] = ok ? (gmap ? gmap[(uint32_t)k] : (uint32_t)k) : kNone;
+  if (is_u8) ((int32_t*)dists)[i] = ok ? (int32_t)(k >> 32) : 0x7FFFFFFF;
+  else ((uint32_t*)dists)[i] = ok ? (uint32_t)(k >> 32) : 0x7F800000u;
+}
+
+hipError_t keys_to_output(const uint64_t* keys, int64_t nq, int k, const uint32_t* gmap, int is_u8, uint32_t* ids,
+                          void* dists, hipStream_t st) {
+  const int64_t tot = nq * k;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_out_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, keys, tot, gmap, is_u8,
+                     ids, dists);
+  return hipGetLastError();
+}
+
+__global__ void keys_ids_kernel(const uint64_t* __restrict__ keys, int64_t n, int k, int col, uint32_t* __restrict__ out,
+                                int stride) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = keys[i * k + col];
+  out[i * stride] = key == kDummy ? kNone : (uint32_t)key;
+}
+
+hipError_t keys_to_ids(const uint64_t* keys, int64_t n, int k, int col, uint32_t* out, int out_stride, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_ids_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, n, k, col, out,
+                     out_stride);
+  return hipGetLastError();
+}
+
+__global__ void keys_stage_kernel(const uint64_t* __restrict__ keys, int64_t nq, int k, const uint32_t* __restrict__ gmap,
+                                  int S, int s, uint64_t* __restrict__ so) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nq * k) return;
+  const int64_t q = i / k;
+  const int j = (int)(i % k);
+  const uint64_t key = keys[i];
+  so[((size_t)q * S + s) * k + j] = key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | gmap[(uint32_t)key]);
+}
+
+hipError_t keys_to_stage(const uint64_t* keys, int64_t nq, int k, const uint32_t* gmap, int S, int s, uint64_t* so,
+                         hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_stage_kernel, dim3((unsigned)((nq * k + 255) / 256)), dim3(256), 0, st, keys, nq, k, gmap, S,
+                     s, so);
+  return hipGetLastError();
+}
+
+}  // namespace miann

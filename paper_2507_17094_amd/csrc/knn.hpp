@@ -1,0 +1,49 @@
+// Host-callable launchers of the MFMA distance-tile kernels (knn.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace miann {
+
+// f32(scale * decode(code)) rows of a store, padded to d_pad_f32.
+hipError_t dequant_rows(const void* store, const float* scale, int store_dt, int64_t n, int d_pad, int d_pad_f32,
+                        float* out, hipStream_t st);
+
+// Queries-by-ghosts entry (Sec. 3.2.2, dense form): for every query whose start
+// shard is `shard` (every query when !ppe), the exact top-t ghosts of that
+// shard by (dist, id). Writes keys (dist bits << 32 | local id) to
+// out[(q * S + shard) * t + i].
+hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, const uint64_t* qkeys, int S, int shard,
+                       int ppe, const float* g_f32, const void* g_store, const float* g_scale, const uint32_t* g_map,
+                       int64_t R, int d_pad, int d_pad_f32, int t, uint64_t* out, hipStream_t st);
+
+// Exact k-NN of A rows against B rows by MFMA tiles + direct-form rescoring.
+//   A_f32 [na][dpf], B_f32 [nb][dpf]: f32 copies for the GEMM-form selection.
+//   A_raw / B_raw: the exact representation ([n][d_pad_raw], raw_dt) for rescoring;
+//   A_raw == nullptr means the queries are unpadded f32/u8 rows of length d.
+//   out: [na][k] keys (dist bits << 32 | base row index), sorted.
+hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t nb, int dpf, int d,
+                     int raw_dt, const void* A_raw, int a_raw_pad, const void* B_raw, const float* B_scale,
+                     int b_raw_pad, int k, int exclude_self, const uint32_t* qlist, uint64_t* out, hipStream_t st);
+
+// Prepares padded f32 copies of queries (f32 or u8 rows of length d).
+hipError_t queries_to_f32(const void* q, int q_dt, int64_t nq, int d, int dpf, float* out, hipStream_t st);
+
+// Graph pruning (reverse-merge rule) from sorted K0-NN keys [n][K0].
+hipError_t prune_graph(const uint64_t* knn, int64_t n, int K0, int deg, uint32_t* graph, hipStream_t st);
+
+// Seeded random order: ids sorted by (splitmix(seed, i + 1), i).
+hipError_t keyed_order(uint64_t seed, int64_t n, uint32_t* out, hipStream_t st);
+// Sorts u32 values ascending (in place).
+hipError_t sort_u32(uint32_t* v, int64_t n, hipStream_t st);
+
+// Converts final keys to (ids, dists) outputs with a local -> global map.
+hipError_t keys_to_output(const uint64_t* keys, int64_t nq, int k, const uint32_t* gmap, int is_u8, uint32_t* ids,
+                          void* dists, hipStream_t st);
+hipError_t keys_to_ids(const uint64_t* keys, int64_t n, int k, int col, uint32_t* out, int out_stride,
+                       hipStream_t st);
+
+hipError_t keys_to_stage(const uint64_t* keys, int64_t nq, int k, const uint32_t* gmap, int S, int s, uint64_t* so,
+                         hipStream_t st);
+
+}  // namespace miann

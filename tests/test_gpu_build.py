@@ -1,0 +1,98 @@
+"""GPU parity of index construction against the CPU oracle: MFMA exact k-NN with
+direct-form rescoring, reverse-merge pruning, the random shard partition, the
+inter-shard map I(u) (Sec. 3.1.2) and the ghost sample and ghost graph
+(Sec. 3.2.2). Distances are exactly rounded on both sides, so every list must
+match; ties are broken by id on both sides."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import d2h, dev, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+miann = pytest.importorskip("paper_2507_17094_amd")
+
+
+def shard_arrays(gx, s):
+    v = gx.shard(s)
+    out = dict(n=v.n, graph=d2h(v.graph, v.n * v.degree, np.uint32).reshape(v.n, v.degree),
+               gmap=d2h(v.global_ids, v.n, np.uint32))
+    if v.next_map:
+        out["next"] = d2h(v.next_map, v.n, np.uint32)
+    if v.n_ghost:
+        out["g_map"] = d2h(v.ghost_ids, v.n_ghost, np.uint32)
+        out["g_graph"] = d2h(v.ghost_graph, v.n_ghost * v.ghost_degree, np.uint32).reshape(v.n_ghost, v.ghost_degree)
+    return out
+
+
+@pytest.mark.parametrize("d,dtype", [(128, "f32"), (96, "f32"), (40, "f32"), (128, "u8")])
+def test_exact_knn_parity(d, dtype):
+    say(f"exact knn d={d} {dtype}")
+    X = synth.mixture_small(4000, d, 16, 0.3, 61)
+    Q = synth.mixture_small(333, d, 16, 0.3, 62)
+    if dtype == "u8":
+        X, Q = synth.to_u8(X), synth.to_u8(Q)
+    gx = miann.Index.build(dev(X), degree=16, num_shards=1, dgs_table=False)
+    for k in (1, 10, 100):
+        gi, gd = gx.exact_knn(dev(Q), k)
+        oi, od = oracle.knn(X, Q, k)
+        assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+        ref = od.astype(np.int32) if dtype == "u8" else od.astype(np.float32)
+        assert np.array_equal(gd.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("S", [1, 3])
+def test_build_graph_parity(S):
+    say(f"build graph S={S}")
+    X = synth.mixture_small(4000, 96, 16, 0.25, 71)
+    gx = miann.Index.build(dev(X), degree=32, num_shards=S, dgs_table=True, seed=5)
+    ox = oracle.build_index(X, deg=32, S=S, dgs=True, seed=5)
+    for s in range(S):
+        a = shard_arrays(gx, s)
+        assert np.array_equal(a["gmap"], ox.shards[s]["gmap"])
+        same = np.all(a["graph"] == ox.shards[s]["graph"], axis=1).mean()
+        say(f"  shard {s}: graph rows identical {same:.5f}")
+        assert same >= 0.999
+        if S > 1:
+            assert np.array_equal(a["next"], ox.shards[s]["next"])
+    gx.build_ghost(ratio=0.05, ghost_degree=16, seed=5)
+    oxg = oracle.build_index(X, deg=32, S=S, dgs=False, seed=5, ghost_ratio=0.05, deg_g=16)
+    for s in range(S):
+        a = shard_arrays(gx, s)
+        assert np.array_equal(a["g_map"], oxg.shards[s]["g_map"])
+        assert np.all(a["g_graph"] == oxg.shards[s]["g_graph"], axis=1).mean() >= 0.999
+
+
+def test_build_graph_u8_and_search_end_to_end():
+    say("u8 build + search end to end")
+    X = synth.to_u8(synth.mixture_small(3000, 128, 8, 0.3, 81))
+    Q = synth.to_u8(synth.mixture_small(200, 128, 8, 0.3, 82))
+    gx = miann.Index.build(dev(X), degree=32, num_shards=2, dgs_table=True, seed=9)
+    gx.build_ghost(ratio=0.05, ghost_degree=16, seed=9)
+    ox = oracle.build_index(X, deg=32, S=2, dgs=True, seed=9, ghost_ratio=0.05, deg_g=16)
+    for s in range(2):
+        a = shard_arrays(gx, s)
+        assert np.array_equal(a["graph"], ox.shards[s]["graph"])
+        assert np.array_equal(a["next"], ox.shards[s]["next"])
+        assert np.array_equal(a["g_graph"], ox.shards[s]["g_graph"])
+    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    gi, gd = gx.search(dev(Q), 10, 64, 60, opts)
+    oi, od, _ = oracle.search(ox, Q, k=10, l=64, T=60, entry="ghost_graph", dgs_on=True)
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
+def test_build_validation():
+    X = synth.mixture_small(100, 16, 2, 0.3, 1)
+    with pytest.raises(miann.MiannError):
+        miann.Index.build(dev(X), degree=65)
+    with pytest.raises(miann.MiannError):
+        miann.Index.build(dev(X), degree=32, num_shards=4)  # 100 < 4 * 33
+    gx = miann.Index.build(dev(X), degree=8)
+    with pytest.raises(miann.MiannError):
+        gx.build_ghost(num_ghost=10, ghost_degree=8)  # needs R > 2 * ghost_degree
+    with pytest.raises(miann.MiannError) as e:
+        gx.search(dev(X[:2]), 5, 16, 10, miann.SearchOptions(entry="ghost_graph"))
+    assert e.value.status == 4

@@ -1,0 +1,181 @@
+"""GPU parity of the HIP search path against the CPU oracle.
+
+Every case imports an oracle-built index (graphs, shard maps, ghost shards)
+into the library, so search parity is tested independently of build parity,
+and runs the same queries with the same parameters on both sides. The bar:
+the id lists match on >= 99.9% of queries (float distances within 1e-5
+relative, uint8 distances bit-exact), and the per-query expansion, iteration,
+skipped-slot and rerank counts agree.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import compare, dev, run_both, say, to_device_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+miann = pytest.importorskip("paper_2507_17094_amd")
+
+K = 10
+
+
+def mix(n, d, C, sigma, seed):
+    return synth.mixture_small(n, d, C, sigma, seed)
+
+
+@pytest.fixture(scope="module")
+def small():
+    """N = 3,000, d = 128, 8 components; ghost sample of 5% with a degree-16 ghost graph."""
+    X = mix(3000, 128, 8, 0.3, 11)
+    Q = mix(300, 128, 8, 0.3, 12)
+    ox = oracle.build_index(X, deg=32, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    return X, Q, ox, gx
+
+
+CASES = [
+    ("plain", 64, 80, dict()),
+    ("dgs", 64, 80, dict(dgs=True)),
+    ("dgs_r2", 64, 60, dict(dgs=True, search_width=2)),
+    ("r2", 64, 60, dict(search_width=2)),
+    ("ghost_graph", 64, 80, dict(entry="ghost_graph")),
+    ("ghost_graph_dgs", 64, 80, dict(entry="ghost_graph", dgs=True, ghost_iters=5, t_seeds=16)),
+    ("ghost_dense", 64, 80, dict(entry="ghost_dense")),
+    ("random_discard", 64, 80, dict(dgs=True, random_discard=True)),
+    ("stop_on_no_change", 64, 200, dict(stop_on_no_change=True)),
+    ("n_init_300_small_hash", 64, 80, dict(n_init=300, hash_log2=8)),
+    ("itopk_256", 256, 300, dict(dgs=True, cooldown=0.5)),
+    ("itopk_k", 10, 40, dict()),
+    ("T0", 64, 0, dict(n_init=100)),
+    ("discard_07", 64, 80, dict(dgs=True, discard=0.7, cooldown=0.1)),
+]
+
+
+@pytest.mark.parametrize("name,itopk,T,kw", CASES, ids=[c[0] for c in CASES])
+def test_search_parity_small(small, name, itopk, T, kw):
+    X, Q, ox, gx = small
+    say(f"case {name}: nq={len(Q)} itopk={itopk} T={T} {kw}")
+    opts = miann.SearchOptions(**kw)
+    g, o = run_both(ox, gx, Q, min(K, itopk), itopk, T, opts)
+    compare(g, o, label=name)
+
+
+@pytest.mark.parametrize("d", [16, 100, 200])
+def test_search_parity_odd_dims(d):
+    say(f"odd dims d={d}")
+    X = mix(1500, d, 5, 0.3, 21)
+    Q = mix(100, d, 5, 0.3, 22)
+    ox = oracle.build_index(X, deg=16, dgs=True, ghost_R=100, deg_g=8)
+    gx = to_device_index(ox)
+    for kw in (dict(), dict(dgs=True, entry="ghost_graph"), dict(entry="ghost_dense", search_width=4)):
+        g, o = run_both(ox, gx, Q, K, 48, 60, miann.SearchOptions(**kw))
+        compare(g, o, label=f"d{d}-{kw}")
+
+
+@pytest.mark.parametrize("S", [2, 3])
+def test_path_extension_parity(S):
+    """Path extension across S resident shards (Sec. 3.1.2) and naive sharding."""
+    say(f"shards S={S}")
+    X = mix(3000, 96, 8, 0.25, 31)
+    Q = mix(200, 96, 8, 0.25, 32)
+    ox = oracle.build_index(X, deg=32, S=S, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    for kw in (dict(), dict(dgs=True, entry="ghost_graph"), dict(ppe=False, entry="ghost_dense"),
+               dict(forward_f=4, dgs=True), dict(ppe=False)):
+        g, o = run_both(ox, gx, Q, K, 64, 50, miann.SearchOptions(**kw))
+        compare(g, o, label=f"S{S}-{kw}")
+
+
+@pytest.mark.parametrize("store", ["f16", "fp8"])
+def test_low_precision_parity(store):
+    say(f"low precision store={store}")
+    X = mix(2500, 256, 8, 0.2, 41)
+    Q = mix(150, 256, 8, 0.2, 42)
+    ox = oracle.build_index(X, deg=32, dgs=True, store=store, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    for kw, itopk in ((dict(), 64), (dict(dgs=True, entry="ghost_graph"), 64), (dict(entry="ghost_dense"), 40),
+                      (dict(rerank_mult=8), 64)):
+        g, o = run_both(ox, gx, Q, K, itopk, 60, miann.SearchOptions(**kw))
+        compare(g, o, label=f"{store}-{kw}")
+    # traversal codes: the device quantiser matches the oracle's bit for bit
+    from gpu_util import d2h
+    v = gx.shard(0)
+    dt = np.uint16 if store == "f16" else np.uint8
+    codes = d2h(v.store, v.n * v.d_pad, dt).reshape(v.n, v.d_pad)[:, :256]
+    scale = d2h(v.scale, v.n, np.float32)
+    assert np.array_equal(codes, ox.shards[0]["codes"])
+    assert np.array_equal(scale, ox.shards[0]["scale"])
+
+
+def test_u8_parity_bit_exact():
+    say("u8 data")
+    Xf = mix(3000, 128, 8, 0.3, 51)
+    X = synth.to_u8(Xf)
+    Q = synth.to_u8(mix(200, 128, 8, 0.3, 52))
+    ox = oracle.build_index(X, deg=32, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    for kw in (dict(), dict(dgs=True), dict(entry="ghost_graph", dgs=True), dict(entry="ghost_dense")):
+        g, o = run_both(ox, gx, Q, K, 64, 60, miann.SearchOptions(**kw))
+        frac = compare(g, o, min_frac=1.0, label=f"u8-{kw}")
+        assert frac == 1.0
+
+
+def test_sign_table_parity(small):
+    from gpu_util import d2h
+    X, Q, ox, gx = small
+    v = gx.shard(0)
+    S = d2h(v.sign, v.n * v.W * v.degree, np.uint32).reshape(v.n, v.W, v.degree)
+    assert np.array_equal(S.transpose(0, 2, 1), ox.shards[0]["sign"])
+
+
+def test_batch_independence_and_query_keys(small):
+    """A query's result depends on its key, not on its batch (serving requirement)."""
+    X, Q, ox, gx = small
+    opts = miann.SearchOptions(dgs=True, entry="ghost_graph")
+    full = gx.search(dev(Q), K, 64, 60, opts)
+    sub = np.arange(7, 300, 5)
+    part = gx.search(dev(Q[sub]), K, 64, 60, opts, qkeys=torch.from_numpy(sub.astype(np.int64)).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(full[0].cpu().numpy()[sub], part[0].cpu().numpy())
+    assert np.array_equal(full[1].cpu().numpy()[sub], part[1].cpu().numpy())
+
+
+def test_per_query_budget_and_seed_entry(small):
+    X, Q, ox, gx = small
+    rng = np.random.default_rng(3)
+    Tq = rng.integers(0, 90, len(Q)).astype(np.int32)
+    seeds = rng.integers(0, len(X), (len(Q), 24)).astype(np.uint32)
+    opts = miann.SearchOptions(entry="seeds", dgs=True)
+    g, o = run_both(ox, gx, Q, K, 64, 80, opts, seeds=seeds, Tq=Tq)
+    compare(g, o, label="seeds+Tq")
+
+
+def test_full_tiny_workload():
+    """The tiny configuration at full size: N = 10,000, d = 128, 32 components, degree 32,
+    1,000 queries, k = 10, itopk = 64."""
+    say("tiny workload N=10000 nq=1000")
+    X = synth.mixture_small(10_000, 128, 32, 0.3, synth.SEED_BASE)
+    Q = synth.mixture_small(1000, 128, 32, 0.3, synth.SEED_QUERIES)
+    ox = oracle.build_index(X, deg=32, dgs=True, ghost_ratio=0.01, deg_g=32)
+    gx = to_device_index(ox)
+    for kw in (dict(), dict(n_init=256), dict(entry="ghost_dense", dgs=True), dict(entry="ghost_graph", dgs=True)):
+        g, o = run_both(ox, gx, Q, K, 64, 64, miann.SearchOptions(**kw))
+        compare(g, o, label=f"tiny-{kw}")
+
+
+def test_validation_errors(small):
+    X, Q, ox, gx = small
+    q = dev(Q[:4])
+    with pytest.raises(miann.MiannError) as e:
+        gx.search(q, 20, 10, 10)
+    assert e.value.status == 1
+    with pytest.raises(miann.MiannError):
+        gx.search(q, 10, 600, 10)
+    with pytest.raises(miann.MiannError):
+        gx.search(q, 10, 64, 10, miann.SearchOptions(search_width=3))  # 3 * 32 > 64
+    with pytest.raises(miann.MiannError):
+        gx.search(q, 10, 64, 10, miann.SearchOptions(hash_log2=7))
+    ids, dists = gx.search(dev(Q[:0]), 10, 64, 10)
+    assert ids.shape == (0, 10)
