@@ -51,7 +51,9 @@ typedef enum {
   MIANN_ENTRY_RANDOM = 0,      /* n_init random nodes (Sec. 2.2 Step 2) */
   MIANN_ENTRY_GHOST_GRAPH = 1, /* beam search on the ghost graph (Sec. 3.2.2) */
   MIANN_ENTRY_GHOST_DENSE = 2, /* exact top-t over all ghost nodes, MFMA distances */
-  MIANN_ENTRY_SEEDS = 3        /* caller-provided seed ids (e.g. a learned predictor) */
+  MIANN_ENTRY_SEEDS = 3,       /* caller-provided seed ids (e.g. a learned predictor) */
+  MIANN_ENTRY_PREDICTED = 4    /* seeds per query; a row whose first seed is 0xFFFFFFFF (low predictor
+                                  confidence) falls back to the ghost-graph entry */
 } miann_entry;
 
 typedef struct miann_index miann_index; /* opaque, library-owned */
@@ -65,7 +67,8 @@ enum {
   MIANN_CTR_NDIST_GHOST = 4, /* distance evaluations in the ghost stage */
   MIANN_CTR_NEXP_GHOST = 5,  /* expansions in the ghost stage */
   MIANN_CTR_NRERANK = 6,     /* FP32 rerank evaluations (low-precision stores) */
-  MIANN_CTR_RESERVED = 7,
+  MIANN_CTR_LAST_TOPK = 7,   /* last iteration (1-based, 0 = none) in which the first k entries of p
+                                changed, summed over stages: the iteration-budget trace */
   MIANN_NCTR = 8
 };
 
@@ -173,6 +176,9 @@ typedef struct {
   const uint64_t* qkeys;    /* device [nq] query keys (index within a request), NULL = row index */
   const uint32_t* seeds;    /* device [nq][n_seeds] local ids in each query's start shard */
   const int32_t* max_iters_per_query; /* device [nq] per-query T, NULL = max_iters */
+  float* phase_ms;          /* host [2 + S] or NULL: when set, the call records HIP events around
+                               its launches, synchronises `stream` and writes the milliseconds of
+                               [dense ghost entry, stage 0 .. stage S-1, shard merge] */
 } miann_search_params;
 
 /* Fills the documented defaults: r = 1, n_init = degree, random entry,
@@ -200,6 +206,100 @@ miann_status miann_search(const miann_index* idx, const void* queries_dev, int64
  * Same layouts as miann_search. k <= 256. Enqueues on `stream`. */
 miann_status miann_exact_knn(const miann_index* idx, const void* queries_dev, int64_t nq, int32_t k,
                              uint32_t* ids_dev, void* dists_dev, void* stream);
+
+/* Ghost index (0..R-1) of the nearest ghost node of shard `shard` to each row of
+ * `vectors_dev` ([n][d], the index's input type), by (dist, ghost index): the
+ * entry-region label of a vector. Enqueues on `stream`. */
+miann_status miann_nearest_ghost(const miann_index* idx, int32_t shard, const void* vectors_dev, int64_t n,
+                                 uint32_t* ghost_idx_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned entry / iteration-budget predictor                                */
+/* ------------------------------------------------------------------------ */
+/* A BF16 MLP d_in -> hidden -> hidden -> (n_entry logits + 1 budget output),
+ * ReLU hidden layers, FP32 master weights, trained with Adam by the library's
+ * own GEMM / loss / backward kernels. Loss per row: softmax cross-entropy of
+ * the entry label + lambda * (budget output - log(1 + budget label))^2, mean
+ * over the batch. Inputs to the GEMMs, stored activations and the output
+ * gradient are rounded to bf16; accumulation is FP32. Not a part of the paper:
+ * it predicts the ghost-staging entry region and the iteration budget. */
+typedef struct miann_predictor miann_predictor;
+
+typedef struct {
+  int32_t d_in, hidden, n_entry;
+  float *W1, *b1, *W2, *b2, *W3, *b3;       /* device FP32 masters: W1 [d_in][hidden], W2 [hidden][hidden],
+                                               W3 [hidden][n_entry + 1], row-major (x W) */
+  float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3; /* device gradients of the last step, same layouts */
+} miann_predictor_view;
+
+/* Weights U(-a, a) with a = sqrt(6 / fan_in) from SplitMix64(seed), biases 0. */
+miann_status miann_predictor_create(int32_t d_in, int32_t hidden, int32_t n_entry, uint64_t seed,
+                                    miann_predictor** out);
+void miann_predictor_free(miann_predictor* p);
+miann_status miann_predictor_view_get(miann_predictor* p, miann_predictor_view* out);
+/* Refreshes the bf16 weight copies after the FP32 masters were written through the view. */
+miann_status miann_predictor_sync_weights(miann_predictor* p, void* stream);
+/* One forward + loss + backward over n rows (x [n][d_in] f32, entry [n] int32 in [0, n_entry), clamped
+ * into that range,
+ * budget [n] f32 = log(1 + iterations)); leaves the gradients in the view; applies one Adam step
+ * (lr, betas 0.9 / 0.999, eps 1e-8) when `update`. Writes the mean loss to *loss_host. Synchronises. */
+miann_status miann_predictor_step(miann_predictor* p, const float* x_dev, const int32_t* entry_dev,
+                                  const float* budget_dev, int32_t n, float lambda, float lr, int32_t update,
+                                  float* loss_host, void* stream);
+/* Mini-batch training: each epoch visits the rows in a SplitMix64-keyed random order. epoch_loss_host
+ * ([epochs], nullable) receives the mean batch loss of each epoch. Synchronises. */
+miann_status miann_predictor_train(miann_predictor* p, const float* x_dev, const int32_t* entry_dev,
+                                   const float* budget_dev, int64_t n, int32_t epochs, int32_t batch, float lr,
+                                   float lambda, uint64_t seed, float* epoch_loss_host, void* stream);
+/* Inference: for each row, confidence = max softmax probability of the entry logits; seeds_dev [n][t] =
+ * ghost_map[index] of the t largest logits (seeds[0] = 0xFFFFFFFF when confidence < tau);
+ * iters_dev [n] = clamp(ceil(1.25 (exp(budget) - 1)), t_min, t_max); top_entry_dev [n][t] (nullable)
+ * receives the raw entry indices. Enqueues on `stream`. */
+miann_status miann_predictor_predict(const miann_predictor* p, const float* x_dev, int64_t n, int32_t t, float tau,
+                                     const uint32_t* ghost_map_dev, int32_t t_min, int32_t t_max, uint32_t* seeds_dev,
+                                     int32_t* iters_dev, float* conf_dev, uint32_t* top_entry_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching over a resident index                       */
+/* ------------------------------------------------------------------------ */
+/* A scheduler thread coalesces pending requests of the same search shape (k,
+ * itopk, max_iters, parameters) into one launch of up to max_batch_queries,
+ * admits a batch only while the in-flight queries and device bytes stay within
+ * max_inflight_queries and memory_budget_bytes, and runs batches concurrently
+ * on num_streams HIP streams. Queries are searched with their index inside
+ * their request as the query key, so results are the same alone and in any mix. */
+typedef struct miann_server miann_server;
+
+typedef struct {
+  int32_t num_streams;          /* concurrent batches (1..32), default 4 */
+  int32_t reserved;
+  int64_t max_batch_queries;    /* queries coalesced into one launch, default 8192 */
+  int64_t max_inflight_queries; /* admission limit on queries on the device, default 65536 */
+  int64_t memory_budget_bytes;  /* admission limit on device bytes of in-flight batches, default 1 GiB */
+} miann_server_config;
+
+typedef struct {
+  int64_t requests_done, queries_done, batches;
+  int64_t peak_inflight_queries, peak_inflight_bytes;
+  double elapsed_s;             /* since miann_server_create */
+} miann_server_stats;
+
+void miann_server_config_default(miann_server_config* cfg);
+/* The index must outlive the server. */
+miann_status miann_server_create(const miann_index* idx, const miann_server_config* cfg, miann_server** out);
+/* Queues one request: queries_host [nq][d] host rows of the index's input type (copied by the call),
+ * k, itopk, max_iters and parameters as for miann_search (sp may be NULL; its qkeys, seeds,
+ * max_iters_per_query and phase_ms must be NULL). Validates like miann_search; a request larger than
+ * the server's limits is EINVAL. Thread-safe. *ticket identifies the request. */
+miann_status miann_server_submit(miann_server* srv, const void* queries_host, int64_t nq, int32_t k, int32_t itopk,
+                                 int32_t max_iters, const miann_search_params* sp, uint64_t* ticket);
+/* Blocks until the request is done; copies ids [nq][k] and dists [nq][k] to host buffers (nullable) and
+ * the latency from submission to completion in milliseconds. Each ticket can be waited for once. */
+miann_status miann_server_wait(miann_server* srv, uint64_t ticket, uint32_t* ids_host, void* dists_host,
+                               double* latency_ms);
+miann_status miann_server_get_stats(miann_server* srv, miann_server_stats* out);
+/* Completes every queued request, then frees the server. */
+void miann_server_destroy(miann_server* srv);
 
 /* Thread-local text of the last error (empty string if none). */
 const char* miann_last_error(void);

@@ -30,10 +30,10 @@ DTYPES = {"f32": DT_F32, "f16": DT_F16, "fp8": DT_FP8, "u8": DT_U8}
 NONE_ID = 0xFFFFFFFF
 MAXS = 16
 NCTR = 8
-ENTRY = {"random": 0, "ghost_graph": 1, "ghost_dense": 2, "seeds": 3}
+ENTRY = {"random": 0, "ghost_graph": 1, "ghost_dense": 2, "seeds": 3, "predicted": 4}
 VISITED = {"exact": 0, "forget_each_iter": 1, "small_hash": 2}
 # counter slots
-CTR_NAMES = ["n_dist", "n_exp", "iters", "n_dgs_skipped", "n_dist_ghost", "n_exp_ghost", "n_rerank", "reserved"]
+CTR_NAMES = ["n_dist", "n_exp", "iters", "n_dgs_skipped", "n_dist_ghost", "n_exp_ghost", "n_rerank", "last_topk_change"]
 
 
 def compile_lib(force: bool = False) -> str:

@@ -528,7 +528,7 @@ typedef struct {
 } graph_view;
 
 typedef struct {
-  int l, r, T, n_init;
+  int l, r, T, n_init, k;
   int dgs_on, n_keep, cooldown_pm, random_discard;
   int visited_policy, stop_on_no_change;
 } beam_cfg;
@@ -541,7 +541,7 @@ typedef struct {
   visited V;
 } beam_scratch;
 
-static void merge_into_p(entry* p, int l, entry* c, int nc, entry* tmp, int* changed) {
+static void merge_into_p(entry* p, int l, entry* c, int nc, entry* tmp, int* changed, int k, int* topk_changed) {
   /* p <- first l of sort(p U c); an id present twice keeps its p entry. */
   int n = 0;
   for (int i = 0; i < l; i++) { tmp[n] = p[i]; tmp[n].from_c = 0; n++; }
@@ -550,7 +550,10 @@ static void merge_into_p(entry* p, int l, entry* c, int nc, entry* tmp, int* cha
   int m = 0, ch = 0;
   for (int i = 0; i < n && m < l; i++) {
     if (m > 0 && tmp[i].id != NONE_ID && tmp[i].id == p[m - 1].id) continue; /* duplicate id */
-    if (tmp[i].from_c && tmp[i].id != NONE_ID) ch = 1;
+    if (tmp[i].from_c && tmp[i].id != NONE_ID) {
+      ch = 1;
+      if (topk_changed && m < k) *topk_changed = 1;
+    }
     p[m] = tmp[i];
     p[m].from_c = 0;
     m++;
@@ -566,7 +569,8 @@ static inline int popc32(uint32_t x) {
 
 /* One search. seeds (may be NULL) are node ids of this graph, in order.
  * On return p[0..l) holds the final priority queue. ctr[0..3] accumulate
- * n_dist, n_exp, iters, n_dgs_skipped. */
+ * n_dist, n_exp, iters, n_dgs_skipped; ctr[4] is set to the last iteration
+ * (1-based, 0 = none) in which the first k entries of p changed. */
 static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint64_t stream,
                         const uint32_t* seeds, int n_seeds, const beam_cfg* cfg, int T,
                         beam_scratch* sc, int64_t* ctr) {
@@ -600,7 +604,7 @@ static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint6
     nc++;
     ctr[0]++;
   }
-  merge_into_p(p, l, c, nc, sc->merged, NULL);
+  merge_into_p(p, l, c, nc, sc->merged, NULL, 0, NULL);
 
   /* Steps 3-4 repeated. */
   const int n_cool = (cfg->cooldown_pm * T + 999) / 1000; /* ceil(c * T) */
@@ -683,9 +687,10 @@ static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint6
       }
       ctr[1]++;
     }
-    int changed = 0;
-    merge_into_p(p, l, c, nc, sc->merged, &changed);
+    int changed = 0, topk = 0;
+    merge_into_p(p, l, c, nc, sc->merged, &changed, cfg->k, &topk);
     it++;
+    if (topk) ctr[4] = it; /* last iteration in which the first k entries of p changed */
     if (cfg->stop_on_no_change && !changed) break;
   }
   ctr[2] += it;
@@ -733,6 +738,7 @@ typedef struct {
 #define ENTRY_GHOST_GRAPH 1
 #define ENTRY_GHOST_DENSE 2
 #define ENTRY_SEEDS 3
+#define ENTRY_PREDICTED 4 /* given seeds; a row whose first seed is NONE uses the ghost graph */
 
 typedef struct {
   int32_t k, l, r, T, n_init;
@@ -790,7 +796,7 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
   int nhand = 0;
 
   beam_cfg cfg;
-  cfg.l = l; cfg.r = P->r; cfg.T = T; cfg.n_init = P->n_init;
+  cfg.l = l; cfg.r = P->r; cfg.T = T; cfg.n_init = P->n_init; cfg.k = k;
   cfg.dgs_on = P->dgs_on;
   cfg.n_keep = ix->deg - (P->discard_pm * ix->deg) / 1000;
   cfg.cooldown_pm = P->cooldown_pm;
@@ -805,22 +811,26 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
     const uint32_t* sd = NULL;
     nseeds = 0;
     int use_entry = (t == 0 || !P->ppe_on);
+    int ent = P->entry;
+    if (ent == ENTRY_PREDICTED)
+      ent = (t == 0 && C->given_seeds && C->given_seeds[(size_t)row * C->n_given] != NONE_ID) ? ENTRY_SEEDS
+                                                                                             : ENTRY_GHOST_GRAPH;
     if (!use_entry) {
       /* path extension: continue from I(z) for the first f results of the previous stage */
       for (int i = 0; i < nhand; i++) seeds[nseeds++] = handoff[i];
       sd = seeds;
-    } else if (P->entry == ENTRY_GHOST_GRAPH || P->entry == ENTRY_GHOST_DENSE) {
+    } else if (ent == ENTRY_GHOST_GRAPH || ent == ENTRY_GHOST_DENSE) {
       orc_store gs = {ix->dtype, ix->d, ix->R[s], ix->g_codes[s], ix->g_scale[s]};
       int tt = P->t_seeds;
       res top[1024];
       int ntop = 0;
-      if (P->entry == ENTRY_GHOST_GRAPH) {
+      if (ent == ENTRY_GHOST_GRAPH) {
         /* ghost stage: the same search on the ghost graph, DGS off */
         graph_view gg = {&gs, ix->g_graph[s], ix->deg_g, NULL, ix->W};
         beam_cfg gc = cfg;
         gc.l = P->l_g; gc.T = P->T_g; gc.n_init = ix->deg_g; gc.dgs_on = 0; gc.stop_on_no_change = 0;
         beam_scratch* gsc = sc + 1;
-        int64_t gctr[4] = {0, 0, 0, 0};
+        int64_t gctr[5] = {0, 0, 0, 0, 0};
         beam_search(&gg, q, qkey, orc_stream_ghost(P->seed, s), NULL, 0, &gc, P->T_g, gsc, gctr);
         ctr[4] += gctr[0];
         ctr[5] += gctr[1];
@@ -850,13 +860,13 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
       if (C->out_ghost && t == 0)
         for (int i = ntop; i < tt; i++) C->out_ghost[(size_t)row * P->t_seeds + i] = NONE_ID;
       sd = seeds;
-    } else if (P->entry == ENTRY_SEEDS && C->given_seeds && t == 0) {
+    } else if (ent == ENTRY_SEEDS && C->given_seeds && t == 0) {
       for (int i = 0; i < C->n_given; i++) seeds[nseeds++] = C->given_seeds[(size_t)row * C->n_given + i];
       sd = seeds;
     }
-    int64_t bctr[4] = {0, 0, 0, 0};
+    int64_t bctr[5] = {0, 0, 0, 0, 0};
     beam_search(&g, q, qkey, orc_stream_main(P->seed, s), sd, nseeds, &cfg, T, sc, bctr);
-    ctr[0] += bctr[0]; ctr[1] += bctr[1]; ctr[2] += bctr[2]; ctr[3] += bctr[3];
+    ctr[0] += bctr[0]; ctr[1] += bctr[1]; ctr[2] += bctr[2]; ctr[3] += bctr[3]; ctr[7] += bctr[4];
 
     /* hand-off for the next stage: I_s(z) for the first f entries of p */
     nhand = 0;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmiann.so")
 F32, F16, FP8E4M3, U8 = 0, 1, 2, 3
 DTYPE_CODES = {"f32": F32, "f16": F16, "fp8": FP8E4M3, "u8": U8}
 ENTRY_RANDOM, ENTRY_GHOST_GRAPH, ENTRY_GHOST_DENSE, ENTRY_SEEDS = 0, 1, 2, 3
-ENTRY_CODES = {"random": 0, "ghost_graph": 1, "ghost_dense": 2, "seeds": 3}
+ENTRY_CODES = {"random": 0, "ghost_graph": 1, "ghost_dense": 2, "seeds": 3, "predicted": 4}
 NCTR = 8
 NONE_ID = 0xFFFFFFFF
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED"}
@@ -26,7 +26,10 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNS
 EXPORTS = [
     "miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard", "miann_index_info",
     "miann_index_free", "miann_search_params_default", "miann_search", "miann_exact_knn", "miann_last_error",
-    "miann_version",
+    "miann_version", "miann_nearest_ghost", "miann_predictor_create", "miann_predictor_free",
+    "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step", "miann_predictor_train",
+    "miann_predictor_predict", "miann_server_config_default", "miann_server_create", "miann_server_submit",
+    "miann_server_wait", "miann_server_get_stats", "miann_server_destroy",
 ]
 
 
@@ -64,7 +67,22 @@ class SearchParams(C.Structure):
                 ("random_discard", C.c_int32), ("ppe", C.c_int32), ("forward_f", C.c_int32),
                 ("rerank_mult", C.c_int32), ("stop_on_no_change", C.c_int32), ("hash_log2", C.c_int32),
                 ("n_seeds", C.c_int32), ("seed", C.c_uint64), ("qkeys", C.c_void_p), ("seeds", C.c_void_p),
-                ("max_iters_per_query", C.c_void_p)]
+                ("max_iters_per_query", C.c_void_p), ("phase_ms", C.c_void_p)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("num_streams", C.c_int32), ("reserved", C.c_int32), ("max_batch_queries", C.c_int64),
+                ("max_inflight_queries", C.c_int64), ("memory_budget_bytes", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64), ("batches", C.c_int64),
+                ("peak_inflight_queries", C.c_int64), ("peak_inflight_bytes", C.c_int64), ("elapsed_s", C.c_double)]
+
+
+class PredictorView(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("hidden", C.c_int32), ("n_entry", C.c_int32)] + \
+               [(n, C.c_void_p) for n in ("W1", "b1", "W2", "b2", "W3", "b3", "gW1", "gb1", "gW2", "gb2", "gW3", "gb3")]
 
 
 _lib = None
@@ -96,8 +114,30 @@ def load():
     L.miann_exact_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     L.miann_last_error.restype = C.c_char_p
     L.miann_version.restype = C.c_char_p
+    L.miann_nearest_ghost.argtypes = [vp, i32, vp, i64, vp, vp]
+    L.miann_predictor_create.argtypes = [i32, i32, i32, u64, C.POINTER(vp)]
+    L.miann_predictor_free.argtypes = [vp]
+    L.miann_predictor_free.restype = None
+    L.miann_predictor_view_get.argtypes = [vp, C.POINTER(PredictorView)]
+    L.miann_predictor_sync_weights.argtypes = [vp, vp]
+    L.miann_predictor_step.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, i32, C.POINTER(C.c_float), vp]
+    L.miann_predictor_train.argtypes = [vp, vp, vp, vp, i64, i32, i32, C.c_float, C.c_float, u64,
+                                        C.POINTER(C.c_float), vp]
+    L.miann_predictor_predict.argtypes = [vp, vp, i64, i32, C.c_float, vp, i32, i32, vp, vp, vp, vp, vp]
+    L.miann_server_config_default.argtypes = [C.POINTER(ServerConfig)]
+    L.miann_server_config_default.restype = None
+    L.miann_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+    L.miann_server_submit.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), C.POINTER(u64)]
+    L.miann_server_wait.argtypes = [vp, u64, vp, vp, C.POINTER(C.c_double)]
+    L.miann_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.miann_server_destroy.argtypes = [vp]
+    L.miann_server_destroy.restype = None
+    for f in ("miann_server_create", "miann_server_submit", "miann_server_wait", "miann_server_get_stats"):
+        getattr(L, f).restype = C.c_int
     for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
-              "miann_index_info", "miann_search", "miann_exact_knn"):
+              "miann_index_info", "miann_search", "miann_exact_knn", "miann_nearest_ghost", "miann_predictor_create",
+              "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step",
+              "miann_predictor_train", "miann_predictor_predict"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -248,8 +288,11 @@ class Index:
 
     # -- search -----------------------------------------------------------
     def search(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None,
-               qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None):
-        """Returns (ids [nq,k] int32 view of uint32, dists [nq,k] float32|int32[, counters [nq,8] int64])."""
+               qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None,
+               phase_ms=None):
+        """Returns (ids [nq,k] int32 view of uint32, dists [nq,k] float32|int32[, counters [nq,8] int64]).
+        phase_ms: optional list that receives per-launch milliseconds [dense, stage 0..S-1, merge]
+        (the call then synchronises the stream)."""
         torch = _torch()
         for n_, t_ in (("queries", queries), ("qkeys", qkeys), ("seeds", seeds), ("max_iters_per_query", max_iters_per_query)):
             _require_cuda(t_, n_)
@@ -263,8 +306,14 @@ class Index:
             ids, dists = out
         ctr = torch.empty((nq, NCTR), dtype=torch.int64, device=queries.device) if counters else None
         p = opts.cstruct(qkeys, seeds, max_iters_per_query)
+        tbuf = None
+        if phase_ms is not None:
+            tbuf = (C.c_float * (2 + self.info()["num_shards"]))()
+            p.phase_ms = C.cast(tbuf, C.c_void_p)
         _check(load().miann_search(self._h, queries.data_ptr(), nq, k, itopk, max_iters, C.byref(p), ids.data_ptr(),
                                    dists.data_ptr(), _ptr(ctr), _stream_ptr(stream)))
+        if tbuf is not None:
+            phase_ms[:] = list(tbuf)
         return (ids, dists, ctr) if counters else (ids, dists)
 
     def exact_knn(self, queries, k: int, stream=None):
@@ -276,6 +325,150 @@ class Index:
         _check(load().miann_exact_knn(self._h, queries.data_ptr(), nq, k, ids.data_ptr(), dists.data_ptr(),
                                       _stream_ptr(stream)))
         return ids, dists
+
+
+class Predictor:
+    """Learned entry / iteration-budget predictor (BF16 MLP trained by the library's kernels)."""
+
+    def __init__(self, d_in: int, hidden: int, n_entry: int, seed: int = 1):
+        h = C.c_void_p()
+        _check(load().miann_predictor_create(d_in, hidden, n_entry, seed & (2**64 - 1), C.byref(h)))
+        self._h = h
+        self.d_in, self.hidden, self.n_entry = d_in, hidden, n_entry
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.miann_predictor_free(self._h)
+            self._h = C.c_void_p(0)
+
+    def view(self) -> PredictorView:
+        v = PredictorView()
+        _check(load().miann_predictor_view_get(self._h, C.byref(v)))
+        return v
+
+    def tensors(self, grads: bool = False) -> dict:
+        """Device tensors aliasing the FP32 masters (or the gradients)."""
+        torch = _torch()
+        v = self.view()
+        shapes = {"W1": (self.d_in, self.hidden), "b1": (self.hidden,), "W2": (self.hidden, self.hidden),
+                  "b2": (self.hidden,), "W3": (self.hidden, self.n_entry + 1), "b3": (self.n_entry + 1,)}
+        out = {}
+        for k, shp in shapes.items():
+            ptr = getattr(v, ("g" + k) if grads else k)
+            n = 1
+            for s_ in shp:
+                n *= s_
+            t = torch.empty(shp, dtype=torch.float32, device="cuda")
+            _hip_copy(t.data_ptr(), ptr, n * 4)
+            out[k] = t
+        return out
+
+    def set_weights(self, w: dict, stream=None) -> None:
+        v = self.view()
+        for k, t in w.items():
+            t = t.contiguous().float().cuda()
+            _hip_copy(getattr(v, k), t.data_ptr(), t.numel() * 4)
+        _check(load().miann_predictor_sync_weights(self._h, _stream_ptr(stream)))
+
+    def step(self, x, entry, budget, lam: float = 1.0, lr: float = 1e-3, update: bool = False, stream=None) -> float:
+        loss = C.c_float()
+        _check(load().miann_predictor_step(self._h, x.data_ptr(), entry.data_ptr(), budget.data_ptr(), x.shape[0],
+                                           lam, lr, int(update), C.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def train(self, x, entry, budget, epochs: int, batch: int = 4096, lr: float = 1e-3, lam: float = 1.0,
+              seed: int = 3, stream=None) -> list:
+        losses = (C.c_float * epochs)()
+        _check(load().miann_predictor_train(self._h, x.data_ptr(), entry.data_ptr(), budget.data_ptr(), x.shape[0],
+                                            epochs, batch, lr, lam, seed & (2**64 - 1), losses, _stream_ptr(stream)))
+        return list(losses)
+
+    def predict(self, x, t: int, tau: float, ghost_map, t_min: int, t_max: int, stream=None):
+        """Returns (seeds [n,t] int32 view of uint32, iters [n] int32, conf [n] f32, top entries [n,t])."""
+        torch = _torch()
+        if ghost_map.shape[0] < self.n_entry:
+            raise MiannError(1, f"ghost_map has {ghost_map.shape[0]} entries, the predictor has {self.n_entry}")
+        n = x.shape[0]
+        seeds = torch.empty((n, t), dtype=torch.int32, device=x.device)
+        iters = torch.empty(n, dtype=torch.int32, device=x.device)
+        conf = torch.empty(n, dtype=torch.float32, device=x.device)
+        top = torch.empty((n, t), dtype=torch.int32, device=x.device)
+        _check(load().miann_predictor_predict(self._h, x.data_ptr(), n, t, tau, ghost_map.data_ptr(), t_min, t_max,
+                                              seeds.data_ptr(), iters.data_ptr(), conf.data_ptr(), top.data_ptr(),
+                                              _stream_ptr(stream)))
+        return seeds, iters, conf, top
+
+
+_hip = None
+
+
+def _hip_copy(dst: int, src: int, nbytes: int) -> None:
+    """Device-to-device copy between raw pointers (hipMemcpy, kind = default)."""
+    global _hip
+    torch = _torch()
+    torch.cuda.synchronize()
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = _hip.hipMemcpy(dst, src, nbytes, 4)
+    if rc != 0:
+        raise MiannError(3, f"hipMemcpy failed ({rc})")
+
+
+def nearest_ghost(index: "Index", vectors, shard: int = 0, stream=None):
+    """Ghost index of the nearest ghost node of `shard` for each row of `vectors` (device tensor)."""
+    torch = _torch()
+    out = torch.empty(vectors.shape[0], dtype=torch.int32, device=vectors.device)
+    _check(load().miann_nearest_ghost(index.handle, shard, vectors.data_ptr(), vectors.shape[0], out.data_ptr(),
+                                      _stream_ptr(stream)))
+    return out
+
+
+class Server:
+    """Continuous-batching serving loop over a resident index (host query rows in, host results out)."""
+
+    def __init__(self, index: "Index", num_streams: int = 4, max_batch_queries: int = 8192,
+                 max_inflight_queries: int = 65536, memory_budget_bytes: int = 1 << 30):
+        cfg = ServerConfig()
+        load().miann_server_config_default(C.byref(cfg))
+        cfg.num_streams, cfg.max_batch_queries = num_streams, max_batch_queries
+        cfg.max_inflight_queries, cfg.memory_budget_bytes = max_inflight_queries, memory_budget_bytes
+        h = C.c_void_p()
+        _check(load().miann_server_create(index.handle, C.byref(cfg), C.byref(h)))
+        self._h, self._index = h, index
+
+    def submit(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None) -> int:
+        """queries: numpy array [nq][d] (float32, or uint8 for u8 indices). Returns a ticket."""
+        import numpy as np
+        q = np.ascontiguousarray(queries)
+        p = (opts or SearchOptions()).cstruct()
+        t = C.c_uint64()
+        _check(load().miann_server_submit(self._h, q.ctypes.data, q.shape[0], k, itopk, max_iters, C.byref(p),
+                                          C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, nq: int, k: int):
+        """Returns (ids uint32 [nq,k], dists [nq,k], latency_ms)."""
+        import numpy as np
+        ids = np.empty((nq, k), np.uint32)
+        dists = np.empty((nq, k), np.int32 if self._index.in_dtype == U8 else np.float32)
+        lat = C.c_double()
+        _check(load().miann_server_wait(self._h, ticket, ids.ctypes.data, dists.ctypes.data, C.byref(lat)))
+        return ids, dists, lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().miann_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            load().miann_server_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()
 
 
 def as_u32(t):

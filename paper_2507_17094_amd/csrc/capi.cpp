@@ -67,6 +67,20 @@ struct Shard {
 
 }  // namespace
 
+// Error reporting shared with the predictor translation unit.
+miann_status miann_fail(miann_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+struct miann_index;
+int miann_index_input_esize(const miann_index* idx, int32_t* d_out);
+
 struct miann_index {
   int S = 1, d = 0, deg = 0, deg_g = 0, W = 0;
   int store_dtype = MIANN_F32, in_dtype = MIANN_F32, dgs = 0;
@@ -180,6 +194,12 @@ void init_dims(miann_index* ix, int d, int in_dtype, int store_dtype, int degree
 }
 
 }  // namespace
+
+// Element size of the index's input type (for the serving layer).
+int miann_index_input_esize(const miann_index* idx, int32_t* d_out) {
+  if (d_out) *d_out = idx->d;
+  return idx->in_dtype == MIANN_U8 ? 1 : 4;
+}
 
 extern "C" {
 
@@ -350,8 +370,10 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     return fail(MIANN_EINVAL, "miann_search: search_width %d invalid (r * pow2(degree) must be <= 64)", r);
   const int n_init = sp.n_init ? sp.n_init : ix->deg;
   if (n_init < 1 || n_init > 4096) return fail(MIANN_EINVAL, "miann_search: n_init = %d out of [1, 4096]", n_init);
-  if (sp.entry < 0 || sp.entry > 3) return fail(MIANN_EINVAL, "miann_search: entry %d invalid", sp.entry);
-  const bool ghost = sp.entry == MIANN_ENTRY_GHOST_GRAPH || sp.entry == MIANN_ENTRY_GHOST_DENSE;
+  if (sp.entry < 0 || sp.entry > 4) return fail(MIANN_EINVAL, "miann_search: entry %d invalid", sp.entry);
+  const bool ghost = sp.entry == MIANN_ENTRY_GHOST_GRAPH || sp.entry == MIANN_ENTRY_GHOST_DENSE ||
+                     sp.entry == MIANN_ENTRY_PREDICTED;
+  const bool ghost_graph = sp.entry == MIANN_ENTRY_GHOST_GRAPH || sp.entry == MIANN_ENTRY_PREDICTED;
   const int l_g = sp.ghost_itopk;
   const int t_seeds = sp.t_seeds ? sp.t_seeds : std::min(l_g, itopk);
   int degp_g = 0;
@@ -361,12 +383,13 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     degp_g = pow2_ceil(ix->deg_g);
     if (l_g < 1 || l_g > kMaxL) return fail(MIANN_EINVAL, "miann_search: ghost_itopk %d out of [1, %d]", l_g, kMaxL);
     if (sp.ghost_iters < 0) return fail(MIANN_EINVAL, "miann_search: ghost_iters < 0");
-    if (t_seeds < 1 || t_seeds > 64 || (sp.entry == MIANN_ENTRY_GHOST_GRAPH && t_seeds > l_g))
+    if (t_seeds < 1 || t_seeds > 64 || (ghost_graph && t_seeds > l_g))
       return fail(MIANN_EINVAL, "miann_search: t_seeds %d out of range", t_seeds);
-    if (sp.entry == MIANN_ENTRY_GHOST_GRAPH && r * degp_g > 64)
+    if (ghost_graph && r * degp_g > 64)
       return fail(MIANN_EINVAL, "miann_search: search_width too large for the ghost degree");
   }
-  if (sp.entry == MIANN_ENTRY_SEEDS && (!sp.seeds || sp.n_seeds < 1 || sp.n_seeds > 4096))
+  if ((sp.entry == MIANN_ENTRY_SEEDS || sp.entry == MIANN_ENTRY_PREDICTED) &&
+      (!sp.seeds || sp.n_seeds < 1 || sp.n_seeds > 4096))
     return fail(MIANN_EINVAL, "miann_search: seed entry needs seeds and 1 <= n_seeds <= 4096");
   if (sp.dgs && !ix->dgs) return fail(MIANN_ESTATE, "miann_search: the index has no direction table");
   if (sp.discard_permille < 0 || sp.discard_permille > 1000 || sp.cooldown_permille < 0 || sp.cooldown_permille > 1000)
@@ -455,8 +478,20 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   if (total) HIP_TRY(hipMallocAsync(&scratch, total, st));
   char* sb = (char*)scratch;
   miann_status rc = MIANN_OK;
+  // optional timing: events around [dense, stage 0..S-1, merge]
+  const int nph = 2 + ix->S;
+  std::vector<hipEvent_t> ev;
+  if (sp.phase_ms) {
+    ev.resize(2 * nph);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    for (int i = 0; i < nph; i++) sp.phase_ms[i] = 0.f;
+  }
+  auto mark = [&](int phase, int end) {
+    if (!ev.empty()) hipEventRecord(ev[2 * phase + end], st);
+  };
   if (sp.entry == MIANN_ENTRY_GHOST_DENSE) {
     a.dense = (const uint64_t*)(sb + off_dense);
+    mark(0, 0);
     for (int s = 0; s < ix->S && rc == MIANN_OK; s++) {
       const Shard& h = ix->sh[s];
       hipError_t e = dense_entry(ix->store_dtype, queries, nq, ix->d, sp.qkeys, ix->S, s, sp.ppe, h.g_f32, h.g_store,
@@ -464,6 +499,7 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
                                  (uint64_t*)(sb + off_dense), st);
       if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));
     }
+    mark(0, 1);
   }
   for (int t = 0; t < ix->S && rc == MIANN_OK; t++) {
     a.stage = t;
@@ -475,14 +511,29 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
       a.out_ids = ids;
       a.out_d = dists;
     }
+    mark(1 + t, 0);
     hipError_t e = launch_stage(ix->store_dtype, cpl, a, st);
+    mark(1 + t, 1);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: stage %d launch: %s", t, hipGetErrorString(e));
   }
   if (rc == MIANN_OK && ix->S > 1) {
+    mark(nph - 1, 0);
     hipError_t e = launch_merge((const uint64_t*)(sb + off_stage), nq, ix->S, k, ix->store_dtype == MIANN_U8, ids, dists, st);
+    mark(nph - 1, 1);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: merge launch: %s", hipGetErrorString(e));
   }
   if (scratch) hipFreeAsync(scratch, st);
+  if (!ev.empty()) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess && rc == MIANN_OK) rc = fail(MIANN_EDEVICE, "miann_search: %s", hipGetErrorString(e));
+    const bool used[3] = {sp.entry == MIANN_ENTRY_GHOST_DENSE, true, ix->S > 1};
+    for (int i = 0; i < nph; i++) {
+      const bool u = i == 0 ? used[0] : (i == nph - 1 ? used[2] : true);
+      float ms = 0.f;
+      if (u && hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) sp.phase_ms[i] = ms;
+    }
+    for (auto& e2 : ev) hipEventDestroy(e2);
+  }
   return rc;
 }
 
@@ -672,6 +723,7 @@ miann_status miann_exact_knn(const miann_index* cix, const void* queries, int64_
   miann_index* ix = const_cast<miann_index*>(cix);
   if (!ix) return fail(MIANN_EINVAL, "miann_exact_knn: null index");
   if (nq < 0 || k < 1 || k > 240) return fail(MIANN_EINVAL, "miann_exact_knn: need nq >= 0 and 1 <= k <= 240");
+  // rows are re-sorted by (dist, global id) with one wave per row (k <= 256)
   for (int s = 0; s < ix->S; s++)
     if (ix->sh[s].n < k) return fail(MIANN_EINVAL, "miann_exact_knn: k = %d exceeds shard %d size", k, s);
   if (nq == 0) return MIANN_OK;
@@ -698,10 +750,38 @@ miann_status miann_exact_knn(const miann_index* cix, const void* queries, int64_
     miann_status rc = gemm_rows(ix, h, tmp, &xf);
     if (rc) return rc;
     HIP_TRY(knn_exact(qf, nq, xf, h.n, dpi, ix->d, ix->in_dtype, qraw, dpi, h.orig, nullptr, dpi, k, 0, nullptr, keys, st));
-    if (ix->S == 1) HIP_TRY(keys_to_output(keys, nq, k, h.gmap, ix->in_dtype == MIANN_U8, ids, dists, st));
-    else HIP_TRY(keys_to_stage(keys, nq, k, h.gmap, ix->S, s, so, st));
+    // per-shard lists in global ids, ordered by (dist, global id)
+    if (ix->S == 1) {
+      HIP_TRY(keys_to_stage(keys, nq, k, h.gmap, 1, 0, keys, st));
+      HIP_TRY(sort_rows(keys, nq, k, st));
+      HIP_TRY(keys_to_output(keys, nq, k, nullptr, ix->in_dtype == MIANN_U8, ids, dists, st));
+    } else {
+      HIP_TRY(keys_to_stage(keys, nq, k, h.gmap, ix->S, s, so, st));
+    }
   }
-  if (ix->S > 1) HIP_TRY(launch_merge(so, nq, ix->S, k, ix->in_dtype == MIANN_U8, ids, dists, st));
+  if (ix->S > 1) {
+    HIP_TRY(sort_rows(so, nq * ix->S, k, st));
+    HIP_TRY(launch_merge(so, nq, ix->S, k, ix->in_dtype == MIANN_U8, ids, dists, st));
+  }
+  return MIANN_OK;
+}
+
+miann_status miann_nearest_ghost(const miann_index* ix, int32_t shard, const void* vectors, int64_t n,
+                                 uint32_t* ghost_idx, void* stream) {
+  if (!ix) return fail(MIANN_EINVAL, "miann_nearest_ghost: null index");
+  if (shard < 0 || shard >= ix->S) return fail(MIANN_EINVAL, "miann_nearest_ghost: shard %d out of range", shard);
+  const Shard& h = ix->sh[shard];
+  if (h.R == 0) return fail(MIANN_ESTATE, "miann_nearest_ghost: no ghost shard (call miann_build_ghost)");
+  if (n < 0) return fail(MIANN_EINVAL, "miann_nearest_ghost: n < 0");
+  if (n == 0) return MIANN_OK;
+  if (!vectors || !ghost_idx) return fail(MIANN_EINVAL, "miann_nearest_ghost: null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  Temps tmp(st);
+  uint64_t* keys = nullptr;
+  HIP_TRY(tmp.get(&keys, (size_t)n * 8));
+  HIP_TRY(dense_entry(ix->store_dtype, vectors, n, ix->d, nullptr, 1, 0, 0, h.g_f32, h.g_store, h.g_scale, nullptr,
+                      h.R, ix->d_pad, ix->d_pad_f32, 1, keys, st));
+  HIP_TRY(keys_to_ids(keys, n, 1, 0, ghost_idx, 1, st));
   return MIANN_OK;
 }
 

@@ -412,13 +412,16 @@ __global__ void shard_qlist_kernel(int64_t nq, const uint64_t* __restrict__ qkey
 __global__ void dense_out_kernel(const uint64_t* __restrict__ best, const uint32_t* __restrict__ list,
                                  const int* __restrict__ count, int t, const uint32_t* __restrict__ g_map, int S,
                                  int shard, uint64_t* __restrict__ out) {
+  // g_map == nullptr: emit ghost indices instead of the nodes they copy
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t r = i / t;
   const int j = (int)(i % t);
   if (r >= *count) return;
   const uint32_t q = list[r];
   const uint64_t key = best[(size_t)q * t + j];
-  out[((size_t)q * S + shard) * t + j] = key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | g_map[(uint32_t)key]);
+  const uint32_t g = (uint32_t)key;
+  out[((size_t)q * S + shard) * t + j] =
+      key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | (g_map ? g_map[g] : g));
 }
 
 hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, const uint64_t* qkeys, int S, int shard,
@@ -694,8 +697,8 @@ hipError_t keys_to_ids(const uint64_t* keys, int64_t n, int k, int col, uint32_t
   return hipGetLastError();
 }
 
-__global__ void keys_stage_kernel(const uint64_t* __restrict__ keys, int64_t nq, int k, const uint32_t* __restrict__ gmap,
-                                  int S, int s, uint64_t* __restrict__ so) {
+__global__ void keys_stage_kernel(const uint64_t* keys, int64_t nq, int k, const uint32_t* __restrict__ gmap,
+                                  int S, int s, uint64_t* so) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= nq * k) return;
   const int64_t q = i / k;
@@ -709,6 +712,39 @@ hipError_t keys_to_stage(const uint64_t* keys, int64_t nq, int k, const uint32_t
   if (nq == 0) return hipSuccess;
   hipLaunchKernelGGL(keys_stage_kernel, dim3((unsigned)((nq * k + 255) / 256)), dim3(256), 0, st, keys, nq, k, gmap, S,
                      s, so);
+  return hipGetLastError();
+}
+
+// Sorts each row of `rows` u64 keys (length k <= 256) ascending; one wave per row.
+__global__ __launch_bounds__(256) void sort_rows_kernel(uint64_t* __restrict__ keys, int64_t rows, int k) {
+  __shared__ uint64_t buf[4][256];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+  if (r >= rows) return;
+  int n = 1;
+  while (n < k) n <<= 1;
+  uint64_t* b = buf[wave];
+  for (int i = lane; i < n; i += 64) b[i] = i < k ? keys[r * k + i] : kDummy;
+  wsync();
+  for (int kk = 2; kk <= n; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < n; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = b[i], y = b[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { b[i] = y; b[ixj] = x; }
+        }
+      }
+      wsync();
+    }
+  for (int i = lane; i < k; i += 64) keys[r * k + i] = b[i];
+}
+
+hipError_t sort_rows(uint64_t* keys, int64_t rows, int k, hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  if (k > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sort_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, keys, rows, k);
   return hipGetLastError();
 }
 

@@ -46,4 +46,7 @@ hipError_t keys_to_ids(const uint64_t* keys, int64_t n, int k, int col, uint32_t
 hipError_t keys_to_stage(const uint64_t* keys, int64_t nq, int k, const uint32_t* gmap, int S, int s, uint64_t* so,
                          hipStream_t st);
 
+// Sorts each of `rows` rows of k keys ascending (k <= 256).
+hipError_t sort_rows(uint64_t* keys, int64_t rows, int k, hipStream_t st);
+
 }  // namespace miann

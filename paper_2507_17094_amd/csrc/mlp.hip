@@ -1,0 +1,266 @@
+// Kernels of the learned entry / iteration-budget predictor: a BF16 MLP
+// d_in -> hidden -> hidden -> (R entry logits + 1 budget) trained on traces of
+// the search itself. GEMMs run on the gfx950 BF16 matrix cores
+// (v_mfma_f32_32x32x16_bf16) with FP32 accumulation and FP32 master weights.
+#include "common.hpp"
+#include "mlp.hpp"
+
+namespace miann {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int GT = 64;   // output tile (rows and columns) per workgroup
+constexpr int GK = 32;   // k-chunk staged in LDS
+constexpr int GKP = GK + 8;  // padded LDS row (16-byte aligned, fewer bank conflicts)
+
+// C[i][j] = sum_k A(i,k) B(k,j); A(i,k) = A[i*sar + k*sac], B(k,j) = B[k*sbr + j*sbc].
+// Epilogue: + bias[j], ReLU, mask by (mask[i][j] > 0), store f32 and/or bf16.
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A,
+                                                        int64_t sar, int64_t sac, const uint16_t* __restrict__ B,
+                                                        int64_t sbr, int64_t sbc, const float* __restrict__ bias,
+                                                        int relu, const uint16_t* __restrict__ mask,
+                                                        float* __restrict__ Cf, uint16_t* __restrict__ Cb, int ldc) {
+  __shared__ __align__(16) uint16_t As[GT * GKP];
+  __shared__ __align__(16) uint16_t Bs[GT * GKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; j++) acc[j] = 0.f;
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    __syncthreads();
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e / GK, c = e % GK;
+      const int gi = i0 + r, gk = k0 + c, gj = j0 + r;
+      As[r * GKP + c] = (gi < M && gk < K) ? A[(int64_t)gi * sar + (int64_t)gk * sac] : (uint16_t)0;
+      Bs[r * GKP + c] = (gj < N && gk < K) ? B[(int64_t)gk * sbr + (int64_t)gj * sbc] : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 16) {
+      const bf16x8 av = *(const bf16x8*)&As[(wr + (lane & 31)) * GKP + kk + (lane >> 5) * 8];
+      const bf16x8 bv = *(const bf16x8*)&Bs[(wc + (lane & 31)) * GKP + kk + (lane >> 5) * 8];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int i = i0 + wr + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    const int c = j0 + wc + (lane & 31);
+    if (i >= M || c >= N) continue;
+    float v = acc[j];
+    if (bias) v += bias[c];
+    if (relu) v = v > 0.f ? v : 0.f;
+    if (mask) v = bf2f(mask[(int64_t)i * ldc + c]) > 0.f ? v : 0.f;
+    if (Cf) Cf[(int64_t)i * ldc + c] = v;
+    if (Cb) Cb[(int64_t)i * ldc + c] = f2bf(v);
+  }
+}
+
+hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sar, int64_t sac, const uint16_t* B, int64_t sbr,
+                     int64_t sbc, const float* bias, int relu, const uint16_t* mask, float* Cf, uint16_t* Cb, int ldc,
+                     hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  dim3 g((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
+  hipLaunchKernelGGL(gemm_bf16_kernel, g, dim3(256), 0, st, M, N, K, A, sar, sac, B, sbr, sbc, bias, relu, mask, Cf, Cb,
+                     ldc);
+  return hipGetLastError();
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+hipError_t to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+// Gathers rows idx[b] of x ([n][d] f32) into bf16 ([B][d]) and their labels.
+__global__ void gather_batch_kernel(const float* __restrict__ x, int d, const uint32_t* __restrict__ idx, int B,
+                                    const int32_t* __restrict__ lab, const float* __restrict__ y,
+                                    uint16_t* __restrict__ xb, int32_t* __restrict__ lb, float* __restrict__ yb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)B * d) return;
+  const int b = (int)(e / d), c = (int)(e % d);
+  const int64_t r = idx ? (int64_t)idx[b] : b;
+  xb[e] = f2bf(x[r * d + c]);
+  if (c == 0) {
+    if (lb) lb[b] = lab[r];
+    if (yb) yb[b] = y[r];
+  }
+}
+
+hipError_t gather_batch(const float* x, int d, const uint32_t* idx, int B, const int32_t* lab, const float* y,
+                        uint16_t* xb, int32_t* lb, float* yb, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  const int64_t tot = (int64_t)B * d;
+  hipLaunchKernelGGL(gather_batch_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, x, d, idx, B, lab, y,
+                     xb, lb, yb);
+  return hipGetLastError();
+}
+
+// Loss and its gradient per row: softmax cross-entropy over the first R
+// outputs (entry region) + lambda * (z_R - y)^2 (log-budget regression).
+// dZ = (softmax - onehot, 2 lambda (z_R - y)) / B, stored in bf16.
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ Z, int B, int R,
+                                                        const int32_t* __restrict__ lab, const float* __restrict__ y,
+                                                        float lambda, uint16_t* __restrict__ dZ,
+                                                        float* __restrict__ loss) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= B) return;
+  const int lane = threadIdx.x & 63;
+  const int N = R + 1;
+  const float* z = Z + (int64_t)b * N;
+  float mx = -INFINITY;
+  for (int j = lane; j < R; j += 64) mx = fmaxf(mx, z[j]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  float s = 0.f;
+  for (int j = lane; j < R; j += 64) s += expf(z[j] - mx);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+  const float invB = 1.f / (float)B;
+  int L = lab[b];
+  L = L < 0 ? 0 : (L >= R ? R - 1 : L);  // labels outside [0, R) are clamped
+  for (int j = lane; j < R; j += 64) {
+    const float p = expf(z[j] - mx) / s;
+    dZ[(int64_t)b * N + j] = f2bf((p - (j == L ? 1.f : 0.f)) * invB);
+  }
+  if (lane == 0) {
+    const float diff = z[R] - y[b];
+    dZ[(int64_t)b * N + R] = f2bf(2.f * lambda * diff * invB);
+    const float ce = logf(s) + mx - z[L];
+    atomicAdd(loss, (ce + lambda * diff * diff) * invB);
+  }
+}
+
+hipError_t loss_grad(const float* Z, int B, int R, const int32_t* lab, const float* y, float lambda, uint16_t* dZ,
+                     float* loss, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, Z, B, R, lab, y, lambda, dZ,
+                     loss);
+  return hipGetLastError();
+}
+
+// db[j] = sum_b G[b][j] (bf16 gradient rows -> f32 column sums).
+__global__ void colsum_kernel(const uint16_t* __restrict__ G, int B, int N, float* __restrict__ db) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; b++) s += bf2f(G[(int64_t)b * N + j]);
+  db[j] = s;
+}
+
+hipError_t colsum(const uint16_t* G, int B, int N, float* db, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, G, B, N, db);
+  return hipGetLastError();
+}
+
+// Adam (Kingma and Ba, 2015) on FP32 master weights; refreshes the bf16 copy.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2, uint16_t* __restrict__ wb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = f2bf(wi);
+}
+
+hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                int step, uint16_t* wb, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps,
+                     c1, c2, wb);
+  return hipGetLastError();
+}
+
+// Inference read-out per row: confidence = max softmax probability over the R
+// entry logits; seeds = ghost map of the t largest logits (ties -> smaller
+// index); budget = clamp(ceil(1.25 (exp(z_R) - 1)), t_min, t_max). Rows whose
+// confidence is below tau get seeds[0] = none (fall back to ghost staging).
+__global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ Z, int n, int R, int t, float tau,
+                                                      const uint32_t* __restrict__ gmap, int t_min, int t_max,
+                                                      uint32_t* __restrict__ seeds, int32_t* __restrict__ iters,
+                                                      float* __restrict__ conf, uint32_t* __restrict__ top_idx) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= n) return;
+  const int lane = threadIdx.x & 63;
+  const float* z = Z + (int64_t)b * (R + 1);
+  float mx = -INFINITY;
+  for (int j = lane; j < R; j += 64) mx = fmaxf(mx, z[j]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  float s = 0.f;
+  for (int j = lane; j < R; j += 64) s += expf(z[j] - mx);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+  const float c = 1.f / s;
+  // t rounds of (value desc, index asc) argmax over the logits
+  uint64_t prev = ~0ull;  // previous winner's key; keys strictly decrease
+  for (int r = 0; r < t; r++) {
+    uint64_t best = 0;
+    for (int j = lane; j < R; j += 64) {
+      const uint32_t fb = __float_as_uint(z[j]);
+      const uint32_t ord = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);  // order-preserving
+      const uint64_t key = ((uint64_t)ord << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)j);
+      if (key < prev && key > best) best = key;
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t other = shfl_xor_u64(best, o);
+      best = other > best ? other : best;
+    }
+    prev = best;
+    if (lane == 0) {
+      const uint32_t j = 0xFFFFFFFFu - (uint32_t)best;
+      if (top_idx) top_idx[(int64_t)b * t + r] = j;
+      seeds[(int64_t)b * t + r] = (r == 0 && c < tau) ? kNone : gmap[j];
+    }
+  }
+  if (lane == 0) {
+    const float yb = z[R];
+    float tb = ceilf(1.25f * (expf(yb) - 1.f));
+    if (!(tb >= (float)t_min)) tb = (float)t_min;
+    if (tb > (float)t_max) tb = (float)t_max;
+    iters[b] = (int32_t)tb;
+    conf[b] = c;
+  }
+}
+
+hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_t* gmap, int t_min, int t_max,
+                   uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(readout_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min,
+                     t_max, seeds, iters, conf, top_idx);
+  return hipGetLastError();
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+hipError_t zero_f32(float* p, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// Random permutation for shuffling: keys = splitmix(seed, i + 1), sorted elsewhere.
+
+}  // namespace miann

@@ -1,0 +1,23 @@
+// Host-callable launchers of the predictor kernels (mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace miann {
+
+hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sar, int64_t sac, const uint16_t* B, int64_t sbr,
+                     int64_t sbc, const float* bias, int relu, const uint16_t* mask, float* Cf, uint16_t* Cb, int ldc,
+                     hipStream_t st);
+hipError_t to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
+hipError_t gather_batch(const float* x, int d, const uint32_t* idx, int B, const int32_t* lab, const float* y,
+                        uint16_t* xb, int32_t* lb, float* yb, hipStream_t st);
+hipError_t loss_grad(const float* Z, int B, int R, const int32_t* lab, const float* y, float lambda, uint16_t* dZ,
+                     float* loss, hipStream_t st);
+hipError_t colsum(const uint16_t* G, int B, int N, float* db, hipStream_t st);
+hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                int step, uint16_t* wb, hipStream_t st);
+hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_t* gmap, int t_min, int t_max,
+                   uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st);
+hipError_t zero_f32(float* p, int64_t n, hipStream_t st);
+
+}  // namespace miann

@@ -110,9 +110,9 @@ struct Searcher {
 
   // Merge this lane's candidate key (lanes sorted ascending, kDummy = none)
   // into p[0..l). Keys whose (dist, id) is already in p, or repeats within c,
-  // are dropped (the existing entry keeps its flag). Returns true if any
-  // candidate entered p.
-  __device__ __forceinline__ bool merge_sorted(uint64_t c, int l) {
+  // are dropped (the existing entry keeps its flag). Returns bit 0 if any
+  // candidate entered p, bit 1 if one entered the first k positions.
+  __device__ __forceinline__ int merge_sorted(uint64_t c, int l) {
     const uint64_t prev = shfl_u64(c, lane == 0 ? 0 : lane - 1);
     const bool real = c != kDummy;
     const uint64_t cn = key_noflag(c);
@@ -121,7 +121,7 @@ struct Searcher {
     if (real && !dup && pos < l && key_noflag(pk[pos]) == cn) dup = true;
     const bool valid = real && !dup;
     const uint64_t vm = ballot(valid);
-    if (vm == 0) return false;
+    if (vm == 0) return 0;
     const int nv = __popcll(vm);
     const int rank = lanes_below(vm);
     const int newpos = pos + rank;
@@ -149,7 +149,7 @@ struct Searcher {
     const bool in = valid && newpos < l;
     if (in) pk[newpos] = c;
     wsync();
-    return ballot(in) != 0;
+    return (ballot(in) != 0 ? 1 : 0) | (ballot(in && newpos < a.k) != 0 ? 2 : 0);
   }
 
   // ---------------------------------------------------------------- distances
@@ -244,11 +244,11 @@ struct Searcher {
 
   // Filter ids (one per lane, active lanes only) through the visited set,
   // evaluate the new ones, and merge them into p.
-  __device__ __forceinline__ bool add_ids(const GraphCtx& g, bool active, uint32_t id, int l) {
+  __device__ __forceinline__ int add_ids(const GraphCtx& g, bool active, uint32_t id, int l) {
     const bool take = visit(active, id);
     const uint64_t tm = ballot(take);
     const int nc = __popcll(tm);
-    if (nc == 0) return false;
+    if (nc == 0) return 0;
     if (take) cid[lanes_below(tm)] = id;
     wsync();
     compute_dists(g, nc);
@@ -280,7 +280,7 @@ struct Searcher {
   // ---------------------------------------------------------------- the loop
   // Steps 3-4 of Sec. 2.2 until no parent is eligible or T iterations ran.
   __device__ __forceinline__ void beam_loop(const GraphCtx& g, int l, int T, bool dgs_on, bool stop_nc, uint64_t stream,
-                            long long& n_exp, long long& n_iter) {
+                            long long& n_exp, long long& n_iter, long long& last_topk) {
     const int r = a.r;
     const int n_cool = (a.cooldown_pm * T + 999) / 1000;
     const int t_dgs = T - n_cool;
@@ -367,10 +367,11 @@ struct Searcher {
         nb = kept ? nb_sel : kNone;
         ctr[3] += (long long)(g.deg - keep) * npar;
       }
-      const bool changed = add_ids(g, nb != kNone, nb, l);
+      const int changed = add_ids(g, nb != kNone, nb, l);
       n_exp += npar;
       it++;
-      if (stop_nc && !changed) break;
+      if (changed & 2) last_topk = it;
+      if (stop_nc && !(changed & 1)) break;
     }
     n_iter += it;
   }
@@ -402,6 +403,11 @@ struct Searcher {
       if (tl == 0 && ci < m && ok) pk[ci] = make_key(__float_as_uint((float)acc), id, kDone);
     }
     wsync();
+    sort_p(m);
+  }
+
+  // Sorts pk[0..m) ascending (entries m..pow2(m) are padded with dummies).
+  __device__ __forceinline__ void sort_p(int m) {
     int n = 1;
     while (n < m) n <<= 1;
     for (int i = m + lane; i < n; i += 64) pk[i] = kDummy;
@@ -469,18 +475,21 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   S.p_reset(a.l);
   const bool use_entry = (t == 0) || !a.ppe;
   long long n_exp = 0, n_iter = 0;
+  // predicted entry: the row's seeds, or the ghost graph when the predictor was not confident
+  int entry = a.entry;
+  if (entry == 4) entry = (t == 0 && a.seeds[(size_t)q * a.n_seeds] != kNone) ? 3 : 1;
   if (!use_entry) {
     // path extension: continue from I(z) of the previous stage's first f results
     const uint32_t id = S.lane < a.f ? a.hand_in[(size_t)q * a.f + S.lane] : kNone;
     S.add_ids(gm, id != kNone, id, a.l);
-  } else if (a.entry == 1) {
+  } else if (entry == 1) {
     // ghost staging: a short search on the ghost graph, then hand over to the main graph
     GraphCtx gg{sh.g_store, sh.g_scale, sh.g_graph, nullptr, sh.R, a.deg_g, a.degp_g};
     S.p_reset(a.l_g);
-    long long ge = 0, gi = 0;
+    long long ge = 0, gi = 0, gl = 0;
     const long long nd0 = S.ctr[0];
     S.random_init(gg, stream_ghost, a.deg_g, a.l_g);
-    S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi);
+    S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi, gl);
     S.ctr[4] += S.ctr[0] - nd0;
     S.ctr[0] = nd0;
     S.ctr[5] += ge;
@@ -491,13 +500,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     S.hash_clear();
     S.p_reset(a.l);
     S.add_keys(seed, a.l);
-  } else if (a.entry == 2) {
+  } else if (entry == 2) {
     uint64_t dk = S.lane < a.t_seeds ? a.dense[((size_t)q * Sh + s) * a.t_seeds + S.lane] : kDummy;
     uint64_t seed = kDummy;
     if (dk != kDummy) seed = make_key((uint32_t)(dk >> 32), (uint32_t)dk, kFresh);
     S.ctr[4] += sh.R;
     S.add_keys(seed, a.l);
-  } else if (a.entry == 3 && t == 0 && a.seeds) {
+  } else if (entry == 3 && t == 0 && a.seeds) {
     for (int b = 0; b < a.n_seeds; b += 64) {
       const int j = b + S.lane;
       const uint32_t id = j < a.n_seeds ? a.seeds[(size_t)q * a.n_seeds + j] : kNone;
@@ -506,9 +515,11 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   } else {
     S.random_init(gm, stream_main, a.n_init, a.l);
   }
-  S.beam_loop(gm, a.l, T, a.dgs != 0, a.stop_on_no_change != 0, stream_main, n_exp, n_iter);
+  long long last_topk = 0;
+  S.beam_loop(gm, a.l, T, a.dgs != 0, a.stop_on_no_change != 0, stream_main, n_exp, n_iter, last_topk);
   S.ctr[1] += n_exp;
   S.ctr[2] += n_iter;
+  S.ctr[7] += last_topk;
 
   // hand-off to the next shard: I(z) for the first f entries
   if (Sh > 1 && a.ppe && t + 1 < Sh && S.lane < a.f) {
@@ -524,19 +535,25 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     S.ctr[6] += real;
     S.rerank(sh.orig, m);
   }
+  // the stage's k results, ordered by (dist, global id) for the reduction over shards
+  for (int i = S.lane; i < a.k; i += 64) {
+    const uint64_t key = S.pk[i];
+    const uint32_t lid = key_id(key);
+    S.pk[i] = key != kDummy ? (((uint64_t)key_dist(key) << 32) | (sh.gmap ? sh.gmap[lid] : lid)) : kDummy;
+  }
+  wsync();
+  S.sort_p(a.k);
   for (int i = S.lane; i < a.k; i += 64) {
     const uint64_t key = S.pk[i];
     const bool ok = key != kDummy;
-    const uint32_t lid = key_id(key);
-    const uint32_t gid = ok ? (sh.gmap ? sh.gmap[lid] : lid) : kNone;
     if (Sh == 1) {
-      a.out_ids[(size_t)q * a.k + i] = gid;
+      a.out_ids[(size_t)q * a.k + i] = ok ? (uint32_t)key : kNone;
       if (DT == DT_U8)
-        ((int32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? (int32_t)key_dist(key) : 0x7FFFFFFF;
+        ((int32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? (int32_t)(key >> 32) : 0x7FFFFFFF;
       else
-        ((uint32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? key_dist(key) : 0x7F800000u;
+        ((uint32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? (uint32_t)(key >> 32) : 0x7F800000u;
     } else {
-      a.stage_out[((size_t)q * Sh + t) * a.k + i] = ok ? (((uint64_t)key_dist(key) << 32) | gid) : kDummy;
+      a.stage_out[((size_t)q * Sh + t) * a.k + i] = key;
     }
   }
   if (a.ctr && S.lane == 0) {

@@ -80,7 +80,11 @@ def run_both(ox, gx, Q: np.ndarray, k, itopk, T, opts: miann.SearchOptions, qkey
     return g, o
 
 
-def compare(g, o, min_frac=0.999, check_counters=True, label=""):
+def ghost_entry(opts) -> bool:
+    return opts.entry in ("ghost_graph", "ghost_dense", "predicted")
+
+
+def compare(g, o, min_frac=0.999, check_counters=True, label="", ndist_check=True):
     """Element-wise parity. Returns the fraction of queries whose id lists match."""
     gi, gd, gc = g
     oi, od, oc = o
@@ -99,7 +103,10 @@ def compare(g, o, min_frac=0.999, check_counters=True, label=""):
     if check_counters:
         # expansions, iterations, skipped slots, ghost expansions and rerank counts are
         # determined by the search path alone; distance counts depend on the visited hash
-        for c in (1, 2, 3, 5, 6):
+        for c in (1, 2, 3, 5, 6, 7):
             assert np.array_equal(gc[same, c], oc[same, c]), f"{label}: counter {c} differs"
-        assert np.all(gc[same, 0] >= oc[same, 0])
+        if ndist_check:
+            # the device reuses the distances of ghost seeds; otherwise it evaluates at least
+            # what the exact visited set evaluates
+            assert np.all(gc[same, 0] >= oc[same, 0])
     return frac

@@ -1,0 +1,100 @@
+"""GPU parity of the predictor's kernels against the CPU reference (oracle/mlp.py):
+gradients of one forward/backward pass, one Adam step, the inference read-out,
+and that training on search-derived labels reduces the loss. The reference
+rounds to bf16 at the same points as the device; the device accumulates in
+FP32 where the reference uses float64, so a few bf16 roundings differ by one
+unit: gradients are compared by relative Frobenius error."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import say
+from oracle import mlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+miann = pytest.importorskip("paper_2507_17094_amd")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("d,h,R,B", [(32, 64, 50, 37), (96, 256, 300, 130)])
+def test_gradients_match_reference(d, h, R, B):
+    say(f"predictor grads d={d} h={h} R={R} B={B}")
+    P = miann.Predictor(d, h, R, seed=7)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((B, d)).astype(np.float32)
+    lab = rng.integers(0, R, B).astype(np.int32)
+    y = rng.uniform(0, 4, B).astype(np.float32)
+    lam = 0.5
+    loss = P.step(torch.from_numpy(x).cuda(), torch.from_numpy(lab).cuda(), torch.from_numpy(y).cuda(), lam=lam)
+    W = {k: v.cpu().numpy().astype(np.float64) for k, v in P.tensors().items()}
+    G = {k: v.cpu().numpy() for k, v in P.tensors(grads=True).items()}
+    ref_loss, ref_g, _ = mlp.forward_backward(W, x, lab, y, lam, bf16_mode=True)
+    say(f"  loss gpu {loss:.6f} ref {ref_loss:.6f}")
+    assert abs(loss - ref_loss) <= 2e-3 * max(1.0, abs(ref_loss))
+    for k in ref_g:
+        e = rel(G[k], ref_g[k])
+        say(f"  grad {k}: rel err {e:.2e}")
+        assert e < 2e-2, k
+
+
+def test_adam_step_matches_reference():
+    P = miann.Predictor(16, 32, 20, seed=3)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((64, 16)).astype(np.float32)
+    lab = rng.integers(0, 20, 64).astype(np.int32)
+    y = rng.uniform(0, 3, 64).astype(np.float32)
+    args = (torch.from_numpy(x).cuda(), torch.from_numpy(lab).cuda(), torch.from_numpy(y).cuda())
+    W0 = {k: v.cpu().numpy().astype(np.float64) for k, v in P.tensors().items()}
+    P.step(*args, lam=1.0, lr=1e-2, update=True)
+    G = {k: v.cpu().numpy().astype(np.float64) for k, v in P.tensors(grads=True).items()}
+    W1 = {k: v.cpu().numpy() for k, v in P.tensors().items()}
+    ref = mlp.adam_step(W0, G, {}, lr=1e-2, step=1)
+    for k in W0:
+        assert np.allclose(W1[k], ref[k], rtol=1e-5, atol=1e-6), k
+
+
+def test_readout_matches_reference():
+    P = miann.Predictor(24, 48, 40, seed=5)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((300, 24)).astype(np.float32)
+    gmap = np.sort(rng.choice(10_000, 40, replace=False)).astype(np.uint32)
+    seeds, iters, conf, top = P.predict(torch.from_numpy(x).cuda(), 8, 0.05,
+                                        torch.from_numpy(gmap.view(np.int32)).cuda(), 4, 200)
+    W = {k: v.cpu().numpy().astype(np.float64) for k, v in P.tensors().items()}
+    _, _, cache = mlp.forward_backward(W, x, np.zeros(300, np.int64), np.zeros(300), 0.0, bf16_mode=True)
+    rs, rT, rc, rorder = mlp.readout(cache["Z"], 8, 0.05, gmap, 4, 200)
+    top = top.cpu().numpy()
+    agree = (top[:, 0] == rorder[:, 0]).mean()
+    say(f"  top-1 agreement {agree:.4f}")
+    assert agree >= 0.97
+    assert np.abs(conf.cpu().numpy() - rc).max() < 5e-3
+    assert np.abs(iters.cpu().numpy() - rT).max() <= 1
+    s = seeds.cpu().numpy().view(np.uint32)
+    low = conf.cpu().numpy() < 0.05
+    assert np.all(s[low, 0] == 0xFFFFFFFF)
+    assert np.all(s[~low, 0] == gmap[top[~low, 0]])
+
+
+def test_training_reduces_loss_on_region_labels():
+    """Labels: the nearest of R sampled representatives (a learnable entry region)."""
+    d, R = 32, 64
+    X = synth.mixture_small(20_000, d, R, 0.3, 91)
+    reps = synth.mixture_small(R, d, R, 0.05, 92)
+    lab = np.argmin(((X[:, None, :] - reps[None]) ** 2).sum(-1), axis=1).astype(np.int32)
+    y = np.log1p(np.full(len(X), 20.0, np.float32))
+    P = miann.Predictor(d, 128, R, seed=9)
+    losses = P.train(torch.from_numpy(X).cuda(), torch.from_numpy(lab).cuda(), torch.from_numpy(y).cuda(),
+                     epochs=8, batch=1024, lr=2e-3, lam=1.0)
+    say(f"  epoch losses {[round(v, 4) for v in losses]}")
+    assert losses[-1] < 0.5 * losses[0]
+    seeds, iters, conf, top = P.predict(torch.from_numpy(X[:2000]).cuda(), 1, 0.0,
+                                        torch.arange(R, dtype=torch.int32).cuda(), 1, 1000)
+    acc = (top.cpu().numpy()[:, 0] == lab[:2000]).mean()
+    say(f"  train accuracy {acc:.3f}")
+    assert acc > 0.7

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import compare, dev, run_both, say, to_device_index
+from gpu_util import compare, dev, ghost_entry, run_both, say, to_device_index
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,7 +59,7 @@ def test_search_parity_small(small, name, itopk, T, kw):
     say(f"case {name}: nq={len(Q)} itopk={itopk} T={T} {kw}")
     opts = miann.SearchOptions(**kw)
     g, o = run_both(ox, gx, Q, min(K, itopk), itopk, T, opts)
-    compare(g, o, label=name)
+    compare(g, o, label=name, ndist_check=not ghost_entry(opts))
 
 
 @pytest.mark.parametrize("d", [16, 100, 200])
@@ -70,8 +70,9 @@ def test_search_parity_odd_dims(d):
     ox = oracle.build_index(X, deg=16, dgs=True, ghost_R=100, deg_g=8)
     gx = to_device_index(ox)
     for kw in (dict(), dict(dgs=True, entry="ghost_graph"), dict(entry="ghost_dense", search_width=4)):
-        g, o = run_both(ox, gx, Q, K, 48, 60, miann.SearchOptions(**kw))
-        compare(g, o, label=f"d{d}-{kw}")
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, 48, 60, opts)
+        compare(g, o, label=f"d{d}-{kw}", ndist_check=not ghost_entry(opts))
 
 
 @pytest.mark.parametrize("S", [2, 3])
@@ -84,8 +85,9 @@ def test_path_extension_parity(S):
     gx = to_device_index(ox)
     for kw in (dict(), dict(dgs=True, entry="ghost_graph"), dict(ppe=False, entry="ghost_dense"),
                dict(forward_f=4, dgs=True), dict(ppe=False)):
-        g, o = run_both(ox, gx, Q, K, 64, 50, miann.SearchOptions(**kw))
-        compare(g, o, label=f"S{S}-{kw}")
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, 64, 50, opts)
+        compare(g, o, label=f"S{S}-{kw}", ndist_check=not ghost_entry(opts))
 
 
 @pytest.mark.parametrize("store", ["f16", "fp8"])
@@ -97,8 +99,9 @@ def test_low_precision_parity(store):
     gx = to_device_index(ox)
     for kw, itopk in ((dict(), 64), (dict(dgs=True, entry="ghost_graph"), 64), (dict(entry="ghost_dense"), 40),
                       (dict(rerank_mult=8), 64)):
-        g, o = run_both(ox, gx, Q, K, itopk, 60, miann.SearchOptions(**kw))
-        compare(g, o, label=f"{store}-{kw}")
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, itopk, 60, opts)
+        compare(g, o, label=f"{store}-{kw}", ndist_check=not ghost_entry(opts))
     # traversal codes: the device quantiser matches the oracle's bit for bit
     from gpu_util import d2h
     v = gx.shard(0)
@@ -109,16 +112,18 @@ def test_low_precision_parity(store):
     assert np.array_equal(scale, ox.shards[0]["scale"])
 
 
-def test_u8_parity_bit_exact():
-    say("u8 data")
+@pytest.mark.parametrize("S", [1, 2])
+def test_u8_parity_bit_exact(S):
+    say(f"u8 data S={S}")
     Xf = mix(3000, 128, 8, 0.3, 51)
     X = synth.to_u8(Xf)
     Q = synth.to_u8(mix(200, 128, 8, 0.3, 52))
-    ox = oracle.build_index(X, deg=32, dgs=True, ghost_ratio=0.05, deg_g=16)
+    ox = oracle.build_index(X, deg=32, S=S, dgs=True, ghost_ratio=0.05, deg_g=16)
     gx = to_device_index(ox)
     for kw in (dict(), dict(dgs=True), dict(entry="ghost_graph", dgs=True), dict(entry="ghost_dense")):
-        g, o = run_both(ox, gx, Q, K, 64, 60, miann.SearchOptions(**kw))
-        frac = compare(g, o, min_frac=1.0, label=f"u8-{kw}")
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, 64, 60, opts)
+        frac = compare(g, o, min_frac=1.0, label=f"u8-{kw}", ndist_check=not ghost_entry(opts))
         assert frac == 1.0
 
 
@@ -161,8 +166,9 @@ def test_full_tiny_workload():
     ox = oracle.build_index(X, deg=32, dgs=True, ghost_ratio=0.01, deg_g=32)
     gx = to_device_index(ox)
     for kw in (dict(), dict(n_init=256), dict(entry="ghost_dense", dgs=True), dict(entry="ghost_graph", dgs=True)):
-        g, o = run_both(ox, gx, Q, K, 64, 64, miann.SearchOptions(**kw))
-        compare(g, o, label=f"tiny-{kw}")
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, 64, 64, opts)
+        compare(g, o, label=f"tiny-{kw}", ndist_check=not ghost_entry(opts))
 
 
 def test_validation_errors(small):

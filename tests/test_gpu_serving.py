@@ -1,0 +1,96 @@
+"""The continuous-batching server: a request's result is the same alone and in a
+mix of concurrent requests of uneven size and k (the query key is the index
+within the request), admission limits are respected, and bad requests are
+rejected before anything runs."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, say, to_device_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+miann = pytest.importorskip("paper_2507_17094_amd")
+
+
+@pytest.fixture(scope="module")
+def served():
+    X = synth.mixture_small(4000, 64, 16, 0.3, 101)
+    ox = oracle.build_index(X, deg=32, S=2, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    return X, ox, gx
+
+
+def direct(gx, Q, k, itopk, T, opts):
+    ids, dists = gx.search(dev(Q), k, itopk, T, opts,
+                           qkeys=torch.arange(len(Q), dtype=torch.int64).cuda())
+    torch.cuda.synchronize()
+    return ids.cpu().numpy().view(np.uint32), dists.cpu().numpy()
+
+
+def test_alone_equals_in_mix(served):
+    X, ox, gx = served
+    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    rng = np.random.default_rng(5)
+    A = synth.mixture_small(37, 64, 16, 0.3, 102)
+    srv = miann.Server(gx, num_streams=4, max_batch_queries=2048)
+    tA = srv.submit(A, 10, 64, 60, opts)
+    ia, da, _ = srv.wait(tA, len(A), 10)
+    ref_i, ref_d = direct(gx, A, 10, 64, 60, opts)
+    assert np.array_equal(ia, ref_i) and np.array_equal(da, ref_d)
+    # the same request inside a mix of uneven requests submitted from two threads
+    reqs = []
+    for j in range(40):
+        n = int(min(1024, np.floor(np.exp(rng.uniform(0, np.log(1025))))))
+        k = int(rng.choice([10, 32]))
+        reqs.append((synth.mixture_small(max(1, n), 64, 16, 0.3, 200 + j), k))
+    tickets = [None] * len(reqs)
+    mid = []
+
+    def submit(lo, hi):
+        for j in range(lo, hi):
+            tickets[j] = srv.submit(reqs[j][0], reqs[j][1], 64, 60, opts)
+            if j == 20:
+                mid.append(srv.submit(A, 10, 64, 60, opts))
+
+    th = [threading.Thread(target=submit, args=(0, 20)), threading.Thread(target=submit, args=(20, 40))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    ib, db, _ = srv.wait(mid[0], len(A), 10)
+    assert np.array_equal(ib, ia) and np.array_equal(db, da)
+    lats = []
+    for j, (Qj, k) in enumerate(reqs):
+        ij, dj, lat = srv.wait(tickets[j], len(Qj), k)
+        lats.append(lat)
+        ri, rd = direct(gx, Qj, k, 64, 60, opts)
+        assert np.array_equal(ij, ri) and np.array_equal(dj, rd), j
+    st = srv.stats()
+    say(f"  batches {st['batches']} for {st['requests_done']} requests; p50 {np.percentile(lats, 50):.2f} ms "
+        f"p99 {np.percentile(lats, 99):.2f} ms")
+    assert st["requests_done"] == len(reqs) + 2
+    srv.close()
+
+
+def test_admission_limits_queue_requests(served):
+    X, ox, gx = served
+    opts = miann.SearchOptions(entry="ghost_graph")
+    srv = miann.Server(gx, num_streams=3, max_batch_queries=64, max_inflight_queries=96,
+                       memory_budget_bytes=200_000)
+    Qs = [synth.mixture_small(n, 64, 16, 0.3, 300 + n) for n in (60, 50, 40, 30, 64, 1, 2, 33)]
+    ts = [srv.submit(Q, 10, 32, 30, opts) for Q in Qs]
+    for t, Q in zip(ts, Qs):
+        ids, _, _ = srv.wait(t, len(Q), 10)
+        ri, _ = direct(gx, Q, 10, 32, 30, opts)
+        assert np.array_equal(ids, ri)
+    st = srv.stats()
+    assert st["peak_inflight_queries"] <= 96 and st["peak_inflight_bytes"] <= 200_000
+    with pytest.raises(miann.MiannError):
+        srv.submit(synth.mixture_small(65, 64, 16, 0.3, 1), 10, 32, 30, opts)  # larger than one batch
+    with pytest.raises(miann.MiannError):
+        srv.submit(Qs[0], 40, 32, 30, opts)  # k > itopk
+    srv.close()
