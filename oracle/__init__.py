@@ -67,7 +67,7 @@ class Params(C.Structure):
                 ("dgs_on", C.c_int32), ("discard_pm", C.c_int32), ("cooldown_pm", C.c_int32),
                 ("random_discard", C.c_int32), ("ppe_on", C.c_int32), ("forward_f", C.c_int32),
                 ("rerank_mult", C.c_int32), ("visited_policy", C.c_int32), ("stop_on_no_change", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("ghost_every_stage", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -362,7 +362,7 @@ def build_index(X: np.ndarray, deg: int, S: int = 1, seed: int = 5, store: str |
 
 DEFAULTS = dict(k=10, l=64, r=1, T=64, n_init=None, entry="random", l_g=32, T_g=8, t_seeds=None,
                 dgs_on=False, discard=0.5, cooldown=0.3, random_discard=False, ppe_on=True, forward_f=1,
-                rerank_mult=4, visited="exact", stop_on_no_change=False, seed=6)
+                rerank_mult=4, visited="exact", stop_on_no_change=False, ghost_every_stage=False, seed=6)
 
 
 def make_params(ix: OracleIndex, **kw) -> Params:
@@ -381,6 +381,7 @@ def make_params(ix: OracleIndex, **kw) -> Params:
     p.ppe_on, p.forward_f, p.rerank_mult = int(bool(o["ppe_on"])), o["forward_f"], o["rerank_mult"]
     p.visited_policy = VISITED[o["visited"]]
     p.stop_on_no_change = int(bool(o["stop_on_no_change"]))
+    p.ghost_every_stage = int(bool(o["ghost_every_stage"]))
     p.seed = o["seed"] & (2**64 - 1)
     return p
 
@@ -410,12 +411,15 @@ def search(ix: OracleIndex, Q: np.ndarray, qkeys: np.ndarray | None = None, seed
 
 
 def brute_force_numpy(base: np.ndarray, Q: np.ndarray, k: int):
-    """Textbook brute force with numpy (independent of oracle.c): exact squared L2 in float64,
-    ordered by (dist, id). Only for tiny inputs."""
-    b = base.astype(np.float64)
-    q = Q.astype(np.float64)
-    D = ((q[:, None, :] - b[None, :, :]) ** 2).sum(-1)
+    """Textbook brute force with numpy (independent of oracle.c): squared L2 of the float
+    differences (squares summed in float64; exact integers for uint8), ordered by (dist, id).
+    Only for tiny inputs."""
+    if base.dtype == np.uint8:
+        D = ((Q[:, None, :].astype(np.int64) - base[None, :, :].astype(np.int64)) ** 2).sum(-1).astype(np.float64)
+    else:
+        diff = Q[:, None, :].astype(np.float32) - base[None, :, :].astype(np.float32)
+        D = (diff.astype(np.float64) ** 2).sum(-1)
     out = np.empty((Q.shape[0], k), np.int64)
     for i in range(Q.shape[0]):
-        out[i] = np.lexsort((np.arange(b.shape[0]), D[i]))[:k]
+        out[i] = np.lexsort((np.arange(base.shape[0]), D[i]))[:k]
     return out, D

@@ -18,8 +18,9 @@
  *
  * Readings of points the paper leaves open (all documented in the design notes):
  *   - distances are SQUARED L2 (monotone in Eq. 2, so ranks are unchanged);
- *     float inputs accumulate (q_i - x_i)^2 in double in index order and round
- *     once to float; uint8 inputs use exact integer arithmetic.
+ *     float inputs: each difference q_i - x_i is rounded to float, its square
+ *     (exact in double) is summed in double in index order, and the sum is
+ *     rounded once to float; uint8 inputs use exact integer arithmetic.
  *   - every ordering is by the key (dist, id), ascending, id unsigned.
  *   - parents are the first r *unexpanded* entries of p; the search stops when
  *     no entry is eligible or after T iterations.
@@ -187,9 +188,9 @@ static inline float elem(const orc_store* st, int64_t v, int i) {
   }
 }
 
-/* dist(q, x_v) = sum_i (q_i - x_v,i)^2. Float: double accumulation in index
- * order, rounded once to float. uint8: exact integer. Returned as double,
- * which holds either result exactly. */
+/* dist(q, x_v) = sum_i (q_i - x_v,i)^2. Float: the float differences, squared
+ * exactly and summed in double in index order, rounded once to float. uint8:
+ * exact integer. Returned as double, which holds either result exactly. */
 static double dist_qv(const orc_store* st, const void* q, int64_t v) {
   const int d = st->d;
   if (st->dtype == DT_U8) {
@@ -202,8 +203,8 @@ static double dist_qv(const orc_store* st, const void* q, int64_t v) {
   const float* a = (const float*)q;
   double acc = 0.0;
   for (int i = 0; i < d; i++) {
-    double t = (double)a[i] - (double)elem(st, v, i);
-    acc += t * t;
+    float t = a[i] - elem(st, v, i); /* the float difference */
+    acc += (double)t * (double)t;    /* its square is exact in double */
   }
   return (double)(float)acc;
 }
@@ -747,6 +748,7 @@ typedef struct {
   int32_t dgs_on, discard_pm, cooldown_pm, random_discard;
   int32_t ppe_on, forward_f, rerank_mult;
   int32_t visited_policy, stop_on_no_change;
+  int32_t ghost_every_stage, reserved;
   uint64_t seed;
 } orc_params;
 
@@ -815,11 +817,14 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
     if (ent == ENTRY_PREDICTED)
       ent = (t == 0 && C->given_seeds && C->given_seeds[(size_t)row * C->n_given] != NONE_ID) ? ENTRY_SEEDS
                                                                                              : ENTRY_GHOST_GRAPH;
+    const int ghost = ent == ENTRY_GHOST_GRAPH || ent == ENTRY_GHOST_DENSE;
     if (!use_entry) {
       /* path extension: continue from I(z) for the first f results of the previous stage */
       for (int i = 0; i < nhand; i++) seeds[nseeds++] = handoff[i];
       sd = seeds;
-    } else if (ent == ENTRY_GHOST_GRAPH || ent == ENTRY_GHOST_DENSE) {
+    }
+    if (ghost && (use_entry || P->ghost_every_stage)) {
+      /* ghost staging on this shard (also on later stages when ghost_every_stage is set) */
       orc_store gs = {ix->dtype, ix->d, ix->R[s], ix->g_codes[s], ix->g_scale[s]};
       int tt = P->t_seeds;
       res top[1024];
@@ -860,7 +865,7 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
       if (C->out_ghost && t == 0)
         for (int i = ntop; i < tt; i++) C->out_ghost[(size_t)row * P->t_seeds + i] = NONE_ID;
       sd = seeds;
-    } else if (ent == ENTRY_SEEDS && C->given_seeds && t == 0) {
+    } else if (use_entry && ent == ENTRY_SEEDS && C->given_seeds && t == 0) {
       for (int i = 0; i < C->n_given; i++) seeds[nseeds++] = C->given_seeds[(size_t)row * C->n_given + i];
       sd = seeds;
     }

@@ -6,6 +6,7 @@ Paper references: Sec. 2.1 Eq. 1 (k-NN), Sec. 2.2 Eq. 2 and Steps 1-4 (beam
 search), Sec. 3.1.2 (I(u) and the staged search), Sec. 3.2.2 (ghost staging),
 Sec. 3.3.2 / Sec. 4 (direction table and selection), Sec. 5.1 (Recall@k).
 """
+import math
 import os
 
 import numpy as np
@@ -21,7 +22,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 def f32_order(D64, k):
     """Brute force order by (f32(dist), id) from float64 squared distances (numpy)."""
-    D32 = D64.astype(np.float32)
+    D32 = np.asarray(D64).astype(np.float32)
     n = D32.shape[1]
     return np.stack([np.lexsort((np.arange(n), row))[:k] for row in D32])
 
@@ -61,11 +62,12 @@ def test_ghost_sample_uniform_without_replacement():
 # ---------------------------------------------------------------------------
 # Eq. 2 (squared) and Eq. 1
 # ---------------------------------------------------------------------------
-def test_distance_matches_float64_textbook_then_rounded():
+def test_distance_matches_float_differences_summed_in_double():
     X = small(50, 37)
     q = small(1, 37, seed=2)[0]
     for v in range(50):
-        ref = np.float32(((q.astype(np.float64) - X[v].astype(np.float64)) ** 2).sum())
+        diff = (q - X[v]).astype(np.float32)  # numpy float32 subtraction, rounded to nearest
+        ref = np.float32(math.fsum((diff.astype(np.float64) ** 2).tolist()))
         assert oracle.dist(X, q, v) == float(ref)
 
 
@@ -239,7 +241,7 @@ def test_pin2_outputs_sorted_and_distances_recomputed():
             keys = [(float(ds[i, j]), int(ids[i, j])) for j in range(10)]
             assert keys == sorted(keys)
             for j in range(10):
-                ref = np.float32(((Q[i].astype(np.float64) - X[ids[i, j]].astype(np.float64)) ** 2).sum())
+                ref = np.float32((((Q[i] - X[ids[i, j]]).astype(np.float32).astype(np.float64)) ** 2).sum())
                 assert ds[i, j] == ref
 
 
@@ -270,6 +272,24 @@ def test_pin5_special_cases_reduce_to_plain():
     # DGS on with discard > 0 really changes the work done
     o = oracle.search(ix, Q, k=10, l=32, T=50, dgs_on=True)
     assert o[2][:, 3].sum() > 0
+
+
+def test_ghost_every_stage_reduces_to_stage0_entry_without_path_extension():
+    X = small(600, 16, C=5)
+    Q = small(30, 16, C=5, seed=2)
+    ix1 = oracle.build_index(X, deg=10, dgs=True, ghost_ratio=0.1, deg_g=8)
+    for e in ("ghost_graph", "ghost_dense"):
+        a = oracle.search(ix1, Q, k=5, l=32, T=30, entry=e)
+        b = oracle.search(ix1, Q, k=5, l=32, T=30, entry=e, ghost_every_stage=True)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    ix3 = oracle.build_index(X, deg=10, S=3, dgs=True, ghost_ratio=0.1, deg_g=8)
+    a = oracle.search(ix3, Q, k=5, l=32, T=30, entry="ghost_dense", ppe_on=False)
+    b = oracle.search(ix3, Q, k=5, l=32, T=30, entry="ghost_dense", ppe_on=False, ghost_every_stage=True)
+    assert np.array_equal(a[0], b[0])
+    # with path extension, later stages do extra ghost work
+    a = oracle.search(ix3, Q, k=5, l=32, T=30, entry="ghost_dense")
+    b = oracle.search(ix3, Q, k=5, l=32, T=30, entry="ghost_dense", ghost_every_stage=True)
+    assert np.all(b[2][:, 4] == 3 * a[2][:, 4])
 
 
 def test_pin5_dense_ghost_over_all_nodes_is_brute_force():
