@@ -86,13 +86,15 @@ def oracle_from_device(gx, X):
     return ox
 
 
-def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes):
-    """Bytes the search must move per batch, from the per-query counters:
+def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_stage):
+    """Bytes the stage kernel must move per batch, from the per-query counters:
     gathered vectors (n_dist rows), adjacency rows (n_exp), direction-table rows
-    and parent vectors of the expansions made under the filter, ghost-stage
-    vectors and rows, the query per stage and the results per stage."""
+    and parent vectors of the expansions made under the filter, ghost-graph
+    vectors and rows (graph-mode entry, which runs inside the stage kernel),
+    the query per stage and the results per stage. The dense entry runs in its
+    own kernel and is not counted here."""
     n_dist, n_exp, skipped = ctr[:, 0].sum(), ctr[:, 1].sum(), ctr[:, 3].sum()
-    n_dist_g, n_exp_g = ctr[:, 4].sum(), ctr[:, 5].sum()
+    n_dist_g, n_exp_g = (ctr[:, 4].sum(), ctr[:, 5].sum()) if ghost_in_stage else (0, 0)
     n_exp_dgs = skipped / max(1, deg - n_keep) if deg > n_keep else 0
     nq = ctr.shape[0]
     vec = n_dist * row_bytes
@@ -153,7 +155,7 @@ def main():
     def run(ix, itopk, T, opts, counters=False):
         return ix.search(Qd, k, itopk, T, opts, counters=counters)
 
-    def timed(ix, itopk, T, opts, reps=3):
+    def timed(ix, itopk, T, opts, reps=2):
         run(ix, itopk, T, opts)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -162,11 +164,12 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps
 
-    def sweep(ix, form, opts_list, itopks, Tmults):
+    def sweep(ix, form, opts_list, itopks, Ts):
         rows = []
         for itopk in itopks:
-            for tm in Tmults:
-                T = max(4, int(itopk * tm))
+            for T in Ts:
+                if T > 2 * itopk:
+                    continue
                 for name, opts in opts_list:
                     ids, _ = run(ix, itopk, T, opts)
                     torch.cuda.synchronize()
@@ -178,17 +181,21 @@ def main():
         best = max(ok, key=lambda r: r["qps"]) if ok else max(rows, key=lambda r: r["recall"])
         return best, rows
 
-    tuned_opts = [("gs+dgs", miann.SearchOptions(entry="ghost_graph", dgs=True)),
-                  ("gsdense+dgs", miann.SearchOptions(entry="ghost_dense", dgs=True))]
+    tuned_opts = []
+    for r in (1, 2):
+        tuned_opts += [(f"gs+dgs r{r}", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=r)),
+                       (f"gsdense+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r)),
+                       (f"gsdense-all+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r,
+                                                                     ghost_every_stage=True))]
     log("sweep: tuned (ghost staging + direction filter + path extension)")
-    best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], (0.5, 1.0))
+    best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], (16, 32, 64, 128))
 
     plain = None
     if args.plain:
         log("building the plain unsharded index")
         gp = miann.Index.build(Xd, degree=W["deg"], num_shards=1, dgs_table=False, seed=5)
-        plain_opts = [(f"n_init={n}", miann.SearchOptions(n_init=n)) for n in (256, 2048)]
-        pbest, _ = sweep(gp, "plain", plain_opts, W["itopks"], (1.0,))
+        plain_opts = [(f"n_init={n}", miann.SearchOptions(n_init=n)) for n in (2048, 4096)]
+        pbest, _ = sweep(gp, "plain", plain_opts, W["itopks"], (32, 64, 128))
         plain = {k_: pbest[k_] for k_ in ("variant", "itopk", "T", "recall", "qps")}
         del gp
 
@@ -207,7 +214,8 @@ def main():
     v0 = gx.shard(0)
     row_bytes = v0.d_pad * 4
     n_keep = W["deg"] - (int(round(opts.discard * 1000)) * W["deg"]) // 1000 if opts.dgs else W["deg"]
-    bytes_total, vec_bytes = algorithmic_bytes(ctr, W["d"], W["deg"], W["deg_g"], v0.W, n_keep, S, k, row_bytes)
+    bytes_total, vec_bytes = algorithmic_bytes(ctr, W["d"], W["deg"], W["deg_g"], v0.W, n_keep, S, k, row_bytes,
+                                               opts.entry == "ghost_graph")
     stage_total_ms = float(stage_ms.sum())
     achieved = bytes_total / (stage_total_ms * 1e-3) / 1e9
 
@@ -238,6 +246,7 @@ def main():
                                f"std {W['sigma']}, degree {W['deg']}, {S} resident shards with path extension, "
                                f"ghost ratio {W['ghost_ratio']}, direction filter", "nq": nq, "k": k,
                    "itopk": itopk, "max_iters": T, "entry": opts.entry, "dgs": bool(opts.dgs),
+                   "search_width": opts.search_width, "ghost_every_stage": bool(opts.ghost_every_stage),
                    "recall@10": best["recall"], "distance_accumulation": "f64 of f32 inputs"},
         "latency_ms": {"batch_p50": float(np.percentile(step_ms, 50)), "batch_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -256,7 +265,8 @@ def main():
         import oracle
         ox = oracle_from_device(gx, X)
         m = args.cpu_sample or nq
-        okw = dict(k=k, l=itopk, T=T, entry=opts.entry, dgs_on=opts.dgs, l_g=opts.ghost_itopk, T_g=opts.ghost_iters)
+        okw = dict(k=k, l=itopk, T=T, entry=opts.entry, dgs_on=opts.dgs, l_g=opts.ghost_itopk, T_g=opts.ghost_iters,
+                   r=opts.search_width, ghost_every_stage=opts.ghost_every_stage)
         t0 = time.perf_counter()
         oi, od, _ = oracle.search(ox, Q[:m], **okw)
         t_cpu = time.perf_counter() - t0

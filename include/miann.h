@@ -172,6 +172,9 @@ typedef struct {
   int32_t stop_on_no_change;/* also stop when an iteration inserts nothing into p */
   int32_t hash_log2;        /* visited-hash slots per query = 2^hash_log2 (0 = automatic, 8..13) */
   int32_t n_seeds;          /* entries per query in seeds_dev (MIANN_ENTRY_SEEDS) */
+  int32_t ghost_every_stage;/* with path extension and a ghost entry: stages t >= 1 also start from their
+                               shard's ghost-entry seeds, besides I(z) (an extension; 0 = stage 0 only) */
+  int32_t reserved;
   uint64_t seed;            /* random-stream seed */
   const uint64_t* qkeys;    /* device [nq] query keys (index within a request), NULL = row index */
   const uint32_t* seeds;    /* device [nq][n_seeds] local ids in each query's start shard */

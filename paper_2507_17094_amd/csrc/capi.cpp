@@ -441,6 +441,7 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   a.cooldown_pm = sp.cooldown_permille;
   a.random_discard = sp.random_discard;
   a.stop_on_no_change = sp.stop_on_no_change;
+  a.ghost_every = sp.ghost_every_stage;
   a.S = ix->S;
   a.ppe = sp.ppe;
   a.f = f;
@@ -494,7 +495,9 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     mark(0, 0);
     for (int s = 0; s < ix->S && rc == MIANN_OK; s++) {
       const Shard& h = ix->sh[s];
-      hipError_t e = dense_entry(ix->store_dtype, queries, nq, ix->d, sp.qkeys, ix->S, s, sp.ppe, h.g_f32, h.g_store,
+      // dense seeds are needed for the start shard only, unless every stage takes a ghost entry
+      const int start_only = sp.ppe && !sp.ghost_every_stage;
+      hipError_t e = dense_entry(ix->store_dtype, queries, nq, ix->d, sp.qkeys, ix->S, s, start_only, h.g_f32, h.g_store,
                                  h.g_scale, h.g_map, h.R, ix->d_pad, ix->d_pad_f32, t_seeds,
                                  (uint64_t*)(sb + off_dense), st);
       if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));

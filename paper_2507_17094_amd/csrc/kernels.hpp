@@ -37,7 +37,7 @@ struct StageArgs {
   int64_t nq;
   int d, d_pad, d_pad_f32, W, deg, degp, deg_g, degp_g;
   int k, l, r, T, n_init, l_g, T_g, t_seeds;
-  int entry, dgs, n_keep, cooldown_pm, random_discard, stop_on_no_change;
+  int entry, dgs, n_keep, cooldown_pm, random_discard, stop_on_no_change, ghost_every;
   int S, stage, ppe, f, rerank_m, lowp;
   int hash_log2, lp_pow2, waves_per_block;
   int per_wave_lds;         // bytes

@@ -8,8 +8,9 @@
 // v_mfma_f32_32x32x2_f32 (one 32 x 32 block per wave), and each wave then
 // filters 16 rows of the tile against that row's current K'-th best key and
 // merges survivors into the row's sorted list in LDS. The selected K' = K + 16
-// candidates are rescored in direct form (double accumulation, exactly like the
-// search kernel), sorted by (dist, id) and cut to K, so the result is the exact
+// candidates are rescored in direct form (the search kernel's definition: float
+// differences, squares summed in double, rounded once), sorted by (dist, id) and
+// cut to K, so the result is the exact
 // top-K unless the GEMM-form error exceeds the distance gap across 16 ranks.
 #include <hipcub/hipcub.hpp>
 
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(256) void rescore_kernel(const uint64_t* __restrict
 #pragma unroll
           for (int e = 0; e < P16; e++) {
             const float xe = (DT == DT_F16 || DT == DT_FP8) ? s * x[e] : x[e];
-            const double t = (double)qrow[c * P16 + e] - (double)xe;
-            acc = __builtin_fma(t, t, acc);
+            const float t = qrow[c * P16 + e] - xe;
+            acc = __builtin_fma((double)t, (double)t, acc);
           }
         }
       acc += shfl_xor_f64(acc, 1);

@@ -9,9 +9,10 @@
 //           not depend on what the hash forgets
 //   q     : the query, plus the query sign bits of the current parents
 // Neighbour vectors are gathered by 8-lane teams, each lane reading 16-byte
-// chunks of the row (rows are padded to 128-byte multiples), and the squared
-// differences are accumulated in double so a float distance is the exactly
-// rounded value of the sum.
+// chunks of the row (rows are padded to 128-byte multiples). Each difference
+// q_i - x_i is a float; its square is exact in double and the squares are
+// summed in double, so a distance is the sum of the squared float differences
+// rounded once to float, whatever the order of summation.
 //
 // Stages follow path extension (Sec. 3.1.2): stage t of query q runs on shard
 // (q_key + t) mod S, seeded by the inter-shard map of the previous stage's top
@@ -51,7 +52,8 @@ struct Searcher {
   static constexpr int G = (8 / CPL) < 1 ? 1 : ((8 / CPL) > 4 ? 4 : (8 / CPL));
 
   const StageArgs a;
-  uint64_t* pk;
+  uint64_t* pk;      // the priority queue p
+  uint64_t* pk_alt;  // second buffer for merges
   uint64_t* ck;
   uint32_t* cid;
   uint32_t* hash;
@@ -127,28 +129,18 @@ struct Searcher {
     const int newpos = pos + rank;
     if (valid) ck[rank] = c;
     wsync();
-    uint64_t pv[kMaxL / 64];
-    int np[kMaxL / 64];
-    const int nm = (l + 63) >> 6;
-#pragma unroll
-    for (int m = 0; m < kMaxL / 64; m++) {
-      np[m] = -1;
-      pv[m] = kDummy;
-      const int i = lane + 64 * m;
-      if (m < nm && i < l) {
-        pv[m] = pk[i];
-        np[m] = i + count_below(ck, nv, key_noflag(pv[m]));
-      }
-    }
-    wsync();
-#pragma unroll
-    for (int m = 0; m < kMaxL / 64; m++) {
-      const int i = lane + 64 * m;
-      if (m < nm && np[m] >= 0 && np[m] < l && np[m] != i) pk[np[m]] = pv[m];
+    // p entries move right by the number of new keys below them; write into the other buffer
+    for (int i = lane; i < l; i += 64) {
+      const uint64_t pv = pk[i];
+      const int np = i + count_below(ck, nv, key_noflag(pv));
+      if (np < l) pk_alt[np] = pv;
     }
     const bool in = valid && newpos < l;
-    if (in) pk[newpos] = c;
+    if (in) pk_alt[newpos] = c;
     wsync();
+    uint64_t* t = pk;
+    pk = pk_alt;
+    pk_alt = t;
     return (ballot(in) != 0 ? 1 : 0) | (ballot(in && newpos < a.k) != 0 ? 2 : 0);
   }
 
@@ -196,6 +188,7 @@ struct Searcher {
       }
 #pragma unroll
       for (int gi = 0; gi < G; gi++) {
+        asm volatile("" ::: "memory");  // re-read the query slice from LDS rather than pinning it in registers
         uint32_t dbits;
         if constexpr (DT == DT_U8) {
           uint32_t xx = 0, qx = 0;
@@ -226,8 +219,8 @@ struct Searcher {
 #pragma unroll
             for (int e = 0; e < P16; e++) {
               const float xe = kScaled ? sc[gi] * x[e] : x[e];
-              const double t = (double)qc[e] - (double)xe;
-              acc = __builtin_fma(t, t, acc);
+              const float t = qc[e] - xe;  // float difference; its square is exact in double
+              acc = __builtin_fma((double)t, (double)t, acc);
             }
           }
           acc += shfl_xor_f64(acc, 1);
@@ -324,6 +317,12 @@ struct Searcher {
         if (t == pa) u = pid[t];
       uint32_t nb = act ? g.graph[(size_t)u * g.deg + slot] : kNone;
       if (dgs_phase) {
+        // this lane's direction-table words, loaded in the same round trip as the adjacency row
+        constexpr int kSW = 8;
+        const uint32_t* srow = g.sign + (size_t)u * W * g.deg + slot;
+        uint32_t sw[kSW];
+#pragma unroll
+        for (int w = 0; w < kSW; w++) sw[w] = (act && !a.random_discard && w < W) ? srow[(size_t)w * g.deg] : 0u;
         // query sign bits against each parent: bit i = [q_i > x_parent,i]
 #pragma unroll
         for (int t = 0; t < kMaxR; t++) {
@@ -355,8 +354,10 @@ struct Searcher {
             rk = ((uint32_t)(sm_mix(h1 ^ (((uint64_t)u << 8) | (uint64_t)slot)) >> 40) << 8) | (uint32_t)slot;
           } else {
             int mm = 0;
-            const uint32_t* srow = g.sign + (size_t)u * W * g.deg + slot;
-            for (int w = 0; w < W; w++) mm += __popc(qsign[pa * W + w] ^ srow[(size_t)w * g.deg]);
+#pragma unroll
+            for (int w = 0; w < kSW; w++)
+              if (w < W) mm += __popc(qsign[pa * W + w] ^ sw[w]);
+            for (int w = kSW; w < W; w++) mm += __popc(qsign[pa * W + w] ^ srow[(size_t)w * g.deg]);
             rk = ((uint32_t)mm << 8) | (uint32_t)slot;
           }
         }
@@ -392,8 +393,8 @@ struct Searcher {
           const float xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
           for (int e = 0; e < 4; e++) {
-            const double t = (double)qf[4 * c + e] - (double)xs[e];
-            acc = __builtin_fma(t, t, acc);
+            const float t = qf[4 * c + e] - xs[e];
+            acc = __builtin_fma((double)t, (double)t, acc);
           }
         }
       acc += shfl_xor_f64(acc, 1);
@@ -427,8 +428,18 @@ struct Searcher {
   }
 };
 
+// Occupancy target of the stage kernel (waves per SIMD); 0 leaves the choice to the compiler.
+#ifndef MIANN_STAGE_WAVES_PER_EU
+#define MIANN_STAGE_WAVES_PER_EU 0
+#endif
+#if MIANN_STAGE_WAVES_PER_EU > 0
+#define MIANN_STAGE_ATTR __attribute__((amdgpu_waves_per_eu(MIANN_STAGE_WAVES_PER_EU)))
+#else
+#define MIANN_STAGE_ATTR
+#endif
+
 template <int DT, int CPL>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(256) MIANN_STAGE_ATTR void stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
   const int64_t q = (int64_t)blockIdx.x * a.waves_per_block + wave;
@@ -440,6 +451,8 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   S.tl = S.lane & 7;
   char* base = smem + (size_t)wave * a.per_wave_lds;
   S.pk = (uint64_t*)base;
+  base += (size_t)a.lp_pow2 * 8;
+  S.pk_alt = (uint64_t*)base;
   base += (size_t)a.lp_pow2 * 8;
   S.ck = (uint64_t*)base;
   base += 64 * 8;
@@ -478,42 +491,47 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   // predicted entry: the row's seeds, or the ghost graph when the predictor was not confident
   int entry = a.entry;
   if (entry == 4) entry = (t == 0 && a.seeds[(size_t)q * a.n_seeds] != kNone) ? 3 : 1;
+  const bool ghost = entry == 1 || entry == 2;
+  if (ghost && (use_entry || a.ghost_every)) {
+    uint64_t seed = kDummy;
+    if (entry == 1) {
+      // ghost staging: a short search on the ghost graph (p and the hash serve as scratch)
+      GraphCtx gg{sh.g_store, sh.g_scale, sh.g_graph, nullptr, sh.R, a.deg_g, a.degp_g};
+      S.p_reset(a.l_g);
+      long long ge = 0, gi = 0, gl = 0;
+      const long long nd0 = S.ctr[0];
+      S.random_init(gg, stream_ghost, a.deg_g, a.l_g);
+      S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi, gl);
+      S.ctr[4] += S.ctr[0] - nd0;
+      S.ctr[0] = nd0;
+      S.ctr[5] += ge;
+      const uint64_t gk = S.lane < a.t_seeds ? S.pk[S.lane] : kDummy;
+      if (gk != kDummy) seed = make_key(key_dist(gk), sh.g_map[key_id(gk)], kFresh);
+      wsync();
+      S.hash_clear();
+      S.p_reset(a.l);
+    } else {
+      const uint64_t dk = S.lane < a.t_seeds ? a.dense[((size_t)q * Sh + s) * a.t_seeds + S.lane] : kDummy;
+      if (dk != kDummy) seed = make_key((uint32_t)(dk >> 32), (uint32_t)dk, kFresh);
+      S.ctr[4] += sh.R;
+    }
+    // the ghost seeds' distances are those of the nodes they copy
+    S.add_keys(seed, a.l);
+  }
   if (!use_entry) {
     // path extension: continue from I(z) of the previous stage's first f results
     const uint32_t id = S.lane < a.f ? a.hand_in[(size_t)q * a.f + S.lane] : kNone;
     S.add_ids(gm, id != kNone, id, a.l);
-  } else if (entry == 1) {
-    // ghost staging: a short search on the ghost graph, then hand over to the main graph
-    GraphCtx gg{sh.g_store, sh.g_scale, sh.g_graph, nullptr, sh.R, a.deg_g, a.degp_g};
-    S.p_reset(a.l_g);
-    long long ge = 0, gi = 0, gl = 0;
-    const long long nd0 = S.ctr[0];
-    S.random_init(gg, stream_ghost, a.deg_g, a.l_g);
-    S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi, gl);
-    S.ctr[4] += S.ctr[0] - nd0;
-    S.ctr[0] = nd0;
-    S.ctr[5] += ge;
-    uint64_t gk = S.lane < a.t_seeds ? S.pk[S.lane] : kDummy;
-    uint64_t seed = kDummy;
-    if (gk != kDummy) seed = make_key(key_dist(gk), sh.g_map[key_id(gk)], kFresh);
-    wsync();
-    S.hash_clear();
-    S.p_reset(a.l);
-    S.add_keys(seed, a.l);
-  } else if (entry == 2) {
-    uint64_t dk = S.lane < a.t_seeds ? a.dense[((size_t)q * Sh + s) * a.t_seeds + S.lane] : kDummy;
-    uint64_t seed = kDummy;
-    if (dk != kDummy) seed = make_key((uint32_t)(dk >> 32), (uint32_t)dk, kFresh);
-    S.ctr[4] += sh.R;
-    S.add_keys(seed, a.l);
-  } else if (entry == 3 && t == 0 && a.seeds) {
-    for (int b = 0; b < a.n_seeds; b += 64) {
-      const int j = b + S.lane;
-      const uint32_t id = j < a.n_seeds ? a.seeds[(size_t)q * a.n_seeds + j] : kNone;
-      S.add_ids(gm, id != kNone && id < sh.n, id, a.l);
+  } else if (!ghost) {
+    if (entry == 3 && t == 0 && a.seeds) {
+      for (int b = 0; b < a.n_seeds; b += 64) {
+        const int j = b + S.lane;
+        const uint32_t id = j < a.n_seeds ? a.seeds[(size_t)q * a.n_seeds + j] : kNone;
+        S.add_ids(gm, id != kNone && id < sh.n, id, a.l);
+      }
+    } else {
+      S.random_init(gm, stream_main, a.n_init, a.l);
     }
-  } else {
-    S.random_init(gm, stream_main, a.n_init, a.l);
   }
   long long last_topk = 0;
   S.beam_loop(gm, a.l, T, a.dgs != 0, a.stop_on_no_change != 0, stream_main, n_exp, n_iter, last_topk);
@@ -593,7 +611,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
 }
 
 int stage_lds_bytes(const StageArgs& a) {
-  int b = a.lp_pow2 * 8 + 64 * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + kMaxR * 4;
+  int b = 2 * a.lp_pow2 * 8 + 64 * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + kMaxR * 4;
   return (b + 15) & ~15;
 }
 

@@ -84,7 +84,9 @@ def test_path_extension_parity(S):
     ox = oracle.build_index(X, deg=32, S=S, dgs=True, ghost_ratio=0.05, deg_g=16)
     gx = to_device_index(ox)
     for kw in (dict(), dict(dgs=True, entry="ghost_graph"), dict(ppe=False, entry="ghost_dense"),
-               dict(forward_f=4, dgs=True), dict(ppe=False)):
+               dict(forward_f=4, dgs=True), dict(ppe=False),
+               dict(entry="ghost_dense", dgs=True, ghost_every_stage=True),
+               dict(entry="ghost_graph", ghost_every_stage=True, search_width=2)):
         opts = miann.SearchOptions(**kw)
         g, o = run_both(ox, gx, Q, K, 64, 50, opts)
         compare(g, o, label=f"S{S}-{kw}", ndist_check=not ghost_entry(opts))
