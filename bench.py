@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle leg (0 = all)")
     ap.add_argument("--plain", type=int, default=1, help="also sweep the plain (unsharded, random-entry) search")
+    ap.add_argument("--fixed", default="", help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the path-extension ring is "
@@ -187,8 +188,17 @@ def main():
                        (f"gsdense+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r)),
                        (f"gsdense-all+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r,
                                                                      ghost_every_stage=True))]
-    log("sweep: tuned (ghost staging + direction filter + path extension)")
-    best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], (16, 32, 64, 128))
+    if args.fixed:
+        f = args.fixed.split(",")
+        fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])))
+        ids, _ = run(gx, int(f[0]), int(f[1]), fo)
+        torch.cuda.synchronize()
+        best = dict(form="tuned", variant="fixed", itopk=int(f[0]), T=int(f[1]), opts=fo,
+                    recall=recall(gt, ids.cpu().numpy().view(np.uint32), k), qps=0.0)
+        tuned_rows = [best]
+    else:
+        log("sweep: tuned (ghost staging + direction filter + path extension)")
+        best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], (16, 32, 64, 128))
 
     plain = None
     if args.plain:

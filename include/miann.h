@@ -256,7 +256,8 @@ miann_status miann_predictor_train(miann_predictor* p, const float* x_dev, const
                                    float lambda, uint64_t seed, float* epoch_loss_host, void* stream);
 /* Inference: for each row, confidence = max softmax probability of the entry logits; seeds_dev [n][t] =
  * ghost_map[index] of the t largest logits (seeds[0] = 0xFFFFFFFF when confidence < tau);
- * iters_dev [n] = clamp(ceil(1.25 (exp(budget) - 1)), t_min, t_max); top_entry_dev [n][t] (nullable)
+ * iters_dev [n] = clamp(ceil(1.25 (exp(budget) - 1)), t_min, t_max), or t_max when confidence < tau;
+ * top_entry_dev [n][t] (nullable)
  * receives the raw entry indices. Enqueues on `stream`. */
 miann_status miann_predictor_predict(const miann_predictor* p, const float* x_dev, int64_t n, int32_t t, float tau,
                                      const uint32_t* ghost_map_dev, int32_t t_min, int32_t t_max, uint32_t* seeds_dev,

@@ -92,7 +92,7 @@ def adam_step(params: dict, grads: dict, state: dict, lr: float, step: int, b1=0
 
 def readout(Z, t: int, tau: float, gmap, t_min: int, t_max: int):
     """Seeds = gmap of the t largest entry logits (ties: smaller index), budget = clamp(ceil(1.25 (e^z_R - 1))),
-    confidence = max softmax probability; seeds[:, 0] = NONE when confidence < tau."""
+    confidence = max softmax probability; seeds[:, 0] = NONE and budget = t_max when confidence < tau."""
     Z = np.asarray(Z, np.float64)
     R = Z.shape[1] - 1
     logits = Z[:, :R]
@@ -102,4 +102,5 @@ def readout(Z, t: int, tau: float, gmap, t_min: int, t_max: int):
     seeds = np.asarray(gmap, np.uint32)[order]
     seeds[conf < tau, 0] = 0xFFFFFFFF
     T = np.clip(np.ceil(1.25 * (np.exp(Z[:, R]) - 1.0)), t_min, t_max).astype(np.int32)
+    T[conf < tau] = t_max  # fallback queries keep the full budget
     return seeds, T, conf, order

@@ -192,7 +192,8 @@ hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float l
 // Inference read-out per row: confidence = max softmax probability over the R
 // entry logits; seeds = ghost map of the t largest logits (ties -> smaller
 // index); budget = clamp(ceil(1.25 (exp(z_R) - 1)), t_min, t_max). Rows whose
-// confidence is below tau get seeds[0] = none (fall back to ghost staging).
+// confidence is below tau get seeds[0] = none (fall back to ghost staging) and
+// the budget t_max.
 __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ Z, int n, int R, int t, float tau,
                                                       const uint32_t* __restrict__ gmap, int t_min, int t_max,
                                                       uint32_t* __restrict__ seeds, int32_t* __restrict__ iters,
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
     float tb = ceilf(1.25f * (expf(yb) - 1.f));
     if (!(tb >= (float)t_min)) tb = (float)t_min;
     if (tb > (float)t_max) tb = (float)t_max;
-    iters[b] = (int32_t)tb;
+    iters[b] = c < tau ? t_max : (int32_t)tb;  // a fallback query keeps the full budget
     conf[b] = c;
   }
 }

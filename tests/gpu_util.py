@@ -110,3 +110,29 @@ def compare(g, o, min_frac=0.999, check_counters=True, label="", ndist_check=Tru
             # what the exact visited set evaluates
             assert np.all(gc[same, 0] >= oc[same, 0])
     return frac
+
+
+def oracle_from_device(gx, X):
+    """CPU copy of a device-built index (graph, sign table, shard maps, ghost shards) for the oracle."""
+    info = gx.info()
+    ox = oracle.OracleIndex(dtype="u8" if X.dtype == np.uint8 else "f32", d=info["d"], deg=info["degree"],
+                            S=info["num_shards"], n_total=info["n"])
+    for s in range(info["num_shards"]):
+        v = gx.shard(s)
+        n, deg, W = v.n, v.degree, v.W
+        gmap = d2h(v.global_ids, n, np.uint32)
+        Xs = np.ascontiguousarray(X[gmap])
+        sh = dict(n=n, gmap=gmap, orig_base=Xs, codes=Xs, graph=d2h(v.graph, n * deg, np.uint32).reshape(n, deg))
+        if v.sign:
+            sh["sign"] = np.ascontiguousarray(d2h(v.sign, n * W * deg, np.uint32).reshape(n, W, deg).transpose(0, 2, 1))
+        if v.next_map:
+            sh["next"] = d2h(v.next_map, n, np.uint32)
+        if v.n_ghost:
+            sh["R"] = v.n_ghost
+            sh["g_map"] = d2h(v.ghost_ids, v.n_ghost, np.uint32)
+            sh["g_graph"] = d2h(v.ghost_graph, v.n_ghost * v.ghost_degree, np.uint32).reshape(v.n_ghost,
+                                                                                                v.ghost_degree)
+            sh["g_codes"] = np.ascontiguousarray(Xs[sh["g_map"]])
+            ox.deg_g = v.ghost_degree
+        ox.shards.append(sh)
+    return ox

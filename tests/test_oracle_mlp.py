@@ -66,4 +66,4 @@ def test_readout_budget_and_fallback():
     seeds, T, conf, order = mlp.readout(Z, 2, 0.3, np.array([10, 11, 12, 13]), 4, 100)
     assert order[0].tolist() == [1, 2]  # tie -> smaller index first
     assert seeds[0].tolist() == [11, 12] and T[0] == 8
-    assert conf[1] == pytest.approx(0.25) and seeds[1, 0] == 0xFFFFFFFF and T[1] == 4
+    assert conf[1] == pytest.approx(0.25) and seeds[1, 0] == 0xFFFFFFFF and T[1] == 100
