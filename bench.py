@@ -103,21 +103,304 @@ def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_s
     return float(b), float(vec)
 
 
+FORMS = {
+    # FP16 / FP8-e4m3 traversal with FP32 rerank (N reduced from 5M so the exact-kNN build fits a run)
+    "lowprec1m": dict(N=1_000_000, d=256, C=2000, sigma=0.2, nq=100_000, deg=64, knn_k0=96, ghost_ratio=0.01,
+                      deg_g=32),
+    # learned entry / budget predictor (N reduced from 10M; 4,096 ghosts, MLP 96-256-256-4097)
+    "learned1m": dict(N=1_000_000, d=96, C=4000, sigma=0.25, n_train=500_000, nq=100_000, deg=32, R=4096, deg_g=32,
+                      hidden=256),
+    # continuous-batching server on uint8 data (N reduced from 20M)
+    "serving1m": dict(N=1_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32, n_requests=600),
+}
+
+
+def make_data(N, d, C, sigma, seed, u8=False):
+    import synth
+    X = synth.mixture(N, d, C, sigma, seed) if N > 100_000 else synth.mixture_small(N, d, C, sigma, seed)
+    return synth.to_u8(X) if u8 else X
+
+
+def copy_dev(ptr, nbytes):
+    import torch
+    import paper_2507_17094_amd as miann
+    t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    if nbytes:
+        miann._hip_copy(t.data_ptr(), ptr, nbytes)
+    return t
+
+
+def reimport(gx, Xd, store):
+    """The same graph and ghost shard with another traversal store (codes and sign table rebuilt)."""
+    import paper_2507_17094_amd as miann
+    v = gx.shard(0)
+    g = copy_dev(v.graph, v.n * v.degree * 4).view(__import__("torch").int32).view(v.n, v.degree)
+    gi = copy_dev(v.ghost_ids, v.n_ghost * 4).view(__import__("torch").int32)
+    gg = copy_dev(v.ghost_graph, v.n_ghost * v.ghost_degree * 4).view(__import__("torch").int32)
+    gg = gg.view(v.n_ghost, v.ghost_degree)
+    return miann.Index.import_shards([dict(vectors=Xd, graph=g, ghost_ids=gi, ghost_graph=gg)], d=v.d,
+                                     in_dtype="f32", store=store, degree=v.degree, ghost_degree=v.ghost_degree)
+
+
+def time_search(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def form_lowprec(args):
+    """Recall and QPS of FP32, FP16 and FP8 traversal (FP32 rerank) at k = 10 and k = 100."""
+    import torch
+    import paper_2507_17094_amd as miann
+    import synth
+    W = FORMS["lowprec1m"]
+    X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE)
+    Q = make_data(W["nq"], W["d"], W["C"], W["sigma"], synth.SEED_QUERIES)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    t0 = time.time()
+    g32 = miann.Index.build(Xd, degree=W["deg"], knn_k0=W["knn_k0"], num_shards=1, dgs_table=True, seed=5)
+    g32.build_ghost(ratio=W["ghost_ratio"], ghost_degree=W["deg_g"], seed=5)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    log(f"build {t_build:.1f}s")
+    idx = {"f32": g32, "f16": reimport(g32, Xd, "f16"), "fp8": reimport(g32, Xd, "fp8")}
+    gt100, _ = g32.exact_knn(Qd, 100)
+    gt100 = gt100.cpu().numpy().view(np.uint32)
+    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    res = {}
+    for k, itopks in ((10, (32, 64, 128)), (100, (128, 256, 512))):
+        gt = gt100[:, :k]
+        for name, gx in idx.items():
+            rows = []
+            for itopk in itopks:
+                for T in (32, 64, 128):
+                    if T > 2 * itopk:
+                        continue
+                    ids, _ = gx.search(Qd, k, itopk, T, opts)
+                    ids = ids.cpu().numpy().view(np.uint32)
+                    rc = recall(gt, ids, k)
+                    # agreement with the FP32 traversal at the same setting
+                    if name == "f32":
+                        res[("ref", k, itopk, T)] = ids
+                    agree = recall(res[("ref", k, itopk, T)], ids, k)
+                    sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts))
+                    rows.append(dict(itopk=itopk, T=T, recall=rc, agree_f32=agree, qps=W["nq"] / sec))
+                    log(f"  k={k:3d} {name:4s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} "
+                        f"agree_f32={agree:.4f} qps={W['nq'] / sec:,.0f}")
+            ok = [r for r in rows if r["recall"] >= 0.95]
+            best = max(ok, key=lambda r: r["qps"]) if ok else max(rows, key=lambda r: r["recall"])
+            res[(name, k)] = dict(best=best, rows=rows)
+    head = res[("fp8", 10)]["best"]
+    out = {
+        "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": W["nq"] / head["qps"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
+        "config": {"workload": f"lowprec1m: N={W['N']} d={W['d']} f32 vectors ({W['C']}-component mixture, std "
+                               f"{W['sigma']}) traversed as FP16 / FP8-e4m3 with per-vector scale, FP32 rerank of "
+                               f"4k; degree {W['deg']}, ghost staging 1%, direction filter; {W['nq']} queries",
+                   "headline": "fp8, k=10"},
+        "forms": {f"{n}_k{k}": {"best": res[(n, k)]["best"], "sweep": res[(n, k)]["rows"]}
+                  for n in ("f32", "f16", "fp8") for k in (10, 100)},
+        "build_s": t_build,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def form_learned(args):
+    """Ghost staging versus the learned entry / budget predictor at recall@10 >= 0.95."""
+    import torch
+    import paper_2507_17094_amd as miann
+    from paper_2507_17094_amd import learned
+    import synth
+    W = FORMS["learned1m"]
+    X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE)
+    Qtr = make_data(W["n_train"], W["d"], W["C"], W["sigma"], synth.SEED_HELDOUT)
+    Q = make_data(W["nq"], W["d"], W["C"], W["sigma"], synth.SEED_QUERIES)
+    Xd, Qtrd, Qd = (torch.from_numpy(a).cuda() for a in (X, Qtr, Q))
+    k = 10
+    t0 = time.time()
+    gx = miann.Index.build(Xd, degree=W["deg"], num_shards=1, dgs_table=True, seed=5)
+    gx.build_ghost(num_ghost=W["R"], ghost_degree=W["deg_g"], seed=5)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    gt, _ = gx.exact_knn(Qd, k)
+    gt = gt.cpu().numpy().view(np.uint32)
+    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    t0 = time.time()
+    T_max = 128
+    labels = learned.make_labels(gx, Qtrd, k, 64, T_max, opts)
+    torch.cuda.synchronize()
+    t_labels = time.time() - t0
+    t0 = time.time()
+    P, losses = learned.train(gx, Qtrd, labels, hidden=W["hidden"], epochs=8, batch=4096, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"build {t_build:.1f}s labels {t_labels:.1f}s train {t_train:.1f}s losses {losses}")
+    gmap = learned.ghost_map(gx)
+    rows = []
+    for itopk in (32, 64, 128):
+        for T in (16, 32, 64, 128):
+            if T > 2 * itopk:
+                continue
+            ids, _, c = gx.search(Qd, k, itopk, T, opts, counters=True)
+            rc = recall(gt, ids.cpu().numpy().view(np.uint32), k)
+            sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts))
+            nd = float((c[:, 0] + c[:, 4]).double().mean())
+            rows.append(dict(form="ghost", itopk=itopk, T=T, recall=rc, qps=W["nq"] / sec, n_dist=nd))
+            log(f"  ghost     itopk={itopk:3d} T={T:3d} recall={rc:.4f} qps={W['nq'] / sec:,.0f} dists={nd:.0f}")
+            for tau in (0.02, 0.1):
+                (pi, _, pc), _, _, conf = learned.predicted_search(gx, P, Qd, k, itopk, 32, tau, 4, T, opts,
+                                                                   counters=True, gmap=gmap)
+                rp = recall(gt, pi.cpu().numpy().view(np.uint32), k)
+                secp = time_search(lambda: learned.predicted_search(gx, P, Qd, k, itopk, 32, tau, 4, T, opts,
+                                                                    gmap=gmap))
+                ndp = float((pc[:, 0] + pc[:, 4]).double().mean())
+                fb = float((conf < tau).float().mean())
+                rows.append(dict(form=f"learned tau={tau}", itopk=itopk, T=T, recall=rp, qps=W["nq"] / secp,
+                                 n_dist=ndp, fallback=fb))
+                log(f"  learned{tau:5.2f} itopk={itopk:3d} T={T:3d} recall={rp:.4f} qps={W['nq'] / secp:,.0f} "
+                    f"dists={ndp:.0f} fallback={fb:.3f}")
+
+    def best(form_prefix):
+        rr = [r for r in rows if r["form"].startswith(form_prefix)]
+        ok = [r for r in rr if r["recall"] >= 0.95]
+        return max(ok, key=lambda r: r["qps"]) if ok else max(rr, key=lambda r: r["recall"])
+
+    bg, bl = best("ghost"), best("learned")
+    out = {
+        "metric": METRIC, "value": bl["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": W["nq"] / bl["qps"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"learned1m: N={W['N']} d={W['d']} f32 ({W['C']}-component mixture), degree "
+                               f"{W['deg']}, {W['R']} ghosts; BF16 MLP {W['d']}-{W['hidden']}-{W['hidden']}-"
+                               f"{W['R'] + 1} trained on {W['n_train']} queries, {W['nq']} held-out queries"},
+        "ghost_staging": bg, "learned": bl, "gain_qps": bl["qps"] / bg["qps"],
+        "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "sweep": rows, "build_s": t_build,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def form_serving(args):
+    """Poisson request stream into the continuous-batching server: QPS and p50 / p99 latency per rate."""
+    import threading
+    import torch
+    import paper_2507_17094_amd as miann
+    import synth
+    W = FORMS["serving1m"]
+    X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE, u8=True)
+    Xd = torch.from_numpy(X).cuda()
+    t0 = time.time()
+    gx = miann.Index.build(Xd, degree=W["deg"], num_shards=1, dgs_table=True, seed=5)
+    gx.build_ghost(ratio=W["ghost_ratio"], ghost_degree=W["deg_g"], seed=5)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    rng = np.random.default_rng([synth.SEED_ARRIVALS, 1])
+    n_req = W["n_requests"]
+    sizes = np.minimum(1024, np.floor(np.exp(rng.uniform(0, np.log(1025), n_req)))).astype(int)
+    ks = rng.choice([10, 100], n_req)
+    pool = make_data(int(sizes.sum()), W["d"], W["C"], W["sigma"], synth.SEED_QUERIES, u8=True)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    # recall of the settings used, on the whole query pool in one batch
+    Pd = torch.from_numpy(pool).cuda()
+    gt, _ = gx.exact_knn(Pd, 100)
+    gt = gt.cpu().numpy().view(np.uint32)
+    setting = {10: (64, 64), 100: (256, 128)}
+    rec = {}
+    for k, (itopk, T) in setting.items():
+        ids, _ = gx.search(Pd, k, itopk, T, opts)
+        rec[k] = recall(gt[:, :k], ids.cpu().numpy().view(np.uint32), k)
+    log(f"build {t_build:.1f}s recall {rec}")
+    # batch capacity: one large batch of the pool
+    cap_s = time_search(lambda: gx.search(Pd, 10, 64, 64, opts), reps=2)
+    cap_qps = len(pool) / cap_s
+    results = []
+    for load_frac in (0.25, 0.5, 0.8):
+        mean_q = float(sizes.mean())
+        rate = load_frac * cap_qps / mean_q  # requests per second
+        gaps = rng.exponential(1.0 / rate, n_req)
+        srv = miann.Server(gx, num_streams=4, max_batch_queries=8192, max_inflight_queries=65536)
+        tickets = [None] * n_req
+        lat = np.zeros(n_req)
+
+        def collector():
+            for j in range(n_req):
+                while tickets[j] is None:
+                    time.sleep(0.0002)
+                _, _, lat[j] = srv.wait(tickets[j], int(sizes[j]), int(ks[j]))
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t_start = time.perf_counter()
+        nxt = t_start
+        for j in range(n_req):
+            nxt += gaps[j]
+            dt = nxt - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            itopk, T = setting[int(ks[j])]
+            tickets[j] = srv.submit(pool[offs[j]:offs[j + 1]], int(ks[j]), itopk, T, opts)
+        th.join()
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        results.append(dict(offered_load=load_frac, request_rate=rate, qps=float(sizes.sum()) / wall,
+                            p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                            batches=st["batches"], peak_inflight_queries=st["peak_inflight_queries"]))
+        log(f"  load {load_frac:.2f} rate {rate:,.0f} req/s: qps {results[-1]['qps']:,.0f} "
+            f"p50 {results[-1]['p50_ms']:.2f} ms p99 {results[-1]['p99_ms']:.2f} ms batches {st['batches']}")
+    head = results[-1]
+    out = {
+        "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"serving1m: N={W['N']} d={W['d']} uint8 ({W['C']}-component mixture), degree "
+                               f"{W['deg']}, ghost staging 1%, direction filter; Poisson arrivals, requests of "
+                               f"1-1024 queries (log-uniform), k in {{10, 100}}"},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+        "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps, "rates": results,
+        "build_s": t_build,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sharded1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="sharded1m", choices=sorted(WORKLOADS) + sorted(FORMS))
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle leg (0 = all)")
     ap.add_argument("--plain", type=int, default=1, help="also sweep the plain (unsharded, random-entry) search")
     ap.add_argument("--fixed", default="", help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times): the reference for the HBM "
+                         "byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the path-extension ring is "
                                    "exercised with shards resident on one GPU)"}))
         sys.exit(2)
+
+    if args.workload in FORMS:
+        {"lowprec1m": form_lowprec, "learned1m": form_learned, "serving1m": form_serving}[args.workload](args)
+        return
 
     import torch
 
@@ -213,11 +496,29 @@ def main():
     # counters and live per-launch timing of the chosen setting
     ids, dists, ctr = run(gx, itopk, T, opts, counters=True)
     ctr = ctr.cpu().numpy()
-    phases = []
-    for _ in range(3):
+
+    # timed steps; the library records HIP events around each of its launches on the
+    # stream they run on, which gives the per-launch durations of the stage kernel
+    for _ in range(args.warmup):
+        run(gx, itopk, T, opts)
+    torch.cuda.synchronize()
+    starts, ends, phases = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ph = []
+        e0.record()
         gx.search(Qd, k, itopk, T, opts, phase_ms=ph)
+        e1.record()
+        starts.append(e0)
+        ends.append(e1)
         phases.append(ph)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)])
+    ms_per_step = wall / args.steps * 1e3
+    qps = nq * args.steps / wall
+
     phases = np.array(phases).mean(0)
     S = W["S"]
     stage_ms = phases[1:1 + S]
@@ -228,25 +529,6 @@ def main():
                                                opts.entry == "ghost_graph")
     stage_total_ms = float(stage_ms.sum())
     achieved = bytes_total / (stage_total_ms * 1e-3) / 1e9
-
-    # timed steps
-    for _ in range(args.warmup):
-        run(gx, itopk, T, opts)
-    torch.cuda.synchronize()
-    starts, ends = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        run(gx, itopk, T, opts)
-        e1.record()
-        starts.append(e0)
-        ends.append(e1)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = np.array([s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)])
-    ms_per_step = wall / args.steps * 1e3
-    qps = nq * args.steps / wall
 
     out = {
         "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -262,6 +544,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "stage_kernel", "stage_ms": [float(x) for x in stage_ms],
+                     "dense_entry_ms": float(phases[0]), "merge_ms": float(phases[-1]),
                      "bytes_per_launch": bytes_total / S,
                      "gathered_vector_GBps": vec_bytes / (stage_total_ms * 1e-3) / 1e9},
         "counters_per_query": {"n_dist": float(ctr[:, 0].mean()), "n_exp": float(ctr[:, 1].mean()),

@@ -51,6 +51,7 @@
 
 #define NONE_ID 0xFFFFFFFFu
 #define ORC_MAXS 16
+#define ORC_MAX_GIVEN 4096 /* seeds per query accepted by orc_search */
 #define NCTR 8
 
 /* ------------------------------------------------------------------ */
@@ -792,7 +793,7 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
 
   res* all = (res*)malloc(sizeof(res) * (size_t)S * (size_t)k);
   int nall = 0;
-  uint32_t seeds[1024];
+  uint32_t seeds[ORC_MAX_GIVEN + 1024 + 64]; /* given seeds, or the hand-off plus ghost seeds */
   int nseeds = 0;
   uint32_t handoff[64];
   int nhand = 0;
@@ -958,6 +959,7 @@ int orc_search(const orc_index* ix, const orc_params* P, const void* queries, in
   if (P->k < 1 || P->l < P->k || P->l > 1024 || P->r < 1 || P->r > 64 || P->T < 0) return 1;
   if (ix->S < 1 || ix->S > ORC_MAXS) return 1;
   if (P->forward_f > 64 || P->t_seeds > 1024 || P->n_init > 1024 || ix->deg > 1024) return 1;
+  if (n_given < 0 || n_given > ORC_MAX_GIVEN) return 1;
   search_ctx C = {ix, P, queries, qkeys, given_seeds, n_given, given_T, out_id, out_d, ctr, out_ghost};
   int64_t nmax = 1, gmax = 1;
   for (int s = 0; s < ix->S; s++) {
@@ -970,7 +972,8 @@ int orc_search(const orc_index* ix, const orc_params* P, const void* queries, in
   if (P->n_init > cap) cap = P->n_init;
   if (P->t_seeds > cap) cap = P->t_seeds;
   if (n_given > cap) cap = n_given;
-  if (P->forward_f > cap) cap = P->forward_f;
+  /* a later stage may take the hand-off and the ghost seeds together */
+  if (P->t_seeds + P->forward_f > cap) cap = P->t_seeds + P->forward_f;
   search_pool sp = {&C, cap, nmax, gmax};
 
   /* per-thread scratch is a pointer slot filled lazily, freed below */

@@ -70,6 +70,52 @@ __device__ __forceinline__ double shfl_xor_f64(double v, int m) {
 }
 __device__ __forceinline__ int shfl_xor_i32(int v, int m) { return __shfl_xor(v, m, 64); }
 
+// Lane i receives v from lane i ^ J (J = 1, 2, 4, ..., 32) without the LDS
+// crossbar: DPP permutes inside 16-lane rows (quad permutes, the 8-lane
+// mirror, rotation by 8) and gfx950's row-swap permutes across rows. Every
+// mapping used is an involution, so none depends on a shift direction; the
+// row swaps return the lane's own value in one output and its partner's in
+// the other, and the partner's is the one that differs (or both are equal).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "J");
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (J == 4) {
+    const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);    // row_half_mirror: i -> 7 - i
+    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);        // quad_perm [3,2,1,0]
+  } else if constexpr (J == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return r[0] == v ? r[1] : r[0];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return r[0] == v ? r[1] : r[0];
+  }
+}
+// Runtime j; inside fully unrolled loops the switch folds to one case.
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int j) {
+  switch (j) {
+    case 1: return xor_lane<1>(v);
+    case 2: return xor_lane<2>(v);
+    case 4: return xor_lane<4>(v);
+    case 8: return xor_lane<8>(v);
+    case 16: return xor_lane<16>(v);
+    default: return xor_lane<32>(v);
+  }
+}
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j) {
+  const uint32_t lo = xor_lane_u32((uint32_t)v, j), hi = xor_lane_u32((uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double xor_lane_f64(double v, int j) {
+  return __longlong_as_double((long long)xor_lane_u64((uint64_t)__double_as_longlong(v), j));
+}
+__device__ __forceinline__ int xor_lane_i32(int v, int j) { return (int)xor_lane_u32((uint32_t)v, j); }
+
 // Number of set lanes of `mask` below this lane.
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -84,7 +130,7 @@ __device__ __forceinline__ uint64_t bitonic_sort_u64(uint64_t key) {
   for (int k = 2; k <= SEG; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      uint64_t other = shfl_xor_u64(key, j);
+      uint64_t other = xor_lane_u64(key, j);
       bool up = (k == SEG) || ((lane & k) == 0);
       bool lower = (lane & j) == 0;
       uint64_t mn = other < key ? other : key;
@@ -102,7 +148,7 @@ __device__ __forceinline__ uint32_t bitonic_sort_u32(uint32_t key) {
   for (int k = 2; k <= SEG; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      uint32_t other = shfl_xor_u32(key, j);
+      uint32_t other = xor_lane_u32(key, j);
       bool up = (k == SEG) || ((lane & k) == 0);
       bool lower = (lane & j) == 0;
       uint32_t mn = other < key ? other : key;

@@ -192,7 +192,7 @@ __global__ void norms_kernel(const TIN* __restrict__ X, int64_t n, int dpf, floa
     s += x * x;
   }
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) s += shfl_xor_f64(s, o);
+  for (int o = 1; o < 64; o <<= 1) s += xor_lane_f64(s, o);
   if (lane == 0) out[v] = (float)s;
 }
 
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(256) void rescore_kernel(const uint64_t* __restrict
             acc += t * t;
           }
         }
-      acc += shfl_xor_i32(acc, 1);
-      acc += shfl_xor_i32(acc, 2);
-      acc += shfl_xor_i32(acc, 4);
+      acc += xor_lane_i32(acc, 1);
+      acc += xor_lane_i32(acc, 2);
+      acc += xor_lane_i32(acc, 4);
       dbits = (uint32_t)acc;
     } else {
       const float* qrow = (const float*)Q + (size_t)qi * bpad;
@@ -256,9 +256,9 @@ __global__ __launch_bounds__(256) void rescore_kernel(const uint64_t* __restrict
             acc = __builtin_fma((double)t, (double)t, acc);
           }
         }
-      acc += shfl_xor_f64(acc, 1);
-      acc += shfl_xor_f64(acc, 2);
-      acc += shfl_xor_f64(acc, 4);
+      acc += xor_lane_f64(acc, 1);
+      acc += xor_lane_f64(acc, 2);
+      acc += xor_lane_f64(acc, 4);
       dbits = __float_as_uint((float)acc);
     }
     if (tl == 0 && ci < kp) buf[ci] = ok ? (((uint64_t)dbits << 32) | id) : kDummy;

@@ -205,9 +205,9 @@ struct Searcher {
             qx = __builtin_amdgcn_udot4(buf[gi][m].w, qv.w, qx, false);
           }
           int part = (int)(qq8 + xx - 2u * qx);
-          part += shfl_xor_i32(part, 1);
-          part += shfl_xor_i32(part, 2);
-          part += shfl_xor_i32(part, 4);
+          part += xor_lane_i32(part, 1);
+          part += xor_lane_i32(part, 2);
+          part += xor_lane_i32(part, 4);
           dbits = (uint32_t)part;
         } else {
           double acc = 0.0;
@@ -223,9 +223,9 @@ struct Searcher {
               acc = __builtin_fma((double)t, (double)t, acc);
             }
           }
-          acc += shfl_xor_f64(acc, 1);
-          acc += shfl_xor_f64(acc, 2);
-          acc += shfl_xor_f64(acc, 4);
+          acc += xor_lane_f64(acc, 1);
+          acc += xor_lane_f64(acc, 2);
+          acc += xor_lane_f64(acc, 4);
           dbits = __float_as_uint((float)acc);
         }
         const int ci = r0 + gi * 8 + team;
@@ -397,9 +397,9 @@ struct Searcher {
             acc = __builtin_fma((double)t, (double)t, acc);
           }
         }
-      acc += shfl_xor_f64(acc, 1);
-      acc += shfl_xor_f64(acc, 2);
-      acc += shfl_xor_f64(acc, 4);
+      acc += xor_lane_f64(acc, 1);
+      acc += xor_lane_f64(acc, 2);
+      acc += xor_lane_f64(acc, 4);
       wsync();
       if (tl == 0 && ci < m && ok) pk[ci] = make_key(__float_as_uint((float)acc), id, kDone);
     }
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
     uint64_t m = cur;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t other = shfl_xor_u64(m, o);
+      const uint64_t other = xor_lane_u64(m, o);
       m = other < m ? other : m;
     }
     if (lane == 0) {

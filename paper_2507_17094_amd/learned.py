@@ -46,9 +46,9 @@ def _gather_rows(index: Index, ids):
     """Original vectors of `ids` from shard 0 (device gather through torch indexing of a view)."""
     import torch
     v = index.shard(0)
-    d, dp = v.d, v.d_pad
-    n = v.n
+    d, n = v.d, v.n
     esz = 1 if index.in_dtype == 3 else 4
+    dp = (d * esz + 127) // 128 * 128 // esz  # originals rows are padded to 128 bytes
     flat = torch.empty(n * dp * esz, dtype=torch.uint8, device="cuda")
     from . import _hip_copy
     _hip_copy(flat.data_ptr(), v.originals, n * dp * esz)
@@ -66,14 +66,22 @@ def train(index: Index, queries, labels: Labels, hidden: int = 256, epochs: int 
     return P, losses
 
 
-def predicted_search(index: Index, P: Predictor, queries, k: int, itopk: int, t: int, tau: float, t_min: int,
-                     t_max: int, opts: SearchOptions, counters: bool = False):
-    """Seeds and per-query budgets from the predictor; low-confidence queries use the ghost entry."""
+def ghost_map(index: Index):
+    """Device copy of shard 0's ghost map (ghost index -> node id), int32 view of uint32."""
     import torch
+    from . import _hip_copy
     v = index.shard(0)
     gmap = torch.empty(int(v.n_ghost), dtype=torch.int32, device="cuda")
-    from . import _hip_copy
     _hip_copy(gmap.data_ptr(), v.ghost_ids, int(v.n_ghost) * 4)
+    return gmap
+
+
+def predicted_search(index: Index, P: Predictor, queries, k: int, itopk: int, t: int, tau: float, t_min: int,
+                     t_max: int, opts: SearchOptions, counters: bool = False, gmap=None):
+    """Seeds and per-query budgets from the predictor; low-confidence queries use the ghost entry.
+    `gmap` (from ghost_map) may be passed to avoid copying the ghost map on every call."""
+    if gmap is None:
+        gmap = ghost_map(index)
     seeds, iters, conf, _ = P.predict(queries, t, tau, gmap, t_min, t_max)
     o = SearchOptions(**{**opts.__dict__, "entry": "predicted"})
     out = index.search(queries, k, itopk, t_max, o, seeds=seeds, max_iters_per_query=iters, counters=counters)
