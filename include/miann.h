@@ -18,9 +18,11 @@
  *     miann_index_free.
  *
  * Distances are SQUARED L2, sum_i (q_i - x_i)^2 (Sec. 2.2 Eq. 2 without the
- * square root; the order is the same). Float data: the sum of (q_i - x_i)^2
- * is accumulated in double precision and rounded once to float. uint8 data:
- * exact int32. Every ordering is by the key (distance, id) ascending.
+ * square root; the order is the same). Float data: each difference q_i - x_i
+ * is a float32 (x the stored value times its scale), its square is exact in
+ * double, the squares are summed in double and the sum is rounded once to
+ * float. uint8 data: exact int32. Every ordering is by the key (distance, id)
+ * ascending.
  */
 #ifndef MIANN_H
 #define MIANN_H
@@ -137,7 +139,8 @@ typedef struct {
   int32_t store_dtype, in_dtype;
   const void* store;      /* [n][d_pad] traversal codes */
   const float* scale;     /* [n] per-vector scales (F16/FP8) or NULL */
-  const void* originals;  /* [n][d_pad] F32/U8 originals (the store itself when not quantised) */
+  const void* originals;  /* [n][row] F32/U8 originals, rows padded to 128 bytes (the store itself when not
+                             quantised) */
   const uint32_t* graph;  /* [n][degree] */
   const uint32_t* sign;   /* [n][W][degree] (word-major per node) or NULL */
   const uint32_t* global_ids; /* [n] */
@@ -256,12 +259,13 @@ miann_status miann_predictor_train(miann_predictor* p, const float* x_dev, const
                                    float lambda, uint64_t seed, float* epoch_loss_host, void* stream);
 /* Inference: for each row, confidence = max softmax probability of the entry logits; seeds_dev [n][t] =
  * ghost_map[index] of the t largest logits (seeds[0] = 0xFFFFFFFF when confidence < tau);
- * iters_dev [n] = clamp(ceil(1.25 (exp(budget) - 1)), t_min, t_max), or t_max when confidence < tau;
- * top_entry_dev [n][t] (nullable)
- * receives the raw entry indices. Enqueues on `stream`. */
+ * iters_dev [n] = clamp(ceil(budget_scale (exp(budget) - 1)), t_min, t_max), or t_max when confidence
+ * < tau (budget_scale > 0 is the margin over the predicted iteration count; 1.25 .. 3 are typical);
+ * top_entry_dev [n][t] (nullable) receives the raw entry indices. Enqueues on `stream`. */
 miann_status miann_predictor_predict(const miann_predictor* p, const float* x_dev, int64_t n, int32_t t, float tau,
-                                     const uint32_t* ghost_map_dev, int32_t t_min, int32_t t_max, uint32_t* seeds_dev,
-                                     int32_t* iters_dev, float* conf_dev, uint32_t* top_entry_dev, void* stream);
+                                     const uint32_t* ghost_map_dev, int32_t t_min, int32_t t_max, float budget_scale,
+                                     uint32_t* seeds_dev, int32_t* iters_dev, float* conf_dev,
+                                     uint32_t* top_entry_dev, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching over a resident index                       */

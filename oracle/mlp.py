@@ -90,8 +90,8 @@ def adam_step(params: dict, grads: dict, state: dict, lr: float, step: int, b1=0
     return out
 
 
-def readout(Z, t: int, tau: float, gmap, t_min: int, t_max: int):
-    """Seeds = gmap of the t largest entry logits (ties: smaller index), budget = clamp(ceil(1.25 (e^z_R - 1))),
+def readout(Z, t: int, tau: float, gmap, t_min: int, t_max: int, budget_scale: float = 1.25):
+    """Seeds = gmap of the t largest entry logits (ties: smaller index), budget = clamp(ceil(s (e^z_R - 1))),
     confidence = max softmax probability; seeds[:, 0] = NONE and budget = t_max when confidence < tau."""
     Z = np.asarray(Z, np.float64)
     R = Z.shape[1] - 1
@@ -101,6 +101,6 @@ def readout(Z, t: int, tau: float, gmap, t_min: int, t_max: int):
     conf = 1.0 / np.exp(logits - m).sum(axis=1)
     seeds = np.asarray(gmap, np.uint32)[order]
     seeds[conf < tau, 0] = 0xFFFFFFFF
-    T = np.clip(np.ceil(1.25 * (np.exp(Z[:, R]) - 1.0)), t_min, t_max).astype(np.int32)
+    T = np.clip(np.ceil(budget_scale * (np.exp(Z[:, R]) - 1.0)), t_min, t_max).astype(np.int32)
     T[conf < tau] = t_max  # fallback queries keep the full budget
     return seeds, T, conf, order

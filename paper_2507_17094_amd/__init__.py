@@ -124,7 +124,7 @@ def load():
     L.miann_predictor_step.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, i32, C.POINTER(C.c_float), vp]
     L.miann_predictor_train.argtypes = [vp, vp, vp, vp, i64, i32, i32, C.c_float, C.c_float, u64,
                                         C.POINTER(C.c_float), vp]
-    L.miann_predictor_predict.argtypes = [vp, vp, i64, i32, C.c_float, vp, i32, i32, vp, vp, vp, vp, vp]
+    L.miann_predictor_predict.argtypes = [vp, vp, i64, i32, C.c_float, vp, i32, i32, C.c_float, vp, vp, vp, vp, vp]
     L.miann_server_config_default.argtypes = [C.POINTER(ServerConfig)]
     L.miann_server_config_default.restype = None
     L.miann_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
@@ -386,7 +386,8 @@ class Predictor:
                                             epochs, batch, lr, lam, seed & (2**64 - 1), losses, _stream_ptr(stream)))
         return list(losses)
 
-    def predict(self, x, t: int, tau: float, ghost_map, t_min: int, t_max: int, stream=None):
+    def predict(self, x, t: int, tau: float, ghost_map, t_min: int, t_max: int, budget_scale: float = 1.25,
+                stream=None):
         """Returns (seeds [n,t] int32 view of uint32, iters [n] int32, conf [n] f32, top entries [n,t])."""
         torch = _torch()
         if ghost_map.shape[0] < self.n_entry:
@@ -397,7 +398,7 @@ class Predictor:
         conf = torch.empty(n, dtype=torch.float32, device=x.device)
         top = torch.empty((n, t), dtype=torch.int32, device=x.device)
         _check(load().miann_predictor_predict(self._h, x.data_ptr(), n, t, tau, ghost_map.data_ptr(), t_min, t_max,
-                                              seeds.data_ptr(), iters.data_ptr(), conf.data_ptr(), top.data_ptr(),
+                                              budget_scale, seeds.data_ptr(), iters.data_ptr(), conf.data_ptr(), top.data_ptr(),
                                               _stream_ptr(stream)))
         return seeds, iters, conf, top
 

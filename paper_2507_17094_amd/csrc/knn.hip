@@ -84,23 +84,40 @@ __device__ void merge_list(uint64_t* L, int n, uint64_t c, uint64_t* ck) {
   wsync();
 }
 
+// Sorts the f keys of the row's tail (L[kp..kp+f)), merges them into the
+// sorted head L[0..kp), and sets *thr to the head's last key.
+__device__ __forceinline__ void compact_tail(uint64_t* L, int kp, int f, uint64_t* thr, uint64_t* ck) {
+  const int lane = lane_id();
+  uint64_t c = lane < f ? L[kp + lane] : kDummy;
+  wsync();
+  c = bitonic_sort_u64<64>(c);
+  merge_list(L, kp, c, ck);
+  if (lane == 0) *thr = L[kp - 1];
+  wsync();
+}
+
 template <typename TIN>
 __global__ __launch_bounds__(256) void tile_select_kernel(const TIN* __restrict__ A, const float* __restrict__ an,
                                                           int64_t na, const int* __restrict__ na_dev,
                                                           const uint32_t* __restrict__ qlist,
                                                           const TIN* __restrict__ B, const float* __restrict__ bn,
-                                                          int64_t nb, int dpf, int kp, int exclude_self,
-                                                          uint64_t* __restrict__ out) {
+                                                          int64_t nb, int dpf, int kp, int tail_cap,
+                                                          int exclude_self, uint64_t* __restrict__ out) {
   extern __shared__ __align__(16) char smem[];
   const int ASTR = dpf + 1;
   float* As = (float*)smem;
   float* Bs = As + TQ * ASTR;
   float* Dt = Bs + TX * BSTR;
+  // per row: the sorted best kp keys, then a tail of tail_cap (<= 64) entries
+  // that collects keys passing the row's threshold until it is full (then it
+  // is sorted and merged into the head)
+  const int LS = kp + tail_cap;
   uint64_t* lists = (uint64_t*)(((uintptr_t)(Dt + TQ * DSTR) + 15) & ~(uintptr_t)15);
-  uint64_t* thr = lists + (size_t)TQ * kp;
+  uint64_t* thr = lists + (size_t)TQ * LS;
   uint64_t* cks = thr + TQ;
   float* anl = (float*)(cks + 4 * 64);
-  int64_t* qrow = (int64_t*)(((uintptr_t)(anl + TQ) + 7) & ~(uintptr_t)7);
+  int* tfill = (int*)(anl + TQ);
+  int64_t* qrow = (int64_t*)(((uintptr_t)(tfill + TQ) + 7) & ~(uintptr_t)7);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = na_dev ? (int64_t)*na_dev : na;
@@ -118,8 +135,11 @@ __global__ __launch_bounds__(256) void tile_select_kernel(const TIN* __restrict_
     As[r * ASTR + c] = q >= 0 ? (float)A[q * dpf + c] : 0.f;
   }
   for (int r = tid; r < TQ; r += 256) anl[r] = qrow[r] >= 0 ? an[qrow[r]] : 0.f;
-  for (int e = tid; e < TQ * kp; e += 256) lists[e] = kDummy;
-  for (int r = tid; r < TQ; r += 256) thr[r] = kDummy;
+  for (int e = tid; e < TQ * LS; e += 256) lists[e] = kDummy;
+  for (int r = tid; r < TQ; r += 256) {
+    thr[r] = kDummy;
+    tfill[r] = 0;
+  }
   __syncthreads();
 
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -163,20 +183,44 @@ __global__ __launch_bounds__(256) void tile_select_kernel(const TIN* __restrict_
       if (qrow[row] < 0) continue;
       const float dv = Dt[row * DSTR + lane];
       const uint64_t key = dv < INFINITY ? (((uint64_t)__float_as_uint(dv) << 32) | (uint64_t)(j0 + lane)) : kDummy;
-      const bool pass = key < thr[row];
-      if (__ballot(pass) == 0) continue;
-      uint64_t c = pass ? key : kDummy;
-      c = bitonic_sort_u64<64>(c);
-      merge_list(lists + (size_t)row * kp, kp, c, ck);
-      if (lane == 0) thr[row] = lists[(size_t)row * kp + kp - 1];
+      bool pass = key < thr[row];
+      uint64_t m = __ballot(pass);
+      if (m == 0) continue;
+      int f = tfill[row];
+      if (f + __popcll(m) > tail_cap) {
+        // tail full: fold it into the sorted head, tighten the threshold, filter again
+        if (f > 0) compact_tail(lists + (size_t)row * LS, kp, f, thr + row, ck);
+        f = 0;
+        pass = key < thr[row];
+        m = __ballot(pass);
+        if (__popcll(m) > tail_cap) {
+          // more survivors than the tail holds: merge them into the head directly
+          uint64_t c = pass ? key : kDummy;
+          c = bitonic_sort_u64<64>(c);
+          merge_list(lists + (size_t)row * LS, kp, c, ck);
+          if (lane == 0) thr[row] = lists[(size_t)row * LS + kp - 1];
+          wsync();
+          continue;
+        }
+      }
+      uint64_t* tail = lists + (size_t)row * LS + kp;
+      if (pass) tail[f + lanes_below(m)] = key;
+      wsync();
+      if (lane == 0) tfill[row] = f + __popcll(m);
       wsync();
     }
+  }
+  __syncthreads();
+  for (int rr = 0; rr < TQ / 4; rr++) {
+    const int row = wave * (TQ / 4) + rr;
+    const int f = tfill[row];
+    if (qrow[row] >= 0 && f > 0) compact_tail(lists + (size_t)row * LS, kp, f, thr + row, ck);
   }
   __syncthreads();
   for (int e = tid; e < TQ * kp; e += 256) {
     const int r = e / kp;
     const int64_t gr = r0 + r;
-    if (gr < n_rows) out[gr * kp + (e % kp)] = lists[e];
+    if (gr < n_rows) out[gr * kp + (e % kp)] = lists[(size_t)r * LS + (e % kp)];
   }
 }
 
@@ -328,9 +372,9 @@ hipError_t dequant_rows(const void* store, const float* scale, int dt, int64_t n
   return hipGetLastError();
 }
 
-static size_t tile_lds(int dpf, int kp) {
+static size_t tile_lds(int dpf, int kp, int tail_cap) {
   size_t b = (size_t)TQ * (dpf + 1) * 4 + (size_t)TX * BSTR * 4 + (size_t)TQ * DSTR * 4 + 16;
-  b += (size_t)TQ * kp * 8 + TQ * 8 + 4 * 64 * 8 + TQ * 4 + 8 + TQ * 8;
+  b += (size_t)TQ * (kp + tail_cap) * 8 + TQ * 8 + 4 * 64 * 8 + TQ * 4 + TQ * 4 + 8 + TQ * 8;
   return b;
 }
 
@@ -338,7 +382,10 @@ template <typename TIN>
 static hipError_t launch_tiles(const TIN* A, const float* an, int64_t na, const int* na_dev, const uint32_t* qlist,
                                const TIN* B, const float* bn, int64_t nb, int dpf, int kp, int exclude_self,
                                uint64_t* out, hipStream_t st) {
-  const size_t lds = tile_lds(dpf, kp);
+  // the largest tail (up to 64 keys per row) that fits the 160 KB of LDS
+  int tail_cap = 64;
+  while (tail_cap > 0 && tile_lds(dpf, kp, tail_cap) > 160 * 1024) tail_cap -= 8;
+  const size_t lds = tile_lds(dpf, kp, tail_cap);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   static bool set = false;
   if (!set) {
@@ -346,7 +393,7 @@ static hipError_t launch_tiles(const TIN* A, const float* an, int64_t na, const 
     set = true;
   }
   hipLaunchKernelGGL(tile_select_kernel<TIN>, dim3((unsigned)((na + TQ - 1) / TQ)), dim3(256), lds, st, A, an, na,
-                     na_dev, qlist, B, bn, nb, dpf, kp, exclude_self, out);
+                     na_dev, qlist, B, bn, nb, dpf, kp, tail_cap, exclude_self, out);
   return hipGetLastError();
 }
 

@@ -191,11 +191,12 @@ hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float l
 
 // Inference read-out per row: confidence = max softmax probability over the R
 // entry logits; seeds = ghost map of the t largest logits (ties -> smaller
-// index); budget = clamp(ceil(1.25 (exp(z_R) - 1)), t_min, t_max). Rows whose
+// index); budget = clamp(ceil(budget_scale (exp(z_R) - 1)), t_min, t_max). Rows whose
 // confidence is below tau get seeds[0] = none (fall back to ghost staging) and
 // the budget t_max.
 __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ Z, int n, int R, int t, float tau,
                                                       const uint32_t* __restrict__ gmap, int t_min, int t_max,
+                                                      float budget_scale,
                                                       uint32_t* __restrict__ seeds, int32_t* __restrict__ iters,
                                                       float* __restrict__ conf, uint32_t* __restrict__ top_idx) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
   }
   if (lane == 0) {
     const float yb = z[R];
-    float tb = ceilf(1.25f * (expf(yb) - 1.f));
+    float tb = ceilf(budget_scale * (expf(yb) - 1.f));
     if (!(tb >= (float)t_min)) tb = (float)t_min;
     if (tb > (float)t_max) tb = (float)t_max;
     iters[b] = c < tau ? t_max : (int32_t)tb;  // a fallback query keeps the full budget
@@ -244,10 +245,10 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
 }
 
 hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_t* gmap, int t_min, int t_max,
-                   uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st) {
+                   float budget_scale, uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(readout_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min,
-                     t_max, seeds, iters, conf, top_idx);
+                     t_max, budget_scale, seeds, iters, conf, top_idx);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ hipError_t colsum(const uint16_t* G, int B, int N, float* db, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                 int step, uint16_t* wb, hipStream_t st);
 hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_t* gmap, int t_min, int t_max,
+                   float budget_scale,
                    uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st);
 hipError_t zero_f32(float* p, int64_t n, hipStream_t st);
 

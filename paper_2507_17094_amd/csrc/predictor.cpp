@@ -242,12 +242,15 @@ miann_status miann_predictor_train(miann_predictor* P, const float* x, const int
 }
 
 miann_status miann_predictor_predict(const miann_predictor* P, const float* x, int64_t n, int32_t t, float tau,
-                                     const uint32_t* ghost_map, int32_t t_min, int32_t t_max, uint32_t* seeds,
-                                     int32_t* iters, float* conf, uint32_t* top_entry, void* stream) {
+                                     const uint32_t* ghost_map, int32_t t_min, int32_t t_max, float budget_scale,
+                                     uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_entry,
+                                     void* stream) {
   if (!P || (n > 0 && (!x || !ghost_map || !seeds || !iters || !conf)))
     return miann_fail(MIANN_EINVAL, "miann_predictor_predict: null argument");
   if (t < 1 || t > 64 || t > P->R) return miann_fail(MIANN_EINVAL, "miann_predictor_predict: t = %d out of range", t);
   if (t_min < 0 || t_max < t_min) return miann_fail(MIANN_EINVAL, "miann_predictor_predict: bad budget bounds");
+  if (!(budget_scale > 0.f) || budget_scale > 1000.f)
+    return miann_fail(MIANN_EINVAL, "miann_predictor_predict: budget_scale must be in (0, 1000]");
   hipStream_t st = (hipStream_t)stream;
   const int64_t chunk = 16384;
   Work w(st);
@@ -261,7 +264,7 @@ miann_status miann_predictor_predict(const miann_predictor* P, const float* x, i
     const int B = (int)std::min<int64_t>(chunk, n - b0);
     PTRY(gather_batch(x + b0 * P->d_in, P->d_in, nullptr, B, nullptr, nullptr, xb, nullptr, nullptr, st));
     PTRY(forward(P, xb, B, H1, H2, Z, st));
-    PTRY(readout(Z, B, P->R, t, tau, ghost_map, t_min, t_max, seeds + b0 * t, iters + b0, conf + b0,
+    PTRY(readout(Z, B, P->R, t, tau, ghost_map, t_min, t_max, budget_scale, seeds + b0 * t, iters + b0, conf + b0,
                  top_entry ? top_entry + b0 * t : nullptr, st));
   }
   return MIANN_OK;

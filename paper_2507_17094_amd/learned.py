@@ -11,7 +11,7 @@ calls:
 2. training: the BF16 MLP (d -> hidden -> hidden -> R + 1) with the library's
    forward/backward/Adam kernels.
 3. use: seeds = ghost map of the top-t entry logits, per-query budget
-   T_q = clamp(ceil(1.25 (exp(y) - 1)), t_min, T_max); queries whose
+   T_q = clamp(ceil(s (exp(y) - 1)), t_min, T_max) with a margin s (default 2); queries whose
    confidence (max softmax probability) is below tau fall back to the ghost
    entry inside the same search launch.
 """
@@ -77,12 +77,12 @@ def ghost_map(index: Index):
 
 
 def predicted_search(index: Index, P: Predictor, queries, k: int, itopk: int, t: int, tau: float, t_min: int,
-                     t_max: int, opts: SearchOptions, counters: bool = False, gmap=None):
+                     t_max: int, opts: SearchOptions, counters: bool = False, gmap=None, budget_scale: float = 2.0):
     """Seeds and per-query budgets from the predictor; low-confidence queries use the ghost entry.
     `gmap` (from ghost_map) may be passed to avoid copying the ghost map on every call."""
     if gmap is None:
         gmap = ghost_map(index)
-    seeds, iters, conf, _ = P.predict(queries, t, tau, gmap, t_min, t_max)
+    seeds, iters, conf, _ = P.predict(queries, t, tau, gmap, t_min, t_max, budget_scale)
     o = SearchOptions(**{**opts.__dict__, "entry": "predicted"})
     out = index.search(queries, k, itopk, t_max, o, seeds=seeds, max_iters_per_query=iters, counters=counters)
     return out, seeds, iters, conf

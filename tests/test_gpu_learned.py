@@ -1,8 +1,11 @@
 """The learned entry / budget predictor end to end: labels from traces of the
 search itself, training by the library's kernels, and the predicted-entry search
 on held-out queries. Checks (1) parity of the predicted-entry search with the
-oracle given the same seeds and budgets, and (2) the gain over ghost staging:
-fewer distance evaluations at no loss of recall."""
+oracle given the same seeds and budgets, and (2) what the network gains over
+ghost staging: at the same iteration cap the predicted entry reaches at least
+ghost staging's recall with fewer distance evaluations, and with per-query
+budgets it stays within 0.005 of ghost staging's full-budget recall at a
+fifth fewer distance evaluations."""
 import numpy as np
 import pytest
 
@@ -14,6 +17,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 miann = pytest.importorskip("paper_2507_17094_amd")
 from paper_2507_17094_amd import learned  # noqa: E402
+
+
+def cost(c):
+    """distance evaluations per query, main graph plus ghost stage"""
+    c = c.cpu().numpy()
+    return float((c[:, 0] + c[:, 4]).mean())
 
 
 def test_predictor_gain_over_ghost_staging():
@@ -31,29 +40,37 @@ def test_predictor_gain_over_ghost_staging():
     labels = learned.make_labels(gx, tr, k, itopk, T, opts)
     P, losses = learned.train(gx, tr, labels, hidden=128, epochs=12, batch=2048, lr=2e-3)
     say(f"  losses {[round(x, 3) for x in losses]}")
-    assert losses[-1] < losses[0]
+    assert losses[-1] < 0.5 * losses[0]
     gt, _ = gx.exact_knn(te, k)
     gt = gt.cpu().numpy().view(np.uint32)
+
+    def rec(ids):
+        return oracle.recall(gt, ids.cpu().numpy().view(np.uint32), k)
+
+    gmap = learned.ghost_map(gx)
+    po = miann.SearchOptions(entry="predicted", dgs=True)
+    # (a) entry only: the same iteration cap for both
+    seeds, _, conf, _ = P.predict(te, 32, 0.0, gmap, 4, T)
+    for Tc in (32, 64):
+        b = gx.search(te, k, itopk, Tc, opts, counters=True)
+        p = gx.search(te, k, itopk, Tc, po, seeds=seeds, counters=True)
+        say(f"  cap {Tc}: ghost staging recall {rec(b[0]):.4f} dists {cost(b[2]):.0f} | "
+            f"predicted entry recall {rec(p[0]):.4f} dists {cost(p[2]):.0f}")
+        assert rec(p[0]) >= rec(b[0]) - 0.002
+        assert cost(p[2]) < cost(b[2])
+    # (b) entry and per-query budget against ghost staging at the full budget
     base = gx.search(te, k, itopk, T, opts, counters=True)
-    (pi, pd, pc), seeds, iters, conf = learned.predicted_search(gx, P, te, k, itopk, 32, 0.05, 4, T, opts,
-                                                                counters=True)
-    torch.cuda.synchronize()
-    rb = oracle.recall(gt, base[0].cpu().numpy().view(np.uint32), k)
-    rp = oracle.recall(gt, pi.cpu().numpy().view(np.uint32), k)
-    cb = base[2].cpu().numpy()
-    cp = pc.cpu().numpy()
-    cost_b = (cb[:, 0] + cb[:, 4]).mean()
-    cost_p = (cp[:, 0] + cp[:, 4]).mean()
-    fb = float((conf.cpu().numpy() < 0.05).mean())
-    say(f"  ghost staging: recall {rb:.4f}, distances/query {cost_b:.1f}, iterations {cb[:, 2].mean():.1f}")
-    say(f"  predictor:     recall {rp:.4f}, distances/query {cost_p:.1f}, iterations {cp[:, 2].mean():.1f}, "
-        f"fallback {fb:.3f}")
-    assert rp >= rb - 0.01
-    assert cost_p < cost_b
+    (pi, pd, pc), seeds2, iters, conf2 = learned.predicted_search(gx, P, te, k, itopk, 32, 0.05, 4, T, opts,
+                                                                  counters=True, gmap=gmap, budget_scale=3.0)
+    rb, rp = rec(base[0]), rec(pi)
+    fb = float((conf2.cpu().numpy() < 0.05).mean())
+    say(f"  full budget: ghost staging recall {rb:.4f} dists {cost(base[2]):.0f}; predictor recall {rp:.4f} "
+        f"dists {cost(pc):.0f} mean budget {iters.float().mean().item():.1f} fallback {fb:.3f}")
+    assert rp >= rb - 0.005
+    assert cost(pc) < 0.8 * cost(base[2])
     # parity of the predicted-entry search with the oracle on the same seeds and budgets
     ox = oracle_from_device(gx, X)
-    po = miann.SearchOptions(**{**opts.__dict__, "entry": "predicted"})
-    oi, od, oc = oracle.search(ox, Qte, seeds=seeds.cpu().numpy().view(np.uint32),
+    oi, od, oc = oracle.search(ox, Qte, seeds=seeds2.cpu().numpy().view(np.uint32),
                                T_per_query=iters.cpu().numpy(), **oracle_kwargs(k, itopk, T, po))
     same = np.all(pi.cpu().numpy().view(np.uint32) == oi, axis=1).mean()
     say(f"  parity with the oracle: {same:.4f}")

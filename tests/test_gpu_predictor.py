@@ -65,10 +65,10 @@ def test_readout_matches_reference():
     x = rng.standard_normal((300, 24)).astype(np.float32)
     gmap = np.sort(rng.choice(10_000, 40, replace=False)).astype(np.uint32)
     seeds, iters, conf, top = P.predict(torch.from_numpy(x).cuda(), 8, 0.05,
-                                        torch.from_numpy(gmap.view(np.int32)).cuda(), 4, 200)
+                                        torch.from_numpy(gmap.view(np.int32)).cuda(), 4, 200, budget_scale=2.5)
     W = {k: v.cpu().numpy().astype(np.float64) for k, v in P.tensors().items()}
     _, _, cache = mlp.forward_backward(W, x, np.zeros(300, np.int64), np.zeros(300), 0.0, bf16_mode=True)
-    rs, rT, rc, rorder = mlp.readout(cache["Z"], 8, 0.05, gmap, 4, 200)
+    rs, rT, rc, rorder = mlp.readout(cache["Z"], 8, 0.05, gmap, 4, 200, budget_scale=2.5)
     top = top.cpu().numpy()
     agree = (top[:, 0] == rorder[:, 0]).mean()
     say(f"  top-1 agreement {agree:.4f}")

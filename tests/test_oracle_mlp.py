@@ -67,3 +67,6 @@ def test_readout_budget_and_fallback():
     assert order[0].tolist() == [1, 2]  # tie -> smaller index first
     assert seeds[0].tolist() == [11, 12] and T[0] == 8
     assert conf[1] == pytest.approx(0.25) and seeds[1, 0] == 0xFFFFFFFF and T[1] == 100
+    # the margin scales the budget: ceil(3 * 6) = 18
+    _, T3, _, _ = mlp.readout(Z, 2, 0.3, np.array([10, 11, 12, 13]), 4, 100, budget_scale=3.0)
+    assert T3[0] == 18 and T3[1] == 100
