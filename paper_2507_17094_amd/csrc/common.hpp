@@ -96,6 +96,15 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     return r[0] == v ? r[1] : r[0];
   }
 }
+// Lane i receives v from lane 63 - i: the row mirror (i -> 15 - i inside each
+// 16-lane row) followed by swapping rows 0 <-> 3 and 1 <-> 2.
+__device__ __forceinline__ uint32_t reverse_lanes_u32(uint32_t v) {
+  const uint32_t m = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return xor_lane<32>(xor_lane<16>(m));
+}
+__device__ __forceinline__ uint64_t reverse_lanes_u64(uint64_t v) {
+  return ((uint64_t)reverse_lanes_u32((uint32_t)(v >> 32)) << 32) | reverse_lanes_u32((uint32_t)v);
+}
 // Runtime j; inside fully unrolled loops the switch folds to one case.
 __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int j) {
   switch (j) {
@@ -155,6 +164,58 @@ __device__ __forceinline__ uint32_t bitonic_sort_u32(uint32_t key) {
       uint32_t mx = other < key ? key : other;
       key = (lower == up) ? mn : mx;
     }
+  }
+  return key;
+}
+
+// Bitonic sort of 64 * NR u64 keys held NR per lane (key index r * 64 + lane),
+// ascending over the whole wave.
+template <int NR>
+__device__ __forceinline__ void bitonic_sort_regs(uint64_t (&v)[NR]) {
+  const int lane = lane_id();
+  constexpr int N = 64 * NR;
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int jr = j >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          if ((r & jr) == 0) {
+            const int p = r | jr;
+            const bool up = (((r << 6) | lane) & k) == 0;
+            const uint64_t a = v[r], b = v[p];
+            const bool sw = (a > b) == up;
+            v[r] = sw ? b : a;
+            v[p] = sw ? a : b;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          const uint64_t other = xor_lane_u64(v[r], j);
+          const bool up = (((r << 6) | lane) & k) == 0;
+          const bool lower = (lane & j) == 0;
+          const uint64_t mn = other < v[r] ? other : v[r];
+          const uint64_t mx = other < v[r] ? v[r] : other;
+          v[r] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
+// Sorts a bitonic sequence of 64 keys (one per lane) ascending.
+__device__ __forceinline__ uint64_t bitonic_merge_u64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 32; j > 0; j >>= 1) {
+    const uint64_t other = xor_lane_u64(key, j);
+    const bool lower = (lane & j) == 0;
+    const uint64_t mn = other < key ? other : key;
+    const uint64_t mx = other < key ? key : other;
+    key = lower ? mn : mx;
   }
   return key;
 }

@@ -449,6 +449,134 @@ hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// Dense ghost entry. The queries-by-ghosts contraction is a plain GEMM: tiles
+// of 64 query rows x 64 ghosts on v_mfma_f32_32x32x2_f32 write the GEMM-form
+// distances |q|^2 + |g|^2 - 2 q.g of a block of rows to D. One wave per row
+// then selects the kp smallest (dist, ghost) keys of its row: the kp-th
+// smallest of the two smallest keys of each lane's columns bounds the row's
+// kp-th smallest key from above, the keys at or below the bound are collected
+// and sorted, and if more than CAP pass, the bound is lowered to the kp-th
+// smallest of the first CAP collected and the row scanned again.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void dense_gemm_kernel(const float* __restrict__ Q, const float* __restrict__ qn,
+                                                         const int* __restrict__ nrows_dev, int64_t nrows_max,
+                                                         const uint32_t* __restrict__ qlist, int64_t row0,
+                                                         int64_t rows_chunk, const float* __restrict__ G,
+                                                         const float* __restrict__ gn, int64_t R, int dpf,
+                                                         int64_t ldd, float* __restrict__ D) {
+  __shared__ float As[64 * BSTR];
+  __shared__ float Bs[64 * BSTR];
+  __shared__ int64_t qrow[64];
+  __shared__ float qnl[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  const int64_t rl0 = (int64_t)blockIdx.y * 64;  // first row of the tile within the chunk
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk) return;
+  for (int r = tid; r < 64; r += 256) {
+    const int64_t gr = row0 + rl0 + r;
+    const bool ok = gr < n_rows && rl0 + r < rows_chunk;
+    qrow[r] = ok ? (qlist ? (int64_t)qlist[gr] : gr) : -1;
+    qnl[r] = ok ? qn[qrow[r]] : 0.f;
+  }
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 31, lk = lane >> 5;
+  floatx16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; j++) acc[j] = 0.f;
+  for (int kc = 0; kc < dpf; kc += KC) {
+    __syncthreads();
+    for (int e = tid; e < 64 * KC; e += 256) {
+      const int r = e / KC, c = e % KC;
+      const int64_t q = qrow[r];
+      As[r * BSTR + c] = (q >= 0 && kc + c < dpf) ? Q[q * dpf + kc + c] : 0.f;
+      const int64_t g = c0 + r;
+      Bs[r * BSTR + c] = (g < R && kc + c < dpf) ? G[g * dpf + kc + c] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; kk += 2) {
+      const float av = As[(wr + li) * BSTR + kk + lk];
+      const float bv = Bs[(wc + li) * BSTR + kk + lk];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int row = wr + 8 * (j >> 2) + 4 * lk + (j & 3);
+    const int64_t col = c0 + wc + li;
+    if (qrow[row] >= 0 && col < R) {
+      float dv = qnl[row] + gn[col] - 2.f * acc[j];
+      D[(rl0 + row) * ldd + col] = dv < 0.f ? 0.f : dv;
+    }
+  }
+}
+
+template <int CAP>
+__global__ __launch_bounds__(256) void dense_select_kernel(const float* __restrict__ D, int64_t ldd, int64_t R,
+                                                           const int* __restrict__ nrows_dev, int64_t nrows_max,
+                                                           int64_t row0, int64_t rows_chunk, int kp,
+                                                           uint64_t* __restrict__ out) {
+  constexpr int NR = CAP / 64;
+  __shared__ uint64_t bufs[4 * CAP];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t rl = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  if (rl >= rows_chunk || row0 + rl >= n_rows) return;
+  uint64_t* buf = bufs + wave * CAP;
+  const float* d = D + rl * ldd;
+  auto mk = [](float v, int64_t j) { return ((uint64_t)__float_as_uint(v) << 32) | (uint64_t)j; };
+  // the two smallest keys of this lane's columns
+  uint64_t m[2] = {kDummy, kDummy};
+  for (int64_t j = lane; j < R; j += 64) {
+    const uint64_t key = mk(d[j], j);
+    if (key < m[0]) {
+      m[1] = m[0];
+      m[0] = key;
+    } else if (key < m[1]) {
+      m[1] = key;
+    }
+  }
+  bitonic_sort_regs<2>(m);
+  const int rb = (kp - 1) >> 6, lb = (kp - 1) & 63;
+  uint64_t bound = shfl_u64(rb == 0 ? m[0] : m[1], lb);
+  uint64_t v[NR];
+  for (;;) {
+    int cnt = 0;
+    for (int64_t j0 = 0; j0 < R; j0 += 64) {
+      const int64_t j = j0 + lane;
+      const uint64_t key = j < R ? mk(d[j], j) : kDummy;
+      const bool pass = key != kDummy && key <= bound;
+      const uint64_t bm = ballot(pass);
+      const int pos = cnt + lanes_below(bm);
+      if (pass && pos < CAP) buf[pos] = key;
+      cnt += __popcll(bm);
+    }
+    wsync();
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      const int i = r * 64 + lane;
+      v[r] = i < cnt && i < CAP ? buf[i] : kDummy;
+    }
+    wsync();
+    bitonic_sort_regs<NR>(v);
+    if (cnt <= CAP) break;
+    // more than CAP keys at or below the bound: the kp-th smallest of the first CAP is a lower bound
+    uint64_t x = v[0];
+#pragma unroll
+    for (int r = 1; r < NR; r++)
+      if (r == rb) x = v[r];
+    bound = shfl_u64(x, lb);
+  }
+  uint64_t* o = out + (row0 + rl) * kp;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int i = r * 64 + lane;
+    if (i < kp) o[i] = v[r];
+  }
+}
+
 __global__ void shard_qlist_kernel(int64_t nq, const uint64_t* __restrict__ qkeys, int S, int shard, int all,
                                    uint32_t* __restrict__ list, int* __restrict__ count) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -518,7 +646,21 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
     hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, g_f32, R, d_pad_f32, gn);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = launch_tiles<float>(qf, qn, nq, cnt, list, g_f32, gn, R, d_pad_f32, kp, 0, cand, st);
+  // GEMM-form distances of blocks of rows against all ghosts, then per-row selection of kp candidates
+  const int64_t ldd = (R + 63) / 64 * 64;
+  int64_t chunk = ((int64_t)1 << 27) / ldd;  // at most 512 MB of distances at a time
+  chunk = chunk < 64 ? 64 : chunk / 64 * 64;
+  if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
+  float* D = nullptr;
+  if (e == hipSuccess) e = hipMallocAsync((void**)&D, (size_t)chunk * ldd * 4, st);
+  for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
+    hipLaunchKernelGGL(dense_gemm_kernel, dim3((unsigned)(ldd / 64), (unsigned)(chunk / 64)), dim3(256), 0, st, qf,
+                       qn, cnt, nq, list, row0, chunk, g_f32, gn, R, d_pad_f32, ldd, D);
+    hipLaunchKernelGGL(dense_select_kernel<256>, dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, D, ldd, R, cnt,
+                       nq, row0, chunk, kp, cand);
+    e = hipGetLastError();
+  }
+  if (D) hipFreeAsync(D, st);
   if (e == hipSuccess)
     e = launch_rescore(store_dt, cand, nq, cnt, kp, list, qraw, g_store, g_scale, d_pad, t, best, st);
   if (e == hipSuccess) {

@@ -144,6 +144,45 @@ struct Searcher {
     return (ballot(in) != 0 ? 1 : 0) | (ballot(in && newpos < a.k) != 0 ? 2 : 0);
   }
 
+  // The same merge for l <= 64 without LDS searches: p (one entry per lane)
+  // and the reversed candidates form a bitonic sequence; the elementwise
+  // minimum and maximum are its lower and upper 64 keys, each sorted by a
+  // half-cleaner network. In the sorted 128 keys a key whose (dist, id)
+  // equals the next one's is dropped (the later copy has the larger flag:
+  // p's entry), and the first l survivors become the new p.
+  __device__ __forceinline__ int merge_sorted_small(uint64_t c, int l) {
+    const uint64_t pv = lane < l ? pk[lane] : kDummy;
+    const uint64_t cr = reverse_lanes_u64(c);
+    uint64_t lo = pv < cr ? pv : cr;
+    uint64_t hi = pv < cr ? cr : pv;
+    lo = bitonic_merge_u64(lo);
+    hi = bitonic_merge_u64(hi);
+    // the next key of the sorted 128: lo[i+1], hi[0] after lo[63], hi[i+1]
+    const int nx = (lane + 1) & 63;
+    const uint64_t lo_n = shfl_u64(lo, nx), hi_n = shfl_u64(hi, nx);
+    const uint64_t lo_next = lane == 63 ? hi_n : lo_n;  // hi_n at lane 63 is hi[0]
+    const uint64_t hi_next = lane == 63 ? kDummy : hi_n;
+    const bool keep_lo = lo == kDummy || key_noflag(lo) != key_noflag(lo_next);
+    const bool keep_hi = hi == kDummy || key_noflag(hi) != key_noflag(hi_next);
+    const uint64_t mlo = ballot(keep_lo), mhi = ballot(keep_hi);
+    const int pos_lo = lanes_below(mlo);
+    const int pos_hi = __popcll(mlo) + lanes_below(mhi);
+    if (keep_lo && pos_lo < l) pk_alt[pos_lo] = lo;
+    if (keep_hi && pos_hi < l) pk_alt[pos_hi] = hi;
+    wsync();
+    const uint64_t nv = lane < l ? pk_alt[lane] : kDummy;
+    const bool diff = nv != pv;
+    const int changed = (ballot(diff) != 0 ? 1 : 0) | (ballot(diff && lane < a.k) != 0 ? 2 : 0);
+    uint64_t* t = pk;
+    pk = pk_alt;
+    pk_alt = t;
+    return changed;
+  }
+
+  __device__ __forceinline__ int merge(uint64_t c, int l) {
+    return l <= 64 ? merge_sorted_small(c, l) : merge_sorted(c, l);
+  }
+
   // ---------------------------------------------------------------- distances
   __device__ __forceinline__ void load_query(const void* qptr) {
     const int d = a.d;
@@ -248,8 +287,8 @@ struct Searcher {
     ctr[0] += nc;
     uint64_t key = lane < nc ? ck[lane] : kDummy;
     wsync();
-    key = nc > 32 ? bitonic_sort_u64<64>(key) : bitonic_sort_u64<32>(key);
-    return merge_sorted(key, l);
+    key = nc > 32 ? bitonic_sort_u64<64>(key) : (nc > 16 ? bitonic_sort_u64<32>(key) : bitonic_sort_u64<16>(key));
+    return merge(key, l);
   }
 
   // Seeds whose distance is already known (one key per lane, kDummy = none).
@@ -257,7 +296,7 @@ struct Searcher {
     const bool take = visit(key != kDummy, key_id(key));
     key = take ? key : kDummy;
     key = bitonic_sort_u64<64>(key);
-    merge_sorted(key, l);
+    merge(key, l);
   }
 
   __device__ __forceinline__ void random_init(const GraphCtx& g, uint64_t stream, int n_init, int l) {
