@@ -139,12 +139,11 @@ __device__ __forceinline__ uint64_t bitonic_sort_u64(uint64_t key) {
   for (int k = 2; k <= SEG; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      uint64_t other = xor_lane_u64(key, j);
-      bool up = (k == SEG) || ((lane & k) == 0);
-      bool lower = (lane & j) == 0;
-      uint64_t mn = other < key ? other : key;
-      uint64_t mx = other < key ? key : other;
-      key = (lower == up) ? mn : mx;
+      // the lane keeps the smaller key iff it is the lower lane of an ascending pair or the upper
+      // of a descending one; one compare decides, the lane pattern is a scalar mask
+      const uint64_t other = xor_lane_u64(key, j);
+      const bool want_min = ((lane & j) == 0) == ((k == SEG) || ((lane & k) == 0));
+      key = ((other < key) == want_min) ? other : key;
     }
   }
   return key;
@@ -157,12 +156,9 @@ __device__ __forceinline__ uint32_t bitonic_sort_u32(uint32_t key) {
   for (int k = 2; k <= SEG; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      uint32_t other = xor_lane_u32(key, j);
-      bool up = (k == SEG) || ((lane & k) == 0);
-      bool lower = (lane & j) == 0;
-      uint32_t mn = other < key ? other : key;
-      uint32_t mx = other < key ? key : other;
-      key = (lower == up) ? mn : mx;
+      const uint32_t other = xor_lane_u32(key, j);
+      const bool want_min = ((lane & j) == 0) == ((k == SEG) || ((lane & k) == 0));
+      key = ((other < key) == want_min) ? other : key;
     }
   }
   return key;
@@ -195,11 +191,8 @@ __device__ __forceinline__ void bitonic_sort_regs(uint64_t (&v)[NR]) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
           const uint64_t other = xor_lane_u64(v[r], j);
-          const bool up = (((r << 6) | lane) & k) == 0;
-          const bool lower = (lane & j) == 0;
-          const uint64_t mn = other < v[r] ? other : v[r];
-          const uint64_t mx = other < v[r] ? v[r] : other;
-          v[r] = (lower == up) ? mn : mx;
+          const bool want_min = ((lane & j) == 0) == ((((r << 6) | lane) & k) == 0);
+          v[r] = ((other < v[r]) == want_min) ? other : v[r];
         }
       }
     }
@@ -212,10 +205,7 @@ __device__ __forceinline__ uint64_t bitonic_merge_u64(uint64_t key) {
 #pragma unroll
   for (int j = 32; j > 0; j >>= 1) {
     const uint64_t other = xor_lane_u64(key, j);
-    const bool lower = (lane & j) == 0;
-    const uint64_t mn = other < key ? other : key;
-    const uint64_t mx = other < key ? key : other;
-    key = lower ? mn : mx;
+    key = ((other < key) == ((lane & j) == 0)) ? other : key;
   }
   return key;
 }
