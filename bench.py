@@ -32,9 +32,9 @@ HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
     "sharded1m": dict(N=1_000_000, d=96, C=1000, sigma=0.25, nq=10_000, k=10, deg=32, S=4, ghost_ratio=0.01,
-                      deg_g=32, itopks=(32, 64, 128, 256)),
+                      deg_g=32, itopks=(32, 64), Ts=(8, 12, 16, 24, 32)),
     "tiny": dict(N=10_000, d=128, C=32, sigma=0.3, nq=1_000, k=10, deg=32, S=1, ghost_ratio=0.01, deg_g=32,
-                 itopks=(32, 64, 128)),
+                 itopks=(32, 64, 128), Ts=(16, 32, 64)),
 }
 
 
@@ -173,7 +173,9 @@ def form_lowprec(args):
     idx = {"f32": g32, "f16": reimport(g32, Xd, "f16"), "fp8": reimport(g32, Xd, "fp8")}
     gt100, _ = g32.exact_knn(Qd, 100)
     gt100 = gt100.cpu().numpy().view(np.uint32)
-    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    # exact nearest ghosts as the entry: the mixture's k-NN graph splits into one component per mixture
+    # component, so the entry must land in the query's component
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
     res = {}
     for k, itopks in ((10, (32, 64, 128)), (100, (128, 256, 512))):
         gt = gt100[:, :k]
@@ -204,7 +206,8 @@ def form_lowprec(args):
         "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
         "config": {"workload": f"lowprec1m: N={W['N']} d={W['d']} f32 vectors ({W['C']}-component mixture, std "
                                f"{W['sigma']}) traversed as FP16 / FP8-e4m3 with per-vector scale, FP32 rerank of "
-                               f"4k; degree {W['deg']}, ghost staging 1%, direction filter; {W['nq']} queries",
+                               f"4k; degree {W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; "
+                               f"{W['nq']} queries",
                    "headline": "fp8, k=10"},
         "forms": {f"{n}_k{k}": {"best": res[(n, k)]["best"], "sweep": res[(n, k)]["rows"]}
                   for n in ("f32", "f16", "fp8") for k in (10, 100)},
@@ -233,6 +236,7 @@ def form_learned(args):
     gt, _ = gx.exact_knn(Qd, k)
     gt = gt.cpu().numpy().view(np.uint32)
     opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    dense_opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
     t0 = time.time()
     T_max = 128
     labels = learned.make_labels(gx, Qtrd, k, 64, T_max, opts)
@@ -249,12 +253,14 @@ def form_learned(args):
         for T in (16, 32, 64, 128):
             if T > 2 * itopk:
                 continue
-            ids, _, c = gx.search(Qd, k, itopk, T, opts, counters=True)
-            rc = recall(gt, ids.cpu().numpy().view(np.uint32), k)
-            sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts))
-            nd = float((c[:, 0] + c[:, 4]).double().mean())
-            rows.append(dict(form="ghost", itopk=itopk, T=T, recall=rc, qps=W["nq"] / sec, n_dist=nd))
-            log(f"  ghost     itopk={itopk:3d} T={T:3d} recall={rc:.4f} qps={W['nq'] / sec:,.0f} dists={nd:.0f}")
+            for form, o in (("ghost", opts), ("ghost_dense", dense_opts)):
+                ids, _, c = gx.search(Qd, k, itopk, T, o, counters=True)
+                rc = recall(gt, ids.cpu().numpy().view(np.uint32), k)
+                sec = time_search(lambda: gx.search(Qd, k, itopk, T, o))
+                nd = float((c[:, 0] + c[:, 4]).double().mean())
+                rows.append(dict(form=form, itopk=itopk, T=T, recall=rc, qps=W["nq"] / sec, n_dist=nd))
+                log(f"  {form:11s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} qps={W['nq'] / sec:,.0f} "
+                    f"dists={nd:.0f}")
             for tau, bs in ((0.02, 2.0), (0.02, 3.0), (0.1, 2.0)):
                 (pi, _, pc), _, _, conf = learned.predicted_search(gx, P, Qd, k, itopk, 32, tau, 4, T, opts,
                                                                    counters=True, gmap=gmap, budget_scale=bs)
@@ -268,12 +274,13 @@ def form_learned(args):
                 log(f"  learned tau={tau:4.2f} x{bs:.0f} itopk={itopk:3d} T={T:3d} recall={rp:.4f} "
                     f"qps={W['nq'] / secp:,.0f} dists={ndp:.0f} fallback={fb:.3f}")
 
-    def best(form_prefix):
-        rr = [r for r in rows if r["form"].startswith(form_prefix)]
+    def best(form):
+        rr = [r for r in rows if r["form"] == form or (form == "learned" and r["form"].startswith("learned"))]
         ok = [r for r in rr if r["recall"] >= 0.95]
         return max(ok, key=lambda r: r["qps"]) if ok else max(rr, key=lambda r: r["recall"])
 
-    bg, bl = best("ghost"), best("learned")
+    # the ghost-entry cap: a query whose nearest neighbours' component holds no ghost is not reached
+    bg, bd, bl = best("ghost"), best("ghost_dense"), best("learned")
     out = {
         "metric": METRIC, "value": bl["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
         "ms_per_step": W["nq"] / bl["qps"] * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -281,7 +288,7 @@ def form_learned(args):
         "config": {"workload": f"learned1m: N={W['N']} d={W['d']} f32 ({W['C']}-component mixture), degree "
                                f"{W['deg']}, {W['R']} ghosts; BF16 MLP {W['d']}-{W['hidden']}-{W['hidden']}-"
                                f"{W['R'] + 1} trained on {W['n_train']} queries, {W['nq']} held-out queries"},
-        "ghost_staging": bg, "learned": bl, "gain_qps": bl["qps"] / bg["qps"],
+        "ghost_staging": bg, "ghost_staging_dense": bd, "learned": bl, "gain_qps": bl["qps"] / bg["qps"],
         "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "sweep": rows, "build_s": t_build,
     }
     print(json.dumps(out), flush=True)
@@ -307,7 +314,7 @@ def form_serving(args):
     ks = rng.choice([10, 100], n_req)
     pool = make_data(int(sizes.sum()), W["d"], W["C"], W["sigma"], synth.SEED_QUERIES, u8=True)
     offs = np.concatenate([[0], np.cumsum(sizes)])
-    opts = miann.SearchOptions(entry="ghost_graph", dgs=True)
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
     # recall of the settings used, on the whole query pool in one batch
     Pd = torch.from_numpy(pool).cuda()
     gt, _ = gx.exact_knn(Pd, 100)
@@ -362,7 +369,7 @@ def form_serving(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"serving1m: N={W['N']} d={W['d']} uint8 ({W['C']}-component mixture), degree "
-                               f"{W['deg']}, ghost staging 1%, direction filter; Poisson arrivals, requests of "
+                               f"{W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; Poisson arrivals, requests of "
                                f"1-1024 queries (log-uniform), k in {{10, 100}}"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps, "rates": results,
@@ -380,7 +387,7 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle leg (0 = all)")
     ap.add_argument("--plain", type=int, default=1, help="also sweep the plain (unsharded, random-entry) search")
-    ap.add_argument("--fixed", default="", help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage")
+    ap.add_argument("--fixed", default="", help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage[,ghost_iters]")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the reference for the HBM "
                          "byte counters")
@@ -469,15 +476,17 @@ def main():
 
     tuned_opts = []
     for r in (1, 2):
-        tuned_opts += [(f"gs+dgs r{r}", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=r)),
-                       (f"gs-all+dgs r{r}", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=r,
+        tuned_opts += [(f"gs-all+dgs r{r}", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=r,
                                                                 ghost_every_stage=True)),
-                       (f"gsdense+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r)),
                        (f"gsdense-all+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r,
                                                                      ghost_every_stage=True))]
+    tuned_opts += [("gs-all+dgs r2 Tg4", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2,
+                                                             ghost_every_stage=True, ghost_iters=4)),
+                   ("gs+dgs r2", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2))]
     if args.fixed:
         f = args.fixed.split(",")
-        fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])))
+        fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])),
+                                 ghost_iters=int(f[5]) if len(f) > 5 else 8)
         ids, _ = run(gx, int(f[0]), int(f[1]), fo)
         torch.cuda.synchronize()
         best = dict(form="tuned", variant="fixed", itopk=int(f[0]), T=int(f[1]), opts=fo,
@@ -485,14 +494,14 @@ def main():
         tuned_rows = [best]
     else:
         log("sweep: tuned (ghost staging + direction filter + path extension)")
-        best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], (16, 32, 64, 128))
+        best, tuned_rows = sweep(gx, "tuned", tuned_opts, W["itopks"], W["Ts"])
 
     plain = None
     if args.plain:
         log("building the plain unsharded index")
         gp = miann.Index.build(Xd, degree=W["deg"], num_shards=1, dgs_table=False, seed=5)
         plain_opts = [(f"n_init={n}", miann.SearchOptions(n_init=n)) for n in (2048, 4096)]
-        pbest, _ = sweep(gp, "plain", plain_opts, W["itopks"], (32, 64, 128))
+        pbest, _ = sweep(gp, "plain", plain_opts, W["itopks"], (16, 32, 64))
         plain = {k_: pbest[k_] for k_ in ("variant", "itopk", "T", "recall", "qps")}
         del gp
 

@@ -89,6 +89,7 @@ struct miann_index {
   int d_pad_f32 = 0;  // f32 row length (rerank originals / MFMA copies)
   int64_t n_total = 0;
   std::vector<Shard> sh;
+  DenseGhosts dg;  // all shards' ghosts, bf16-split, for the dense entry
   std::vector<void*> allocs;
   std::vector<void*> ghost_allocs;
   ShardDev* dev_shards = nullptr;  // [S] descriptors read by the search kernels
@@ -109,6 +110,7 @@ struct miann_index {
       s.R = 0;
       s.g_store = nullptr; s.g_scale = nullptr; s.g_graph = nullptr; s.g_map = nullptr; s.g_f32 = nullptr;
     }
+    dg = DenseGhosts();
   }
   ~miann_index() {
     free_ghost();
@@ -165,6 +167,36 @@ miann_status build_ghost_store(miann_index* ix, Shard& sh, hipStream_t st) {
   }
   HIP_TRY(ix->alloc(&sh.g_f32, (size_t)R * ix->d_pad_f32 * 4, true));
   HIP_TRY(dequant_rows(sh.g_store, sh.g_scale, ix->store_dtype, R, ix->d_pad, ix->d_pad_f32, sh.g_f32, st));
+  return MIANN_OK;
+}
+
+// Concatenates the ghost rows of every shard (each block padded to 64 columns)
+// as bf16 hi / lo halves with f32 norms, for the dense entry of all shards.
+miann_status build_dense_ghosts(miann_index* ix, hipStream_t st) {
+  DenseGhosts& G = ix->dg;
+  G = DenseGhosts();
+  G.dk = ix->d_pad_f32;
+  G.off.assign(ix->S + 1, 0);
+  G.R.assign(ix->S, 0);
+  for (int s = 0; s < ix->S; s++) {
+    if (ix->sh[s].R == 0) return MIANN_OK;  // the dense entry needs every shard's ghosts
+    G.R[s] = ix->sh[s].R;
+    G.off[s + 1] = G.off[s] + (G.R[s] + 63) / 64 * 64;
+  }
+  G.cols = G.off[ix->S];
+  HIP_TRY(ix->alloc(&G.hi, (size_t)G.cols * G.dk * 2, true));
+  HIP_TRY(ix->alloc(&G.lo, (size_t)G.cols * G.dk * 2, true));
+  HIP_TRY(ix->alloc(&G.norm, (size_t)G.cols * 4, true));
+  HIP_TRY(ix->alloc(&G.off_dev, (size_t)(ix->S + 1) * 8, true));
+  HIP_TRY(ix->alloc(&G.R_dev, (size_t)ix->S * 8, true));
+  for (int s = 0; s < ix->S; s++) {
+    const size_t o = (size_t)G.off[s];
+    HIP_TRY(split_rows(ix->sh[s].g_f32, G.R[s], G.off[s + 1] - G.off[s], G.dk, G.hi + o * G.dk, G.lo + o * G.dk,
+                       G.norm + o, st));
+  }
+  HIP_TRY(hipMemcpyAsync(G.off_dev, G.off.data(), (size_t)(ix->S + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G.R_dev, G.R.data(), (size_t)ix->S * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return MIANN_OK;
 }
 
@@ -324,6 +356,7 @@ miann_status miann_index_import(const miann_shard_desc* shards, int32_t S, int32
     if (e == hipSuccess) e = ix->refresh(st);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_index_import: %s", hipGetErrorString(e));
   }
+  if (rc == MIANN_OK) rc = build_dense_ghosts(ix, st);
   if (rc != MIANN_OK) {
     delete ix;
     return rc;
@@ -380,6 +413,8 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   if (ghost) {
     for (int s = 0; s < ix->S; s++)
       if (ix->sh[s].R == 0) return fail(MIANN_ESTATE, "miann_search: ghost entry needs miann_build_ghost first");
+    if (sp.entry == MIANN_ENTRY_GHOST_DENSE && ix->dg.cols == 0)
+      return fail(MIANN_ESTATE, "miann_search: dense ghost arrays missing (rebuild the ghost shards)");
     degp_g = pow2_ceil(ix->deg_g);
     if (l_g < 1 || l_g > kMaxL) return fail(MIANN_EINVAL, "miann_search: ghost_itopk %d out of [1, %d]", l_g, kMaxL);
     if (sp.ghost_iters < 0) return fail(MIANN_EINVAL, "miann_search: ghost_iters < 0");
@@ -493,15 +528,13 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   if (sp.entry == MIANN_ENTRY_GHOST_DENSE) {
     a.dense = (const uint64_t*)(sb + off_dense);
     mark(0, 0);
-    for (int s = 0; s < ix->S && rc == MIANN_OK; s++) {
-      const Shard& h = ix->sh[s];
-      // dense seeds are needed for the start shard only, unless every stage takes a ghost entry
-      const int start_only = sp.ppe && !sp.ghost_every_stage;
-      hipError_t e = dense_entry(ix->store_dtype, queries, nq, ix->d, sp.qkeys, ix->S, s, start_only, h.g_f32, h.g_store,
-                                 h.g_scale, h.g_map, h.R, ix->d_pad, ix->d_pad_f32, t_seeds,
-                                 (uint64_t*)(sb + off_dense), st);
-      if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));
-    }
+    // dense seeds are needed for the start shard only, unless every stage takes a ghost entry
+    const int start_only = ix->S > 1 && sp.ppe && !sp.ghost_every_stage;
+    std::vector<DenseShard> ds(ix->S);
+    for (int s = 0; s < ix->S; s++) ds[s] = DenseShard{ix->sh[s].g_store, ix->sh[s].g_scale, ix->sh[s].g_map};
+    hipError_t e = dense_entry_split(ix->store_dtype, queries, nq, ix->d, ix->d_pad, ix->d_pad_f32, sp.qkeys, ix->S,
+                                     start_only, ix->dg, ds.data(), t_seeds, (uint64_t*)(sb + off_dense), st);
+    if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));
     mark(0, 1);
   }
   for (int t = 0; t < ix->S && rc == MIANN_OK; t++) {
@@ -712,6 +745,7 @@ miann_status miann_build_ghost(miann_index* ix, double ratio, int64_t num_ghost,
       if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_ghost: %s", hipGetErrorString(e));
     }
   }
+  if (rc == MIANN_OK) rc = build_dense_ghosts(ix, st);
   if (rc != MIANN_OK) {
     hipStreamSynchronize(st);
     ix->free_ghost();

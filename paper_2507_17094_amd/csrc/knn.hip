@@ -20,6 +20,7 @@
 namespace miann {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int TQ = 64;   // query rows per workgroup
 constexpr int TX = 64;   // base rows per step
@@ -668,6 +669,344 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
                        g_map, S, shard, out);
     e = hipGetLastError();
   }
+  hipFreeAsync(buf, st);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Dense ghost entry over the ghosts of several shards at once. The ghost rows
+// of every shard are concatenated (each shard's block padded to a multiple of
+// 64 columns) and their traversal values split as x = hi + lo with hi, lo in
+// bf16, so q.x ~ qh.xh + qh.xl + ql.xh on the bf16 matrix cores with f32
+// accumulation (relative error about 2^-16 of |q||x|, far below the distance
+// gaps the 16 extra candidates absorb; the candidates are rescored exactly).
+// The GEMM epilogue writes the GEMM-form distances D and, per row, the minimum
+// of every 32-column half tile. One wave per (row, shard) then bounds the
+// row's kp-th smallest distance by the kp-th smallest half-tile minimum of the
+// shard, collects the keys at or below the bound, and sorts them.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// hi/lo bf16 split and f32 norm of n rows of x ([n][dk] f32); rows n..n_pad get zeros and norm +inf.
+__global__ void split_rows_kernel(const float* __restrict__ x, int64_t n, int64_t n_pad, int dk,
+                                  uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, float* __restrict__ norm) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n_pad) return;
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int c = lane; c < dk; c += 64) {
+    const float v = r < n ? x[r * dk + c] : 0.f;
+    const uint16_t h = f32_to_bf16(v);
+    hi[r * dk + c] = h;
+    lo[r * dk + c] = f32_to_bf16(v - bf16_to_f32(h));
+    s += (double)v * (double)v;
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += xor_lane_f64(s, o);
+  if (lane == 0) norm[r] = r < n ? (float)s : INFINITY;
+}
+
+hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t* hi, uint16_t* lo, float* norm,
+                      hipStream_t st) {
+  if (n_pad == 0) return hipSuccess;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((n_pad + 3) / 4)), dim3(256), 0, st, x, n, n_pad, dk, hi, lo,
+                     norm);
+  return hipGetLastError();
+}
+
+constexpr int SK = 32;        // k-chunk (elements) staged in LDS
+constexpr int SKP = SK + 8;   // padded LDS row
+
+// D[rl][c] = |q|^2 + |x_c|^2 - 2 q.x_c for the rows of a chunk (query row = list ? list[row0 + rl] : row0 + rl)
+// and columns c of [col0, col0 + ncols); M[rl][c / 32] = min of each 32-column half tile. Operands are staged
+// with 16-byte loads; the 64 x 64 result goes through LDS so that D is written in whole 256-byte rows and each
+// half-tile minimum is one thread's 32-element scan.
+__global__ __launch_bounds__(256) void dense_gemm3_kernel(
+    const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
+    const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
+    int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl, const float* __restrict__ gn,
+    int64_t col0, int64_t ncols, int dk, float* __restrict__ D, float* __restrict__ M) {
+  constexpr int TS = 64 + 4;  // result tile row stride (floats)
+  __shared__ __align__(16) char smem[4 * 64 * SKP * 2 > 64 * TS * 4 ? 4 * 64 * SKP * 2 : 64 * TS * 4];
+  __shared__ int64_t qrow[64];
+  __shared__ float qnl[64];
+  uint16_t* Ah = (uint16_t*)smem;
+  uint16_t* Al = Ah + 64 * SKP;
+  uint16_t* Bh = Al + 64 * SKP;
+  uint16_t* Bl = Bh + 64 * SKP;
+  float* T = (float*)smem;  // reused after the products
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  const int64_t rl0 = (int64_t)blockIdx.y * 64;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk) return;
+  for (int r = tid; r < 64; r += 256) {
+    const int64_t gr = row0 + rl0 + r;
+    const bool ok = gr < n_rows && rl0 + r < rows_chunk;
+    const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
+    qrow[r] = q;
+    qnl[r] = ok ? qn[q] : 0.f;
+  }
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f32x16_t acc;
+#pragma unroll
+  for (int j = 0; j < 16; j++) acc[j] = 0.f;
+  // staging: thread -> (row tid / 4, 8 elements at (tid % 4) * 8) of each 64 x 32 operand block
+  const int sr = tid >> 2, sc = (tid & 3) * 8;
+  for (int k0 = 0; k0 < dk; k0 += SK) {
+    __syncthreads();
+    {
+      const int64_t q = qrow[sr];
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      *(uint4*)&Ah[sr * SKP + sc] = q >= 0 ? *(const uint4*)&Qh[q * dk + k0 + sc] : z;
+      *(uint4*)&Al[sr * SKP + sc] = q >= 0 ? *(const uint4*)&Ql[q * dk + k0 + sc] : z;
+      const int64_t g = col0 + c0 + sr;
+      *(uint4*)&Bh[sr * SKP + sc] = *(const uint4*)&Gh[g * dk + k0 + sc];
+      *(uint4*)&Bl[sr * SKP + sc] = *(const uint4*)&Gl[g * dk + k0 + sc];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < SK; kk += 16) {
+      const int ra = (wr + (lane & 31)) * SKP + kk + (lane >> 5) * 8;
+      const int rb = (wc + (lane & 31)) * SKP + kk + (lane >> 5) * 8;
+      const bf16x8_t ah = *(const bf16x8_t*)&Ah[ra], al = *(const bf16x8_t*)&Al[ra];
+      const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb], bl = *(const bf16x8_t*)&Bl[rb];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  {
+    const int col = wc + (lane & 31);
+    const float gcol = gn[col0 + c0 + col];
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const int row = wr + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+      const float dv = qnl[row] + gcol - 2.f * acc[j];
+      T[row * TS + col] = dv < 0.f ? 0.f : dv;
+    }
+  }
+  __syncthreads();
+  // D: each thread writes 16 consecutive floats of one row
+  {
+    const int row = tid >> 2, cq = (tid & 3) * 16;
+    if (qrow[row] >= 0) {
+      float4* dst = (float4*)&D[(rl0 + row) * ncols + c0 + cq];
+#pragma unroll
+      for (int v = 0; v < 4; v++) dst[v] = *(const float4*)&T[row * TS + cq + 4 * v];
+    }
+  }
+  // M: thread t < 128 takes row t / 2, half t % 2
+  if (tid < 128) {
+    const int row = tid >> 1, h = tid & 1;
+    if (qrow[row] >= 0) {
+      float m = INFINITY;
+#pragma unroll
+      for (int v = 0; v < 8; v++) {
+        const float4 x = *(const float4*)&T[row * TS + h * 32 + 4 * v];
+        m = fminf(m, fminf(fminf(x.x, x.y), fminf(x.z, x.w)));
+      }
+      M[(rl0 + row) * (ncols / 32) + c0 / 32 + h] = m;
+    }
+  }
+}
+
+// One wave per (row, shard): kp = min(t + 16, R_s) candidate keys (GEMM-form distance bits << 32 | ghost index
+// within the shard), ascending, into cand[((s - s0) * rows_total + row0 + rl) * KP], the rest of the KP slots kDummy.
+template <int CAP>
+__global__ __launch_bounds__(256) void dense_select3_kernel(
+    const float* __restrict__ D, const float* __restrict__ M, int64_t ncols, const int64_t* __restrict__ seg_off,
+    const int64_t* __restrict__ seg_R, int s0, int nseg, const int* __restrict__ nrows_dev, int64_t nrows_max,
+    int64_t row0, int64_t rows_chunk, int64_t rows_total, int t, int KP, uint64_t* __restrict__ cand) {
+  constexpr int NR = CAP / 64;
+  __shared__ uint64_t bufs[4 * CAP];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t rl = item / nseg;
+  const int sl = (int)(item % nseg);
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  if (rl >= rows_chunk || row0 + rl >= n_rows) return;
+  const int s = s0 + sl;
+  const int64_t cb = seg_off[s] - seg_off[s0];  // first column of the shard within the chunk's columns
+  const int64_t R = seg_R[s];
+  const int kp = (int)(t + 16 < R ? t + 16 : R);
+  uint64_t* o = cand + ((int64_t)sl * rows_total + row0 + rl) * KP;
+  if (R == 0) {
+    for (int i = lane; i < KP; i += 64) o[i] = kDummy;
+    return;
+  }
+  uint64_t* buf = bufs + wave * CAP;
+  const float* d = D + rl * ncols + cb;
+  const float* m = M + rl * (ncols / 32) + cb / 32;
+  const int64_t nht = (R + 31) / 32;
+  // the kp-th smallest half-tile minimum bounds the kp-th smallest distance from above
+  uint64_t mm[2] = {kDummy, kDummy};
+  for (int64_t j = lane; j < nht; j += 64) {
+    const uint64_t key = ((uint64_t)__float_as_uint(m[j]) << 32) | (uint64_t)j;
+    if (key < mm[0]) {
+      mm[1] = mm[0];
+      mm[0] = key;
+    } else if (key < mm[1]) {
+      mm[1] = key;
+    }
+  }
+  bitonic_sort_regs<2>(mm);
+  const int rb = (kp - 1) >> 6, lb = (kp - 1) & 63;
+  const uint64_t bk = shfl_u64(rb == 0 ? mm[0] : mm[1], lb);
+  // keys at or below the bound distance (every key when fewer than kp half tiles)
+  uint64_t bound = bk == kDummy ? kDummy : ((bk | 0xFFFFFFFFull));
+  uint64_t v[NR];
+  for (;;) {
+    // 4 columns per lane per step (rows of the segment are padded to 64 columns)
+    int cnt = 0;
+    for (int64_t j0 = 0; j0 < R; j0 += 256) {
+      const int64_t jb = j0 + 4 * lane;
+      const float4 x = jb < R ? *(const float4*)&d[jb] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int64_t j = jb + e;
+        const uint64_t key = ((uint64_t)__float_as_uint(xs[e]) << 32) | (uint64_t)j;
+        const bool pass = j < R && key <= bound;
+        const uint64_t bm = ballot(pass);
+        const int pos = cnt + lanes_below(bm);
+        if (pass && pos < CAP) buf[pos] = key;
+        cnt += __popcll(bm);
+      }
+    }
+    wsync();
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      const int i = r * 64 + lane;
+      v[r] = i < cnt && i < CAP ? buf[i] : kDummy;
+    }
+    wsync();
+    // sort only as many 64-key registers as hold keys
+    if (cnt <= 64) {
+      v[0] = bitonic_sort_u64<64>(v[0]);
+    } else if (cnt <= 128) {
+      uint64_t w2[2] = {v[0], v[1]};
+      bitonic_sort_regs<2>(w2);
+      v[0] = w2[0];
+      v[1] = w2[1];
+    } else {
+      bitonic_sort_regs<NR>(v);
+    }
+    if (cnt <= CAP) break;
+    uint64_t x = v[0];
+#pragma unroll
+    for (int r = 1; r < NR; r++)
+      if (r == rb) x = v[r];
+    bound = shfl_u64(x, lb);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int i = r * 64 + lane;
+    if (i < KP) o[i] = i < kp ? v[r] : kDummy;
+  }
+}
+
+__global__ void dense_out2_kernel(const uint64_t* __restrict__ best, const uint32_t* __restrict__ list,
+                                  const int* __restrict__ count, int64_t nmax, int t, const uint32_t* __restrict__ g_map,
+                                  int S, int shard, uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = i / t;
+  const int j = (int)(i % t);
+  const int64_t n = count ? (int64_t)*count : nmax;
+  if (r >= n) return;
+  const uint32_t q = list ? list[r] : (uint32_t)r;
+  const uint64_t key = best[(size_t)q * t + j];
+  out[((size_t)q * S + shard) * t + j] =
+      key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | g_map[(uint32_t)key]);
+}
+
+hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int d, int d_pad, int dk,
+                             const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G,
+                             const DenseShard* shards, int t, uint64_t* out, hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  const int qdt = store_dt == DT_U8 ? DT_U8 : DT_F32;
+  const int KP = t + 16;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t sz_qf = al((size_t)nq * dk * 4), sz_qb = al((size_t)nq * dk * 2), sz_qn = al((size_t)nq * 4);
+  const size_t sz_qraw = al((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4));
+  const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
+  const size_t sz_cand = al((size_t)nq * S * KP * 8), sz_best = al((size_t)nq * t * 8);
+  const size_t total = sz_qf + 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt + sz_cand + sz_best;
+  char* buf = nullptr;
+  hipError_t e = hipMallocAsync((void**)&buf, total, st);
+  if (e != hipSuccess) return e;
+  char* p = buf;
+  float* qf = (float*)p; p += sz_qf;
+  uint16_t* qh = (uint16_t*)p; p += sz_qb;
+  uint16_t* ql = (uint16_t*)p; p += sz_qb;
+  float* qn = (float*)p; p += sz_qn;
+  void* qraw = p; p += sz_qraw;
+  uint32_t* list = (uint32_t*)p; p += sz_list;
+  int* cnt = (int*)p; p += sz_cnt;
+  uint64_t* cand = (uint64_t*)p; p += sz_cand;
+  uint64_t* best = (uint64_t*)p;
+  e = queries_to_f32(queries, qdt, nq, d, dk, qf, st);
+  if (e == hipSuccess) e = split_rows(qf, nq, nq, dk, qh, ql, qn, st);
+  if (e == hipSuccess) {
+    if (qdt == DT_U8) {
+      hipLaunchKernelGGL(pad_u8_kernel, dim3((unsigned)((nq * d_pad + 255) / 256)), dim3(256), 0, st,
+                         (const uint8_t*)queries, nq, d, d_pad, (uint8_t*)qraw);
+      e = hipGetLastError();
+    } else {
+      e = queries_to_f32(queries, DT_F32, nq, d, d_pad, (float*)qraw, st);
+    }
+  }
+  // (rows, shard range) passes: every query against every shard, or each shard against the queries starting there
+  const int npass = start_only ? S : 1;
+  float* Dm = nullptr;
+  for (int ps = 0; ps < npass && e == hipSuccess; ps++) {
+    const int s0 = start_only ? ps : 0, s1 = start_only ? ps + 1 : S;
+    const int64_t col0 = G.off[s0], ncols = G.off[s1] - G.off[s0];
+    if (ncols == 0) continue;
+    const uint32_t* rl = nullptr;
+    const int* rc = nullptr;
+    if (start_only) {
+      hipLaunchKernelGGL(fill_cnt_kernel, dim3(1), dim3(1), 0, st, cnt);
+      hipLaunchKernelGGL(shard_qlist_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, qkeys, S, s0,
+                         0, list, cnt);
+      rl = list;
+      rc = cnt;
+    }
+    int64_t chunk = ((int64_t)1 << 27) / ncols;  // at most 512 MB of distances at a time
+    chunk = chunk < 64 ? 64 : chunk / 64 * 64;
+    if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
+    if (!Dm) e = hipMallocAsync((void**)&Dm, (size_t)chunk * ncols * 4 + (size_t)chunk * (ncols / 32) * 4, st);
+    float* D = Dm;
+    float* M = Dm + (size_t)chunk * ncols;
+    const int nseg = s1 - s0;
+    for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
+      hipLaunchKernelGGL(dense_gemm3_kernel, dim3((unsigned)(ncols / 64), (unsigned)(chunk / 64)), dim3(256), 0, st,
+                         qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo, G.norm, col0, ncols, dk, D, M);
+      hipLaunchKernelGGL(dense_select3_kernel<256>, dim3((unsigned)((chunk * nseg + 3) / 4)), dim3(256), 0, st, D, M,
+                         ncols, G.off_dev, G.R_dev, s0, nseg, rc, nq, row0, chunk, nq, t, KP, cand);
+      e = hipGetLastError();
+    }
+    for (int s = s0; s < s1 && e == hipSuccess; s++) {
+      if (G.R[s] == 0) continue;
+      const uint64_t* cs = cand + (size_t)(s - s0) * nq * KP;
+      e = launch_rescore(store_dt, cs, nq, rc, KP, rl, qraw, shards[s].g_store, shards[s].g_scale, d_pad, t, best, st);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(dense_out2_kernel, dim3((unsigned)((nq * t + 255) / 256)), dim3(256), 0, st, best, rl, rc,
+                           nq, t, shards[s].g_map, S, s, out);
+        e = hipGetLastError();
+      }
+    }
+    if (Dm && start_only) {
+      // chunk sizes differ per shard: release the buffer for the next pass
+      hipFreeAsync(Dm, st);
+      Dm = nullptr;
+    }
+  }
+  if (Dm) hipFreeAsync(Dm, st);
   hipFreeAsync(buf, st);
   return e;
 }
