@@ -319,17 +319,22 @@ def form_serving(args):
     Pd = torch.from_numpy(pool).cuda()
     gt, _ = gx.exact_knn(Pd, 100)
     gt = gt.cpu().numpy().view(np.uint32)
-    setting = {10: (64, 64), 100: (256, 128)}
+    setting = {10: (64, 32), 100: (128, 64)}
     rec = {}
     for k, (itopk, T) in setting.items():
         ids, _ = gx.search(Pd, k, itopk, T, opts)
         rec[k] = recall(gt[:, :k], ids.cpu().numpy().view(np.uint32), k)
     log(f"build {t_build:.1f}s recall {rec}")
-    # batch capacity: one large batch of the pool
-    cap_s = time_search(lambda: gx.search(Pd, 10, 64, 64, opts), reps=2)
+    # batch capacity on the request mix: the pool's k = 10 and k = 100 queries as one batch each
+    qk = np.repeat(ks, sizes)
+    cap_s = 0.0
+    for k, (itopk, T) in setting.items():
+        sub_q = torch.from_numpy(np.ascontiguousarray(pool[qk == k])).cuda()
+        if len(sub_q):
+            cap_s += time_search(lambda: gx.search(sub_q, k, itopk, T, opts), reps=2)
     cap_qps = len(pool) / cap_s
     results = []
-    for load_frac in (0.25, 0.5, 0.8):
+    for load_frac in (0.25, 0.5, 0.75):
         mean_q = float(sizes.mean())
         rate = load_frac * cap_qps / mean_q  # requests per second
         gaps = rng.exponential(1.0 / rate, n_req)

@@ -125,88 +125,120 @@ __device__ __forceinline__ double xor_lane_f64(double v, int j) {
 }
 __device__ __forceinline__ int xor_lane_i32(int v, int j) { return (int)xor_lane_u32((uint32_t)v, j); }
 
+// Global-memory views of generic pointers: loads through them compile to
+// global_load (vector memory only) instead of flat_load, which would also
+// count against the LDS wait counter.
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+// 16-byte global load (a builtin vector type, so it can be read through gptr)
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load16(gptr<u32x4_t> p, int i) {
+  const u32x4_t v = p[i];
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Number of set lanes of `mask` below this lane.
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Bitonic networks. Stage (K, J) of a sort over N keys (key index i = r * 64 +
+// lane, r the register) exchanges keys i and i ^ J; key i keeps the smaller one
+// iff (i & J) == 0 equals the pair's direction (ascending iff K == N or
+// (i & K) == 0). Every stage is a template instance, so the lanes that keep the
+// smaller key form a compile-time mask: one compare, a scalar XOR with the mask
+// (take the partner where "partner < key" agrees with "keep the smaller") and
+// two selects per 64-bit exchange.
+constexpr uint64_t keep_min_mask(int K, int J, int N, int R) {
+  uint64_t m = 0;
+  for (int l = 0; l < 64; l++) {
+    const int i = (R << 6) | l;
+    const bool lower = (i & J) == 0;
+    const bool up = (K >= N) || ((i & K) == 0);
+    if (lower == up) m |= 1ull << l;
+  }
+  return m;
+}
+
+template <uint64_t WM, typename T>
+__device__ __forceinline__ T exchange(T key, T other) {
+  const bool take = __builtin_amdgcn_inverse_ballot_w64(~(__ballot(other < key) ^ WM));
+  return take ? other : key;
+}
+
+template <int SEG, int K, int J>
+__device__ __forceinline__ void bsort_stage_u64(uint64_t& key) {
+  key = exchange<keep_min_mask(K, J, SEG, 0)>(key, xor_lane_u64(key, J));
+  if constexpr (J > 1) bsort_stage_u64<SEG, K, J / 2>(key);
+  else if constexpr (K < SEG) bsort_stage_u64<SEG, K * 2, K>(key);
+}
+template <int SEG, int K, int J>
+__device__ __forceinline__ void bsort_stage_u32(uint32_t& key) {
+  key = exchange<keep_min_mask(K, J, SEG, 0)>(key, xor_lane_u32(key, J));
+  if constexpr (J > 1) bsort_stage_u32<SEG, K, J / 2>(key);
+  else if constexpr (K < SEG) bsort_stage_u32<SEG, K * 2, K>(key);
 }
 
 // Bitonic sort of one u64 key per lane, ascending in segments of SEG lanes
 // (SEG a power of two, 2..64).
 template <int SEG>
 __device__ __forceinline__ uint64_t bitonic_sort_u64(uint64_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= SEG; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      // the lane keeps the smaller key iff it is the lower lane of an ascending pair or the upper
-      // of a descending one; one compare decides, the lane pattern is a scalar mask
-      const uint64_t other = xor_lane_u64(key, j);
-      const bool want_min = ((lane & j) == 0) == ((k == SEG) || ((lane & k) == 0));
-      key = ((other < key) == want_min) ? other : key;
-    }
-  }
+  bsort_stage_u64<SEG, 2, 1>(key);
   return key;
 }
 
 template <int SEG>
 __device__ __forceinline__ uint32_t bitonic_sort_u32(uint32_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= SEG; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t other = xor_lane_u32(key, j);
-      const bool want_min = ((lane & j) == 0) == ((k == SEG) || ((lane & k) == 0));
-      key = ((other < key) == want_min) ? other : key;
-    }
-  }
+  bsort_stage_u32<SEG, 2, 1>(key);
   return key;
+}
+
+// One stage (K, J) over NR registers, registers R.. (recursion over R).
+template <int NR, int K, int J, int R>
+__device__ __forceinline__ void bregs_stage(uint64_t (&v)[NR]) {
+  if constexpr (R < NR) {
+    if constexpr (J >= 64) {
+      constexpr int jr = J >> 6;
+      if constexpr ((R & jr) == 0) {
+        // partner in register R | jr of the same lane; the direction depends on R only
+        constexpr bool up = (K >= 64 * NR) || (((R << 6) & K) == 0);
+        const uint64_t a = v[R], b = v[R | jr];
+        const bool sw = (a > b) == up;
+        v[R] = sw ? b : a;
+        v[R | jr] = sw ? a : b;
+      }
+    } else {
+      v[R] = exchange<keep_min_mask(K, J, 64 * NR, R)>(v[R], xor_lane_u64(v[R], J));
+    }
+    bregs_stage<NR, K, J, R + 1>(v);
+  }
+}
+template <int NR, int K, int J>
+__device__ __forceinline__ void bregs_sort(uint64_t (&v)[NR]) {
+  bregs_stage<NR, K, J, 0>(v);
+  if constexpr (J > 1) bregs_sort<NR, K, J / 2>(v);
+  else if constexpr (K < 64 * NR) bregs_sort<NR, K * 2, K>(v);
 }
 
 // Bitonic sort of 64 * NR u64 keys held NR per lane (key index r * 64 + lane),
 // ascending over the whole wave.
 template <int NR>
 __device__ __forceinline__ void bitonic_sort_regs(uint64_t (&v)[NR]) {
-  const int lane = lane_id();
-  constexpr int N = 64 * NR;
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 64) {
-        const int jr = j >> 6;
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-          if ((r & jr) == 0) {
-            const int p = r | jr;
-            const bool up = (((r << 6) | lane) & k) == 0;
-            const uint64_t a = v[r], b = v[p];
-            const bool sw = (a > b) == up;
-            v[r] = sw ? b : a;
-            v[p] = sw ? a : b;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-          const uint64_t other = xor_lane_u64(v[r], j);
-          const bool want_min = ((lane & j) == 0) == ((((r << 6) | lane) & k) == 0);
-          v[r] = ((other < v[r]) == want_min) ? other : v[r];
-        }
-      }
-    }
-  }
+  bregs_sort<NR, 2, 1>(v);
 }
 
+template <int J>
+__device__ __forceinline__ void bmerge_stage(uint64_t& key) {
+  key = exchange<keep_min_mask(64, J, 64, 0)>(key, xor_lane_u64(key, J));
+  if constexpr (J > 1) bmerge_stage<J / 2>(key);
+}
 // Sorts a bitonic sequence of 64 keys (one per lane) ascending.
 __device__ __forceinline__ uint64_t bitonic_merge_u64(uint64_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int j = 32; j > 0; j >>= 1) {
-    const uint64_t other = xor_lane_u64(key, j);
-    key = ((other < key) == ((lane & j) == 0)) ? other : key;
-  }
+  bmerge_stage<32>(key);
   return key;
 }
 

@@ -217,13 +217,15 @@ struct Searcher {
       bool ok[G];
 #pragma unroll
       for (int gi = 0; gi < G; gi++) {
+        // every lane loads (row 0 for the unused teams), so the gathers need no branches
         const int ci = r0 + gi * 8 + team;
         ok[gi] = ci < nc;
-        ids[gi] = ok[gi] ? cid[ci] : 0u;
-        const uint4* row = (const uint4*)((const char*)g.store + (size_t)ids[gi] * row_bytes);
+        ids[gi] = cid[ci < nc ? ci : 0];
+        const uint32_t lid = ok[gi] ? ids[gi] : 0u;
+        const gptr<u32x4_t> row = as_global((const u32x4_t*)((const char*)g.store + (size_t)lid * row_bytes));
 #pragma unroll
-        for (int m = 0; m < CPL; m++) buf[gi][m] = ok[gi] ? row[tl + 8 * m] : make_uint4(0, 0, 0, 0);
-        if constexpr (kScaled) sc[gi] = ok[gi] ? g.scale[ids[gi]] : 0.f;
+        for (int m = 0; m < CPL; m++) buf[gi][m] = load16(row, tl + 8 * m);
+        if constexpr (kScaled) sc[gi] = as_global(g.scale)[lid];
       }
 #pragma unroll
       for (int gi = 0; gi < G; gi++) {
@@ -354,14 +356,17 @@ struct Searcher {
 #pragma unroll
       for (int t = 0; t < kMaxR; t++)
         if (t == pa) u = pid[t];
-      uint32_t nb = act ? g.graph[(size_t)u * g.deg + slot] : kNone;
+      uint32_t nb = as_global(g.graph)[(size_t)u * g.deg + (act ? slot : 0)];
+      nb = act ? nb : kNone;
       if (dgs_phase) {
         // this lane's direction-table words, loaded in the same round trip as the adjacency row
         constexpr int kSW = 8;
-        const uint32_t* srow = g.sign + (size_t)u * W * g.deg + slot;
+        // inactive lanes read slot 0 of a valid row (slots beyond deg would run past the table)
+        const uint32_t* srow = g.sign + (size_t)u * W * g.deg + (act ? slot : 0);
         uint32_t sw[kSW];
 #pragma unroll
-        for (int w = 0; w < kSW; w++) sw[w] = (act && !a.random_discard && w < W) ? srow[(size_t)w * g.deg] : 0u;
+        for (int w = 0; w < kSW; w++)
+          sw[w] = (!a.random_discard && w < W) ? as_global(srow)[(size_t)w * g.deg] : 0u;
         // query sign bits against each parent: bit i = [q_i > x_parent,i]
 #pragma unroll
         for (int t = 0; t < kMaxR; t++) {
@@ -374,7 +379,7 @@ struct Searcher {
             if (i < a.d) {
               if constexpr (DT == DT_U8) gt = qb[i] > ((const uint8_t*)row)[i];
               else {
-                const float x = load_elem<DT>(row, i);
+                const float x = load_elem<DT>((const void*)as_global((const char*)row), i);
                 gt = qf[i] > (kScaled ? su * x : x);
               }
             }
