@@ -189,6 +189,10 @@ miann_status build_dense_ghosts(miann_index* ix, hipStream_t st) {
   HIP_TRY(ix->alloc(&G.norm, (size_t)G.cols * 4, true));
   HIP_TRY(ix->alloc(&G.off_dev, (size_t)(ix->S + 1) * 8, true));
   HIP_TRY(ix->alloc(&G.R_dev, (size_t)ix->S * 8, true));
+  HIP_TRY(ix->alloc(&G.shards_dev, sizeof(DenseShardDev) * ix->S, true));
+  std::vector<DenseShardDev> sd(ix->S);
+  for (int s = 0; s < ix->S; s++) sd[s] = DenseShardDev{ix->sh[s].g_store, ix->sh[s].g_scale, ix->sh[s].g_map};
+  HIP_TRY(hipMemcpyAsync(G.shards_dev, sd.data(), sizeof(DenseShardDev) * ix->S, hipMemcpyHostToDevice, st));
   for (int s = 0; s < ix->S; s++) {
     const size_t o = (size_t)G.off[s];
     HIP_TRY(split_rows(ix->sh[s].g_f32, G.R[s], G.off[s + 1] - G.off[s], G.dk, G.hi + o * G.dk, G.lo + o * G.dk,
@@ -530,10 +534,8 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     mark(0, 0);
     // dense seeds are needed for the start shard only, unless every stage takes a ghost entry
     const int start_only = ix->S > 1 && sp.ppe && !sp.ghost_every_stage;
-    std::vector<DenseShard> ds(ix->S);
-    for (int s = 0; s < ix->S; s++) ds[s] = DenseShard{ix->sh[s].g_store, ix->sh[s].g_scale, ix->sh[s].g_map};
     hipError_t e = dense_entry_split(ix->store_dtype, queries, nq, ix->d, ix->d_pad, ix->d_pad_f32, sp.qkeys, ix->S,
-                                     start_only, ix->dg, ds.data(), t_seeds, (uint64_t*)(sb + off_dense), st);
+                                     start_only, ix->dg, t_seeds, (uint64_t*)(sb + off_dense), st);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));
     mark(0, 1);
   }

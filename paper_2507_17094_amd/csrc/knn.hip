@@ -14,6 +14,8 @@
 // top-K unless the GEMM-form error exceeds the distance gap across 16 ranks.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "knn.hpp"
 
@@ -680,10 +682,12 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
 // bf16, so q.x ~ qh.xh + qh.xl + ql.xh on the bf16 matrix cores with f32
 // accumulation (relative error about 2^-16 of |q||x|, far below the distance
 // gaps the 16 extra candidates absorb; the candidates are rescored exactly).
-// The GEMM epilogue writes the GEMM-form distances D and, per row, the minimum
-// of every 32-column half tile. One wave per (row, shard) then bounds the
-// row's kp-th smallest distance by the kp-th smallest half-tile minimum of the
-// shard, collects the keys at or below the bound, and sorts them.
+// The distances are never stored: pass 1 keeps the smallest key of every 8
+// columns, a bound kernel takes for each (query, shard) the kp-th smallest of a
+// subset of those minima (so at least kp keys lie at or below it), pass 2
+// recomputes the tiles and appends only the keys at or below the bound to a
+// short per-(query, shard) list, and one wave per list sorts it, rescores the
+// kp smallest exactly and writes the exact top-t seeds.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
@@ -720,16 +724,32 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
 constexpr int SK = 32;        // k-chunk (elements) staged in LDS
 constexpr int SKP = SK + 8;   // padded LDS row
 
-// D[rl][c] = |q|^2 + |x_c|^2 - 2 q.x_c for the rows of a chunk (query row = list ? list[row0 + rl] : row0 + rl)
-// and columns c of [col0, col0 + ncols); M[rl][c / 32] = min of each 32-column half tile. Operands are staged
-// with 16-byte loads; the 64 x 64 result goes through LDS so that D is written in whole 256-byte rows and each
-// half-tile minimum is one thread's 32-element scan.
-__global__ __launch_bounds__(256) void dense_gemm3_kernel(
+constexpr int DG = 8;     // columns per group minimum (pass 1)
+constexpr int SMAX = 16;  // candidate slots per (query, shard, 64-column tile) (pass 2)
+constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
+
+// The shard owning column gc of the concatenated ghost matrix (shards s0 .. s0 + nseg - 1).
+__device__ __forceinline__ int shard_of_col(const int64_t* __restrict__ off, int s0, int nseg, int64_t gc) {
+  int s = s0;
+  for (int i = 1; i < nseg; i++)
+    if (gc >= off[s0 + i]) s = s0 + i;
+  return s;
+}
+
+// GEMM-form distances of a 64-row x 64-column tile (three bf16 products), then
+// MODE 0: the smallest distance of every 8 columns -> M;
+// MODE 1: the keys (dist bits << 32 | ghost index) at or below the row's bound for the tile's shard, into the
+// SMAX slots of (row, shard, tile); the four threads of a row place their keys by a prefix sum over the quad,
+// and the first writes the tile's count (which may exceed SMAX).
+template <int MODE>
+__global__ __launch_bounds__(256) void dense_pass_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl, const float* __restrict__ gn,
-    int64_t col0, int64_t ncols, int dk, float* __restrict__ D, float* __restrict__ M) {
-  constexpr int TS = 64 + 4;  // result tile row stride (floats)
+    int64_t col0, int64_t ncols, int dk, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0,
+    int nseg, int ntmax, float* __restrict__ M, const float* __restrict__ bound, int* __restrict__ tcnt,
+    uint64_t* __restrict__ slots) {
+  constexpr int TS = 64 + 4;
   __shared__ __align__(16) char smem[4 * 64 * SKP * 2 > 64 * TS * 4 ? 4 * 64 * SKP * 2 : 64 * TS * 4];
   __shared__ int64_t qrow[64];
   __shared__ float qnl[64];
@@ -759,10 +779,10 @@ __global__ __launch_bounds__(256) void dense_gemm3_kernel(
   for (int k0 = 0; k0 < dk; k0 += SK) {
     __syncthreads();
     {
-      const int64_t q = qrow[sr];
-      const uint4 z = make_uint4(0, 0, 0, 0);
-      *(uint4*)&Ah[sr * SKP + sc] = q >= 0 ? *(const uint4*)&Qh[q * dk + k0 + sc] : z;
-      *(uint4*)&Al[sr * SKP + sc] = q >= 0 ? *(const uint4*)&Ql[q * dk + k0 + sc] : z;
+      // rows without a query load row 0: an output row depends only on its own operand row
+      const int64_t q = qrow[sr] >= 0 ? qrow[sr] : 0;
+      *(uint4*)&Ah[sr * SKP + sc] = *(const uint4*)&Qh[q * dk + k0 + sc];
+      *(uint4*)&Al[sr * SKP + sc] = *(const uint4*)&Ql[q * dk + k0 + sc];
       const int64_t g = col0 + c0 + sr;
       *(uint4*)&Bh[sr * SKP + sc] = *(const uint4*)&Gh[g * dk + k0 + sc];
       *(uint4*)&Bl[sr * SKP + sc] = *(const uint4*)&Gl[g * dk + k0 + sc];
@@ -791,39 +811,62 @@ __global__ __launch_bounds__(256) void dense_gemm3_kernel(
     }
   }
   __syncthreads();
-  // D: each thread writes 16 consecutive floats of one row
-  {
-    const int row = tid >> 2, cq = (tid & 3) * 16;
-    if (qrow[row] >= 0) {
-      float4* dst = (float4*)&D[(rl0 + row) * ncols + c0 + cq];
+  // the tile lies inside one shard's block (blocks are multiples of 64 columns)
+  const int s = shard_of_col(off, s0, nseg, col0 + c0);
+  const int sl = s - s0;
+  const int64_t jb = col0 + c0 - off[s];  // ghost index of the tile's first column
+  const int64_t R = Rs[s];
+  const int row = tid >> 2, c4 = tid & 3, cq = c4 * 16;
+  if (qrow[row] < 0) return;  // whole quads leave together (one row per quad)
+  const int64_t rr = rl0 + row;  // row within the chunk
+  if constexpr (MODE == 0) {
 #pragma unroll
-      for (int v = 0; v < 4; v++) dst[v] = *(const float4*)&T[row * TS + cq + 4 * v];
-    }
-  }
-  // M: thread t < 128 takes row t / 2, half t % 2
-  if (tid < 128) {
-    const int row = tid >> 1, h = tid & 1;
-    if (qrow[row] >= 0) {
+    for (int g = 0; g < 16 / DG; g++) {
       float m = INFINITY;
 #pragma unroll
-      for (int v = 0; v < 8; v++) {
-        const float4 x = *(const float4*)&T[row * TS + h * 32 + 4 * v];
-        m = fminf(m, fminf(fminf(x.x, x.y), fminf(x.z, x.w)));
+      for (int e = 0; e < DG; e++) {
+        const int64_t j = jb + cq + g * DG + e;
+        if (j < R) m = fminf(m, T[row * TS + cq + g * DG + e]);
       }
-      M[(rl0 + row) * (ncols / 32) + c0 / 32 + h] = m;
+      M[rr * (ncols / DG) + (c0 + cq) / DG + g] = m;
+    }
+  } else {
+    const float b = bound[rr * nseg + sl];
+    uint32_t pm = 0;
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      const int64_t j = jb + cq + e;
+      pm |= (j < R && T[row * TS + cq + e] <= b) ? (1u << e) : 0u;
+    }
+    // prefix over the quad (lanes 4 row .. 4 row + 3): quad_perm broadcasts of each lane's count
+    const int np = __popc(pm);
+    const int n0 = __builtin_amdgcn_mov_dpp(np, 0x00, 0xF, 0xF, false);
+    const int n1 = __builtin_amdgcn_mov_dpp(np, 0x55, 0xF, 0xF, false);
+    const int n2 = __builtin_amdgcn_mov_dpp(np, 0xAA, 0xF, 0xF, false);
+    const int n3 = __builtin_amdgcn_mov_dpp(np, 0xFF, 0xF, 0xF, false);
+    int at = (c4 > 0 ? n0 : 0) + (c4 > 1 ? n1 : 0) + (c4 > 2 ? n2 : 0);
+    const int64_t tile = jb / 64;
+    const int64_t base = (rr * nseg + sl) * ntmax + tile;
+    if (c4 == 0) tcnt[base] = n0 + n1 + n2 + n3;
+    uint64_t* L = slots + base * SMAX;
+    while (pm) {
+      const int e = __ffs(pm) - 1;
+      pm &= pm - 1;
+      if (at < SMAX) L[at] = ((uint64_t)__float_as_uint(T[row * TS + cq + e]) << 32) | (uint64_t)(jb + cq + e);
+      at++;
     }
   }
 }
 
-// One wave per (row, shard): kp = min(t + 16, R_s) candidate keys (GEMM-form distance bits << 32 | ghost index
-// within the shard), ascending, into cand[((s - s0) * rows_total + row0 + rl) * KP], the rest of the KP slots kDummy.
-template <int CAP>
-__global__ __launch_bounds__(256) void dense_select3_kernel(
-    const float* __restrict__ D, const float* __restrict__ M, int64_t ncols, const int64_t* __restrict__ seg_off,
-    const int64_t* __restrict__ seg_R, int s0, int nseg, const int* __restrict__ nrows_dev, int64_t nrows_max,
-    int64_t row0, int64_t rows_chunk, int64_t rows_total, int t, int KP, uint64_t* __restrict__ cand) {
-  constexpr int NR = CAP / 64;
-  __shared__ uint64_t bufs[4 * CAP];
+// One wave per (row, shard): the bound for pass 2 = the kp-th smallest of the 4 smallest 8-column minima of
+// every lane (a subset of the shard's distances, so at least kp distances lie at or below it; +inf when the
+// shard has fewer than kp groups).
+__global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int64_t ncols,
+                                                          const int64_t* __restrict__ off,
+                                                          const int64_t* __restrict__ Rs, int s0, int nseg,
+                                                          int64_t col0, const int* __restrict__ nrows_dev,
+                                                          int64_t nrows_max, int64_t row0, int64_t rows_chunk, int t,
+                                                          float* __restrict__ bound) {
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t item = (int64_t)blockIdx.x * 4 + wave;
   const int64_t rl = item / nseg;
@@ -831,111 +874,193 @@ __global__ __launch_bounds__(256) void dense_select3_kernel(
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   if (rl >= rows_chunk || row0 + rl >= n_rows) return;
   const int s = s0 + sl;
-  const int64_t cb = seg_off[s] - seg_off[s0];  // first column of the shard within the chunk's columns
-  const int64_t R = seg_R[s];
+  const int64_t R = Rs[s];
   const int kp = (int)(t + 16 < R ? t + 16 : R);
-  uint64_t* o = cand + ((int64_t)sl * rows_total + row0 + rl) * KP;
-  if (R == 0) {
-    for (int i = lane; i < KP; i += 64) o[i] = kDummy;
-    return;
-  }
-  uint64_t* buf = bufs + wave * CAP;
-  const float* d = D + rl * ncols + cb;
-  const float* m = M + rl * (ncols / 32) + cb / 32;
-  const int64_t nht = (R + 31) / 32;
-  // the kp-th smallest half-tile minimum bounds the kp-th smallest distance from above
-  uint64_t mm[2] = {kDummy, kDummy};
-  for (int64_t j = lane; j < nht; j += 64) {
-    const uint64_t key = ((uint64_t)__float_as_uint(m[j]) << 32) | (uint64_t)j;
-    if (key < mm[0]) {
-      mm[1] = mm[0];
-      mm[0] = key;
-    } else if (key < mm[1]) {
-      mm[1] = key;
+  const int64_t ng = (R + DG - 1) / DG;
+  const float* m = M + rl * (ncols / DG) + (off[s] - col0) / DG;
+  // keys = distance bits (non-negative floats order like their bits); 0xFFFFFFFF = none
+  uint64_t v[4] = {kDummy, kDummy, kDummy, kDummy};
+  for (int64_t g = lane; g < ng; g += 64) {
+    uint64_t x = ((uint64_t)__float_as_uint(m[g]) << 32) | (uint64_t)g;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {  // insertion into the lane's 4 smallest
+      const uint64_t lo = x < v[i] ? x : v[i];
+      x = x < v[i] ? v[i] : x;
+      v[i] = lo;
     }
   }
-  bitonic_sort_regs<2>(mm);
-  const int rb = (kp - 1) >> 6, lb = (kp - 1) & 63;
-  const uint64_t bk = shfl_u64(rb == 0 ? mm[0] : mm[1], lb);
-  // keys at or below the bound distance (every key when fewer than kp half tiles)
-  uint64_t bound = bk == kDummy ? kDummy : ((bk | 0xFFFFFFFFull));
-  uint64_t v[NR];
-  for (;;) {
-    // 4 columns per lane per step (rows of the segment are padded to 64 columns)
-    int cnt = 0;
-    for (int64_t j0 = 0; j0 < R; j0 += 256) {
-      const int64_t jb = j0 + 4 * lane;
-      const float4 x = jb < R ? *(const float4*)&d[jb] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float xs[4] = {x.x, x.y, x.z, x.w};
+  bitonic_sort_regs<4>(v);
+  const int rk = (kp - 1) >> 6, lk = (kp - 1) & 63;
+  uint64_t x = v[0];
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int64_t j = jb + e;
-        const uint64_t key = ((uint64_t)__float_as_uint(xs[e]) << 32) | (uint64_t)j;
-        const bool pass = j < R && key <= bound;
-        const uint64_t bm = ballot(pass);
-        const int pos = cnt + lanes_below(bm);
-        if (pass && pos < CAP) buf[pos] = key;
-        cnt += __popcll(bm);
+  for (int r = 1; r < 4; r++)
+    if (r == rk) x = v[r];
+  const uint64_t b = shfl_u64(x, lk);
+  if (lane == 0) bound[rl * nseg + sl] = b == kDummy ? INFINITY : __uint_as_float((uint32_t)(b >> 32));
+}
+
+// Exact distance (the search's definition) of query row q to a stored row, by an 8-lane team; every lane of the
+// team returns the team's result.
+template <int DT>
+__device__ __forceinline__ uint32_t exact_dist_team(const void* __restrict__ Q, int64_t qi, const void* __restrict__ brow,
+                                                    float bscale, int bpad, int tl) {
+  constexpr int P16 = Fmt<DT>::per16;
+  constexpr int ESZ = Fmt<DT>::esize;
+  const int row16 = bpad * ESZ / 16;
+  const uint4* b4 = (const uint4*)brow;
+  if constexpr (DT == DT_U8) {
+    const uint4* q4 = (const uint4*)((const uint8_t*)Q + (size_t)qi * bpad);
+    int acc = 0;
+    for (int c = tl; c < row16; c += 8) {
+      const uint4 xb = b4[c], qb = q4[c];
+      const uint32_t xw[4] = {xb.x, xb.y, xb.z, xb.w}, qw[4] = {qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int t = (int)((qw[e >> 2] >> (8 * (e & 3))) & 0xFF) - (int)((xw[e >> 2] >> (8 * (e & 3))) & 0xFF);
+        acc += t * t;
       }
     }
-    wsync();
+    acc += xor_lane_i32(acc, 1);
+    acc += xor_lane_i32(acc, 2);
+    acc += xor_lane_i32(acc, 4);
+    return (uint32_t)acc;
+  } else {
+    const float* qrow = (const float*)Q + (size_t)qi * bpad;
+    double acc = 0.0;
+    for (int c = tl; c < row16; c += 8) {
+      float x[P16];
+      decode16<DT>(b4[c], x);
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-      const int i = r * 64 + lane;
-      v[r] = i < cnt && i < CAP ? buf[i] : kDummy;
+      for (int e = 0; e < P16; e++) {
+        const float xe = (DT == DT_F16 || DT == DT_FP8) ? bscale * x[e] : x[e];
+        const float t = qrow[c * P16 + e] - xe;
+        acc = __builtin_fma((double)t, (double)t, acc);
+      }
     }
-    wsync();
-    // sort only as many 64-key registers as hold keys
-    if (cnt <= 64) {
-      v[0] = bitonic_sort_u64<64>(v[0]);
-    } else if (cnt <= 128) {
-      uint64_t w2[2] = {v[0], v[1]};
-      bitonic_sort_regs<2>(w2);
-      v[0] = w2[0];
-      v[1] = w2[1];
-    } else {
-      bitonic_sort_regs<NR>(v);
-    }
-    if (cnt <= CAP) break;
-    uint64_t x = v[0];
-#pragma unroll
-    for (int r = 1; r < NR; r++)
-      if (r == rb) x = v[r];
-    bound = shfl_u64(x, lb);
-  }
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    const int i = r * 64 + lane;
-    if (i < KP) o[i] = i < kp ? v[r] : kDummy;
+    acc += xor_lane_f64(acc, 1);
+    acc += xor_lane_f64(acc, 2);
+    acc += xor_lane_f64(acc, 4);
+    return __float_as_uint((float)acc);
   }
 }
 
-__global__ void dense_out2_kernel(const uint64_t* __restrict__ best, const uint32_t* __restrict__ list,
-                                  const int* __restrict__ count, int64_t nmax, int t, const uint32_t* __restrict__ g_map,
-                                  int S, int shard, uint64_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t r = i / t;
-  const int j = (int)(i % t);
-  const int64_t n = count ? (int64_t)*count : nmax;
-  if (r >= n) return;
-  const uint32_t q = list ? list[r] : (uint32_t)r;
-  const uint64_t key = best[(size_t)q * t + j];
-  out[((size_t)q * S + shard) * t + j] =
-      key == kDummy ? kDummy : ((key & 0xFFFFFFFF00000000ull) | g_map[(uint32_t)key]);
+// One wave per (row, shard): sort the list's keys, rescore the kp smallest exactly, and write the exact top-t
+// seeds (dist bits << 32 | node id) to out[(q * S + s) * t + i]. A list that overflowed is replaced by an exact
+// scan of all the shard's ghosts, which gives the same exact top-t.
+template <int DT>
+__global__ __launch_bounds__(256) void dense_final_kernel(
+    const uint64_t* __restrict__ slots, const int* __restrict__ tcnt, int ntmax, const uint32_t* __restrict__ list,
+    const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
+    const int64_t* __restrict__ Rs, int s0, int nseg, int t, const DenseShardDev* __restrict__ shd,
+    const void* __restrict__ qraw, int d_pad, int S, uint64_t* __restrict__ out) {
+  constexpr int ESZ = Fmt<DT>::esize;
+  __shared__ uint64_t ebufs[4 * CAPG];
+  const int wave = threadIdx.x >> 6, lane = lane_id(), team = lane >> 3, tl = lane & 7;
+  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t rl = item / nseg;
+  const int sl = (int)(item % nseg);
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  if (rl >= rows_chunk || row0 + rl >= n_rows) return;
+  const int s = s0 + sl;
+  const int64_t R = Rs[s];
+  const int kp = (int)(t + 16 < R ? t + 16 : R);
+  const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+  const DenseShardDev sh = shd[s];
+  uint64_t* ebuf = ebufs + wave * CAPG;
+  const size_t row_bytes = (size_t)d_pad * ESZ;
+  // gather the tiles' slots: tile i (one per lane and round) holds min(tcnt, SMAX) keys
+  const int nt = (int)((R + 63) / 64);
+  const int64_t base = (rl * nseg + sl) * ntmax;
+  int n = 0;
+  bool over = false;
+  for (int i0 = 0; i0 < nt; i0 += 64) {
+    const int i = i0 + lane;
+    const int c = i < nt ? tcnt[base + i] : 0;
+    over |= __ballot(c > SMAX) != 0;
+    // inclusive prefix of c over the lanes
+    int pre = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = (int)shfl_u32((uint32_t)pre, lane >= o ? lane - o : lane);
+      pre += lane >= o ? y : 0;
+    }
+    const int at = n + pre - c;
+    if (!over)
+      for (int e = 0; e < c && at + e < CAPG; e++) ebuf[at + e] = slots[(base + i) * SMAX + e];
+    n += (int)shfl_u32((uint32_t)pre, 63);
+  }
+  over |= n > CAPG;
+  wsync();
+  uint64_t best;  // exact keys, ascending, one per lane (the first t are the result)
+  if (!over) {
+    uint64_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < n ? ebuf[r * 64 + lane] : kDummy;
+    wsync();
+    if (n <= 64) {
+      v[0] = bitonic_sort_u64<64>(v[0]);
+    } else if (n <= 128) {
+      uint64_t w[2] = {v[0], v[1]};
+      bitonic_sort_regs<2>(w);
+      v[0] = w[0];
+      v[1] = w[1];
+    } else {
+      bitonic_sort_regs<4>(v);
+    }
+    // the kp smallest GEMM-form keys, rescored exactly in rounds of 8 rows
+    ebuf[lane] = lane < kp ? v[0] : kDummy;
+    ebuf[64 + lane] = 64 + lane < kp ? v[1] : kDummy;
+    wsync();
+    for (int r0 = 0; r0 < kp; r0 += 8) {
+      const int ci = r0 + team;
+      const uint64_t key = ci < kp ? ebuf[ci] : kDummy;
+      const bool ok = key != kDummy;
+      const uint32_t j = ok ? (uint32_t)key : 0u;
+      const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[j] : 1.f;
+      const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)j * row_bytes, sc, d_pad, tl);
+      wsync();
+      if (tl == 0 && ci < kp) ebuf[ci] = ok ? (((uint64_t)db << 32) | j) : kDummy;
+      wsync();
+    }
+    uint64_t w[2] = {ebuf[lane], 64 + lane < kp ? ebuf[64 + lane] : kDummy};
+    if (lane >= kp) w[0] = kDummy;
+    bitonic_sort_regs<2>(w);
+    best = w[0];
+  } else {
+    // a tile or the row overflowed its slots: exact scan, 64 ghosts per round, merged into the running 64 best
+    best = kDummy;
+    for (int64_t g0 = 0; g0 < R; g0 += 64) {
+      for (int r0 = 0; r0 < 64; r0 += 8) {
+        const int64_t j = g0 + r0 + team;
+        const bool ok = j < R;
+        const uint32_t jj = ok ? (uint32_t)j : 0u;
+        const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[jj] : 1.f;
+        const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)jj * row_bytes, sc, d_pad, tl);
+        if (tl == 0) ebuf[r0 + team] = ok ? (((uint64_t)db << 32) | jj) : kDummy;
+      }
+      wsync();
+      uint64_t c = bitonic_sort_u64<64>(ebuf[lane]);
+      wsync();
+      const uint64_t cr = reverse_lanes_u64(c);
+      best = bitonic_merge_u64(best < cr ? best : cr);
+    }
+  }
+  if (lane < t) {
+    out[((size_t)qi * S + s) * t + lane] =
+        best == kDummy ? kDummy : ((best & 0xFFFFFFFF00000000ull) | sh.g_map[(uint32_t)best]);
+  }
 }
 
 hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int d, int d_pad, int dk,
-                             const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G,
-                             const DenseShard* shards, int t, uint64_t* out, hipStream_t st) {
+                             const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G, int t, uint64_t* out,
+                             hipStream_t st) {
   if (nq == 0) return hipSuccess;
   const int qdt = store_dt == DT_U8 ? DT_U8 : DT_F32;
-  const int KP = t + 16;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t sz_qf = al((size_t)nq * dk * 4), sz_qb = al((size_t)nq * dk * 2), sz_qn = al((size_t)nq * 4);
   const size_t sz_qraw = al((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4));
   const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
-  const size_t sz_cand = al((size_t)nq * S * KP * 8), sz_best = al((size_t)nq * t * 8);
-  const size_t total = sz_qf + 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt + sz_cand + sz_best;
+  const size_t total = sz_qf + 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
   char* buf = nullptr;
   hipError_t e = hipMallocAsync((void**)&buf, total, st);
   if (e != hipSuccess) return e;
@@ -946,9 +1071,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   float* qn = (float*)p; p += sz_qn;
   void* qraw = p; p += sz_qraw;
   uint32_t* list = (uint32_t*)p; p += sz_list;
-  int* cnt = (int*)p; p += sz_cnt;
-  uint64_t* cand = (uint64_t*)p; p += sz_cand;
-  uint64_t* best = (uint64_t*)p;
+  int* qcnt = (int*)p;
   e = queries_to_f32(queries, qdt, nq, d, dk, qf, st);
   if (e == hipSuccess) e = split_rows(qf, nq, nq, dk, qh, ql, qn, st);
   if (e == hipSuccess) {
@@ -962,51 +1085,67 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   }
   // (rows, shard range) passes: every query against every shard, or each shard against the queries starting there
   const int npass = start_only ? S : 1;
-  float* Dm = nullptr;
   for (int ps = 0; ps < npass && e == hipSuccess; ps++) {
     const int s0 = start_only ? ps : 0, s1 = start_only ? ps + 1 : S;
+    const int nseg = s1 - s0;
     const int64_t col0 = G.off[s0], ncols = G.off[s1] - G.off[s0];
     if (ncols == 0) continue;
     const uint32_t* rl = nullptr;
     const int* rc = nullptr;
     if (start_only) {
-      hipLaunchKernelGGL(fill_cnt_kernel, dim3(1), dim3(1), 0, st, cnt);
+      hipLaunchKernelGGL(fill_cnt_kernel, dim3(1), dim3(1), 0, st, qcnt);
       hipLaunchKernelGGL(shard_qlist_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, qkeys, S, s0,
-                         0, list, cnt);
+                         0, list, qcnt);
       rl = list;
-      rc = cnt;
+      rc = qcnt;
     }
-    int64_t chunk = ((int64_t)1 << 27) / ncols;  // at most 512 MB of distances at a time
+    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], tile counts [rows][nseg][ntmax],
+    // slots [rows][nseg][ntmax][SMAX]
+    int64_t ntmax = 0;
+    for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
+    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)ntmax * (4 + SMAX * 8));
+    int64_t chunk = ((int64_t)1 << 29) / (int64_t)per_row;  // at most 512 MB of scratch
     chunk = chunk < 64 ? 64 : chunk / 64 * 64;
     if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
-    if (!Dm) e = hipMallocAsync((void**)&Dm, (size_t)chunk * ncols * 4 + (size_t)chunk * (ncols / 32) * 4, st);
-    float* D = Dm;
-    float* M = Dm + (size_t)chunk * ncols;
-    const int nseg = s1 - s0;
+    char* wb = nullptr;
+    e = hipMallocAsync((void**)&wb, (size_t)chunk * per_row + 4096, st);
+    if (e != hipSuccess) break;
+    uint64_t* slots = (uint64_t*)wb;
+    float* Mg = (float*)(slots + (size_t)chunk * nseg * ntmax * SMAX);
+    float* bnd = Mg + (size_t)chunk * (ncols / DG);
+    int* tcnt = (int*)(bnd + (size_t)chunk * nseg);
+    const dim3 gg((unsigned)(ncols / 64), (unsigned)(chunk / 64));
+    const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
+    const int ntm = (int)ntmax;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
-      hipLaunchKernelGGL(dense_gemm3_kernel, dim3((unsigned)(ncols / 64), (unsigned)(chunk / 64)), dim3(256), 0, st,
-                         qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo, G.norm, col0, ncols, dk, D, M);
-      hipLaunchKernelGGL(dense_select3_kernel<256>, dim3((unsigned)((chunk * nseg + 3) / 4)), dim3(256), 0, st, D, M,
-                         ncols, G.off_dev, G.R_dev, s0, nseg, rc, nq, row0, chunk, nq, t, KP, cand);
+      hipLaunchKernelGGL(dense_pass_kernel<0>, gg, dim3(256), 0, st, qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo,
+                         G.norm, col0, ncols, dk, G.off_dev, G.R_dev, s0, nseg, ntm, Mg, bnd, tcnt, slots);
+      hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, ncols, G.off_dev, G.R_dev, s0, nseg,
+                         col0, rc, nq, row0, chunk, t, bnd);
+      hipLaunchKernelGGL(dense_pass_kernel<1>, gg, dim3(256), 0, st, qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo,
+                         G.norm, col0, ncols, dk, G.off_dev, G.R_dev, s0, nseg, ntm, Mg, bnd, tcnt, slots);
+      switch (store_dt) {
+        case DT_F32:
+          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
+          break;
+        case DT_F16:
+          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
+          break;
+        case DT_FP8:
+          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
+          break;
+        default:
+          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
+          break;
+      }
       e = hipGetLastError();
     }
-    for (int s = s0; s < s1 && e == hipSuccess; s++) {
-      if (G.R[s] == 0) continue;
-      const uint64_t* cs = cand + (size_t)(s - s0) * nq * KP;
-      e = launch_rescore(store_dt, cs, nq, rc, KP, rl, qraw, shards[s].g_store, shards[s].g_scale, d_pad, t, best, st);
-      if (e == hipSuccess) {
-        hipLaunchKernelGGL(dense_out2_kernel, dim3((unsigned)((nq * t + 255) / 256)), dim3(256), 0, st, best, rl, rc,
-                           nq, t, shards[s].g_map, S, s, out);
-        e = hipGetLastError();
-      }
-    }
-    if (Dm && start_only) {
-      // chunk sizes differ per shard: release the buffer for the next pass
-      hipFreeAsync(Dm, st);
-      Dm = nullptr;
-    }
+    hipFreeAsync(wb, st);
   }
-  if (Dm) hipFreeAsync(Dm, st);
   hipFreeAsync(buf, st);
   return e;
 }

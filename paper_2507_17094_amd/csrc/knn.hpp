@@ -22,6 +22,11 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
 // Ghosts of all shards concatenated for the split-bf16 dense entry. Shard s
 // owns columns [off[s], off[s+1]) (a multiple of 64 wide; its R[s] real
 // ghosts first, then padding with norm +inf).
+struct DenseShardDev {
+  const void* g_store;  // [R][d_pad] ghost codes in the store type
+  const float* g_scale; // [R] or null
+  const uint32_t* g_map;// [R] ghost -> local node id
+};
 struct DenseGhosts {
   int64_t cols = 0;
   int dk = 0;                   // row length (elements), a multiple of 32
@@ -30,12 +35,8 @@ struct DenseGhosts {
   float* norm = nullptr;        // [cols]
   int64_t* off_dev = nullptr;   // [S + 1]
   int64_t* R_dev = nullptr;     // [S]
+  DenseShardDev* shards_dev = nullptr;  // [S]
   std::vector<int64_t> off, R;  // host copies
-};
-struct DenseShard {
-  const void* g_store;
-  const float* g_scale;
-  const uint32_t* g_map;
 };
 // hi / lo bf16 split and f32 norms of n rows ([n][dk] f32); rows n..n_pad padded (norm +inf).
 hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t* hi, uint16_t* lo, float* norm,
@@ -44,8 +45,8 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
 // the exact top-t ghosts of the shard by (dist, id), as keys (dist bits << 32 | local node id) in
 // out[(q * S + s) * t + i].
 hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int d, int d_pad, int dk,
-                             const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G,
-                             const DenseShard* shards, int t, uint64_t* out, hipStream_t st);
+                             const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G, int t, uint64_t* out,
+                             hipStream_t st);
 
 // Exact k-NN of A rows against B rows by MFMA tiles + direct-form rescoring.
 //   A_f32 [na][dpf], B_f32 [nb][dpf]: f32 copies for the GEMM-form selection.
