@@ -248,6 +248,8 @@ def form_learned(args):
     t_train = time.time() - t0
     log(f"build {t_build:.1f}s labels {t_labels:.1f}s train {t_train:.1f}s losses {losses}")
     gmap = learned.ghost_map(gx)
+    t_predict = time_search(lambda: P.predict(Qd, 32, 0.02, gmap, 4, T_max, 3.0))
+    log(f"predictor inference {t_predict * 1e3:.2f} ms for {W['nq']} queries")
     rows = []
     for itopk in (32, 64, 128):
         for T in (16, 32, 64, 128):
@@ -289,7 +291,8 @@ def form_learned(args):
                                f"{W['deg']}, {W['R']} ghosts; BF16 MLP {W['d']}-{W['hidden']}-{W['hidden']}-"
                                f"{W['R'] + 1} trained on {W['n_train']} queries, {W['nq']} held-out queries"},
         "ghost_staging": bg, "ghost_staging_dense": bd, "learned": bl, "gain_qps": bl["qps"] / bg["qps"],
-        "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "sweep": rows, "build_s": t_build,
+        "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "predict_ms": t_predict * 1e3,
+        "sweep": rows, "build_s": t_build,
     }
     print(json.dumps(out), flush=True)
 

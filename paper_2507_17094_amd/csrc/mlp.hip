@@ -32,13 +32,37 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; j++) acc[j] = 0.f;
+  // 16-byte staging where the operand is contiguous along the staged dimension (row-major A along K,
+  // row-major B along N) and the tile lies inside the matrix; element-wise staging otherwise
+  const bool a_vec = sac == 1 && (sar & 7) == 0 && (K & 7) == 0 && i0 + GT <= M;
+  const bool b_vec = sbc == 1 && (sbr & 7) == 0 && (N & 7) == 0 && j0 + GT <= N;
   for (int k0 = 0; k0 < K; k0 += GK) {
     __syncthreads();
-    for (int e = tid; e < GT * GK; e += 256) {
-      const int r = e / GK, c = e % GK;
-      const int gi = i0 + r, gk = k0 + c, gj = j0 + r;
-      As[r * GKP + c] = (gi < M && gk < K) ? A[(int64_t)gi * sar + (int64_t)gk * sac] : (uint16_t)0;
-      Bs[r * GKP + c] = (gj < N && gk < K) ? B[(int64_t)gk * sbr + (int64_t)gj * sbc] : (uint16_t)0;
+    const bool kfull = k0 + GK <= K;
+    if (a_vec && kfull) {
+      const int r = tid >> 2, c = (tid & 3) * 8;  // 64 rows x 32 k: one 8-element vector per thread
+      *(uint4*)&As[r * GKP + c] = *(const uint4*)&A[(int64_t)(i0 + r) * sar + k0 + c];
+    } else {
+      for (int e = tid; e < GT * GK; e += 256) {
+        const int r = sac == 1 ? e / GK : e % GT, c = sac == 1 ? e % GK : e / GT;
+        const int gi = i0 + r, gk = k0 + c;
+        As[r * GKP + c] = (gi < M && gk < K) ? A[(int64_t)gi * sar + (int64_t)gk * sac] : (uint16_t)0;
+      }
+    }
+    if (b_vec && kfull) {
+      // 32 k x 64 columns: thread -> (k = tid / 8, 8 consecutive columns), stored transposed
+      const int kk = tid >> 3, c = (tid & 7) * 8;
+      const uint4 v = *(const uint4*)&B[(int64_t)(k0 + kk) * sbr + j0 + c];
+      const uint16_t* h = (const uint16_t*)&v;
+#pragma unroll
+      for (int q = 0; q < 8; q++) Bs[(c + q) * GKP + kk] = h[q];
+    } else {
+      // consecutive threads walk the operand's contiguous dimension
+      for (int e = tid; e < GT * GK; e += 256) {
+        const int r = sbc == 1 ? e % GT : e / GK, c = sbc == 1 ? e / GT : e % GK;
+        const int gk = k0 + c, gj = j0 + r;
+        Bs[r * GKP + c] = (gj < N && gk < K) ? B[(int64_t)gk * sbr + (int64_t)gj * sbc] : (uint16_t)0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -199,9 +223,11 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
                                                       float budget_scale,
                                                       uint32_t* __restrict__ seeds, int32_t* __restrict__ iters,
                                                       float* __restrict__ conf, uint32_t* __restrict__ top_idx) {
+  __shared__ uint64_t sels[4 * 256];
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= n) return;
   const int lane = threadIdx.x & 63;
+  uint64_t* sel = sels + (threadIdx.x >> 6) * 256;
   const float* z = Z + (int64_t)b * (R + 1);
   float mx = -INFINITY;
   for (int j = lane; j < R; j += 64) mx = fmaxf(mx, z[j]);
@@ -212,27 +238,65 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
   const float c = 1.f / s;
-  // t rounds of (value desc, index asc) argmax over the logits
-  uint64_t prev = ~0ull;  // previous winner's key; keys strictly decrease
-  for (int r = 0; r < t; r++) {
-    uint64_t best = 0;
-    for (int j = lane; j < R; j += 64) {
-      const uint32_t fb = __float_as_uint(z[j]);
-      const uint32_t ord = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);  // order-preserving
-      const uint64_t key = ((uint64_t)ord << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)j);
-      if (key < prev && key > best) best = key;
-    }
+  // the t largest logits by (value desc, index asc), as ascending keys ((~ord(value)) << 32 | index)
+  auto key_of = [&](int j) {
+    const uint32_t fb = __float_as_uint(z[j]);
+    const uint32_t ord = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);  // order-preserving
+    return ((uint64_t)(~ord) << 32) | (uint64_t)j;
+  };
+  // bound: the t-th smallest of the two smallest keys of every lane (a subset of the keys)
+  uint64_t m2[2] = {~0ull, ~0ull};
+  for (int j = lane; j < R; j += 64) {
+    uint64_t x = key_of(j);
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t other = shfl_xor_u64(best, o);
-      best = other > best ? other : best;
+    for (int i = 0; i < 2; i++) {
+      const uint64_t lo = x < m2[i] ? x : m2[i];
+      x = x < m2[i] ? m2[i] : x;
+      m2[i] = lo;
     }
-    prev = best;
-    if (lane == 0) {
-      const uint32_t j = 0xFFFFFFFFu - (uint32_t)best;
-      if (top_idx) top_idx[(int64_t)b * t + r] = j;
-      seeds[(int64_t)b * t + r] = (r == 0 && c < tau) ? kNone : gmap[j];
+  }
+  bitonic_sort_regs<2>(m2);
+  const uint64_t bound = shfl_u64(t > 64 ? m2[1] : m2[0], (t - 1) & 63);
+  // collect the keys at or below the bound (at least t of them) and sort them
+  int cnt = 0;
+  for (int j0 = 0; j0 < R; j0 += 64) {
+    const int j = j0 + lane;
+    const uint64_t key = j < R ? key_of(j) : ~0ull;
+    const bool pass = j < R && key <= bound;
+    const uint64_t bm = __ballot(pass);
+    const int pos = cnt + lanes_below(bm);
+    if (pass && pos < 256) sel[pos] = key;
+    cnt += __popcll(bm);
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < cnt && r * 64 + lane < 256 ? sel[r * 64 + lane] : ~0ull;
+  bitonic_sort_regs<4>(v);
+  if (cnt > 256) {
+    // more than 256 keys at the bound: t rounds of argmax instead
+    uint64_t prev = 0;  // keys strictly increase
+    for (int r = 0; r < t; r++) {
+      uint64_t best = ~0ull;
+      for (int j = lane; j < R; j += 64) {
+        const uint64_t key = key_of(j);
+        if ((r == 0 || key > prev) && key < best) best = key;
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t other = shfl_xor_u64(best, o);
+        best = other < best ? other : best;
+      }
+      prev = best;
+      if (lane == 0) sel[r] = best;
     }
+    __builtin_amdgcn_wave_barrier();
+    v[0] = lane < t ? sel[lane] : ~0ull;
+  }
+  if (lane < t) {
+    const uint32_t j = (uint32_t)v[0];
+    if (top_idx) top_idx[(int64_t)b * t + lane] = j;
+    seeds[(int64_t)b * t + lane] = (lane == 0 && c < tau) ? kNone : gmap[j];
   }
   if (lane == 0) {
     const float yb = z[R];
