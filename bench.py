@@ -86,6 +86,25 @@ def oracle_from_device(gx, X):
     return ox
 
 
+def measured_traffic(workload, itopk, T, opts):
+    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE) per stage launch from the committed rocprofv3 record, when
+    the stage kernel's sources and the setting are those the counters were taken on; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    st = rec["setting"]
+    same = (h.hexdigest() == rec["sources_sha256"] and workload == rec["workload"] and itopk == st["itopk"] and
+            T == st["T"] and opts.entry == st["entry"] and opts.search_width == st["search_width"] and
+            bool(opts.ghost_every_stage) == st["ghost_every_stage"])
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"] if same else None
+
+
 def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_stage):
     """Bytes the stage kernel must move per batch, from the per-query counters.
     HBM-resident arrays: gathered vectors (n_dist rows), adjacency rows (n_exp),
@@ -563,7 +582,8 @@ def main():
                    "recall@10": best["recall"], "distance_accumulation": "f64 of f32 inputs"},
         "latency_ms": {"batch_p50": float(np.percentile(step_ms, 50)), "batch_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload, itopk, T, opts),
+                     "traffic_unit": "bytes per stage launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "stage_kernel", "stage_ms": [float(x) for x in stage_ms],
                      "dense_entry_ms": float(phases[0]), "merge_ms": float(phases[-1]),
                      "bytes_per_launch": bytes_total / S,
