@@ -355,6 +355,15 @@ def form_serving(args):
         if len(sub_q):
             cap_s += time_search(lambda: gx.search(sub_q, k, itopk, T, opts), reps=2)
     cap_qps = len(pool) / cap_s
+    # latency floor: single-query requests one at a time on an idle server
+    srv = miann.Server(gx, num_streams=4, max_batch_queries=8192, max_inflight_queries=65536)
+    idle = []
+    for j in range(60):
+        tk = srv.submit(pool[j:j + 1], 10, *setting[10], opts)
+        idle.append(srv.wait(tk, 1, 10)[2])
+    srv.close()
+    idle = np.array(idle[10:])
+    log(f"idle single-query latency p50 {np.percentile(idle, 50):.3f} ms p99 {np.percentile(idle, 99):.3f} ms")
     results = []
     for load_frac in (0.25, 0.5, 0.75):
         mean_q = float(sizes.mean())
@@ -400,6 +409,7 @@ def form_serving(args):
                                f"1-1024 queries (log-uniform), k in {{10, 100}}"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps, "rates": results,
+        "idle_single_query_ms": {"p50": float(np.percentile(idle, 50)), "p99": float(np.percentile(idle, 99))},
         "build_s": t_build,
     }
     print(json.dumps(out), flush=True)

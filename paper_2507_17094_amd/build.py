@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmiann.so")
-SOURCES = ["search.hip", "build.hip", "knn.hip", "mlp.hip", "capi.cpp", "predictor.cpp", "serve.cpp"]
+SOURCES = ["search.hip", "build.hip", "knn.hip", "mlp.hip", "capi.cpp", "predictor.cpp", "serve.cpp", "pool.cpp"]
 ARCH = os.environ.get("MIANN_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,6 +1,7 @@
 // Index-preparation kernels: padded copies, per-vector quantisation, the
 // direction sign table (Sec. 3.3.2 (a), Sec. 4), row gathers, small fills.
 #include "build.hpp"
+#include "pool.hpp"
 #include "common.hpp"
 
 namespace miann {
@@ -209,7 +210,7 @@ hipError_t count_out_of_range(const uint32_t* ids, int64_t n, uint32_t limit, in
   *host_bad = 0;
   if (n == 0) return hipSuccess;
   unsigned long long* d = nullptr;
-  hipError_t e = hipMallocAsync((void**)&d, 8, st);
+  hipError_t e = pool_malloc_async((void**)&d, 8, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, st, (uint32_t*)d, 2, 0u);
   hipLaunchKernelGGL(count_bad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ids, n, limit, allow_none, d);

@@ -13,6 +13,7 @@
 
 #include "../../include/miann.h"
 #include "build.hpp"
+#include "pool.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 #include "knn.hpp"
@@ -515,7 +516,7 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     off_dense = total;
     total += (size_t)nq * ix->S * t_seeds * 8;
   }
-  if (total) HIP_TRY(hipMallocAsync(&scratch, total, st));
+  if (total) HIP_TRY(pool_malloc_async(&scratch, total, st));
   char* sb = (char*)scratch;
   miann_status rc = MIANN_OK;
   // optional timing: events around [dense, stage 0..S-1, merge]
@@ -587,7 +588,7 @@ struct Temps {
   template <typename T>
   hipError_t get(T** p, size_t bytes) {
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, bytes ? bytes : 16, st);
+    hipError_t e = pool_malloc_async(&q, bytes ? bytes : 16, st);
     if (e == hipSuccess) { v.push_back(q); *p = (T*)q; }
     return e;
   }

@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "pool.hpp"
 #include "knn.hpp"
 
 namespace miann {
@@ -435,9 +436,9 @@ hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t
   if (kp < k) kp = k;
   float *an = nullptr, *bn = nullptr;
   uint64_t* cand = nullptr;
-  hipError_t e = hipMallocAsync(&an, (size_t)na * 4, st);
-  if (e == hipSuccess) e = hipMallocAsync(&bn, (size_t)nb * 4, st);
-  if (e == hipSuccess) e = hipMallocAsync(&cand, (size_t)na * kp * 8, st);
+  hipError_t e = pool_malloc_async(&an, (size_t)na * 4, st);
+  if (e == hipSuccess) e = pool_malloc_async(&bn, (size_t)nb * 4, st);
+  if (e == hipSuccess) e = pool_malloc_async(&cand, (size_t)na * kp * 8, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((na + 3) / 4)), dim3(256), 0, st, A_f32, na, dpf, an);
     hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, B_f32, nb, dpf, bn);
@@ -621,7 +622,7 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
   const size_t sz_cand = ((size_t)nq * kp * 8 + 255) & ~(size_t)255;
   const size_t sz_best = (size_t)nq * t * 8;
   const size_t total = sz_list + sz_cnt + sz_qf + sz_qraw + sz_qn + sz_gn + sz_cand + sz_best;
-  hipError_t e = hipMallocAsync((void**)&buf, total, st);
+  hipError_t e = pool_malloc_async((void**)&buf, total, st);
   if (e != hipSuccess) return e;
   char* p = buf;
   uint32_t* list = (uint32_t*)p; p += sz_list;
@@ -655,7 +656,7 @@ hipError_t dense_entry(int store_dt, const void* queries, int64_t nq, int d, con
   chunk = chunk < 64 ? 64 : chunk / 64 * 64;
   if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
   float* D = nullptr;
-  if (e == hipSuccess) e = hipMallocAsync((void**)&D, (size_t)chunk * ldd * 4, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&D, (size_t)chunk * ldd * 4, st);
   for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
     hipLaunchKernelGGL(dense_gemm_kernel, dim3((unsigned)(ldd / 64), (unsigned)(chunk / 64)), dim3(256), 0, st, qf,
                        qn, cnt, nq, list, row0, chunk, g_f32, gn, R, d_pad_f32, ldd, D);
@@ -1062,7 +1063,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
   const size_t total = sz_qf + 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
   char* buf = nullptr;
-  hipError_t e = hipMallocAsync((void**)&buf, total, st);
+  hipError_t e = pool_malloc_async((void**)&buf, total, st);
   if (e != hipSuccess) return e;
   char* p = buf;
   float* qf = (float*)p; p += sz_qf;
@@ -1108,7 +1109,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     chunk = chunk < 64 ? 64 : chunk / 64 * 64;
     if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
     char* wb = nullptr;
-    e = hipMallocAsync((void**)&wb, (size_t)chunk * per_row + 4096, st);
+    e = pool_malloc_async((void**)&wb, (size_t)chunk * per_row + 4096, st);
     if (e != hipSuccess) break;
     uint64_t* slots = (uint64_t*)wb;
     float* Mg = (float*)(slots + (size_t)chunk * nseg * ntmax * SMAX);
@@ -1249,10 +1250,10 @@ hipError_t prune_graph(const uint64_t* knn, int64_t n, int K0, int deg, uint32_t
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   const int64_t nh = n * h;
-  hipError_t e = hipMallocAsync((void**)&cnt, (size_t)(n + 1) * 4, st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&fill, (size_t)(n + 1) * 4, st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&off, (size_t)(n + 1) * 8, st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&rev, (size_t)(nh ? nh : 1) * 8, st);
+  hipError_t e = pool_malloc_async((void**)&cnt, (size_t)(n + 1) * 4, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&fill, (size_t)(n + 1) * 4, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&off, (size_t)(n + 1) * 8, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&rev, (size_t)(nh ? nh : 1) * 8, st);
   if (e != hipSuccess) return e;
   const unsigned gn = (unsigned)((n + 1 + 255) / 256);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(gn), dim3(256), 0, st, cnt, n + 1);
@@ -1260,12 +1261,12 @@ hipError_t prune_graph(const uint64_t* knn, int64_t n, int K0, int deg, uint32_t
   hipLaunchKernelGGL(rev_count_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, knn, n, K0, h, cnt);
   // exclusive prefix over n + 1 counts (the last count is 0) -> off[0..n]
   int64_t* cnt64 = nullptr;
-  e = hipMallocAsync((void**)&cnt64, (size_t)(n + 1) * 8, st);
+  e = pool_malloc_async((void**)&cnt64, (size_t)(n + 1) * 8, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(widen_kernel, dim3(gn), dim3(256), 0, st, cnt, n + 1, cnt64);
     e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt64, off, (int)(n + 1), st);
   }
-  if (e == hipSuccess) e = hipMallocAsync(&tmp, tmp_bytes ? tmp_bytes : 16, st);
+  if (e == hipSuccess) e = pool_malloc_async(&tmp, tmp_bytes ? tmp_bytes : 16, st);
   if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt64, off, (int)(n + 1), st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(rev_fill_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, knn, n, K0, h, off, fill,
@@ -1299,14 +1300,14 @@ hipError_t keyed_order(uint64_t seed, int64_t n, uint32_t* out, hipStream_t st) 
   uint32_t* v0 = nullptr;
   void* tmp = nullptr;
   size_t tb = 0;
-  hipError_t e = hipMallocAsync((void**)&k0, (size_t)n * 8, st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&k1, (size_t)n * 8, st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&v0, (size_t)n * 4, st);
+  hipError_t e = pool_malloc_async((void**)&k0, (size_t)n * 8, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&k1, (size_t)n * 8, st);
+  if (e == hipSuccess) e = pool_malloc_async((void**)&v0, (size_t)n * 4, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sm_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, n, k0, v0);
   // radix sort is stable and the ids enter in increasing order: ties in the key keep id order
   e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, k1, v0, out, (int)n, 0, 64, st);
-  if (e == hipSuccess) e = hipMallocAsync(&tmp, tb ? tb : 16, st);
+  if (e == hipSuccess) e = pool_malloc_async(&tmp, tb ? tb : 16, st);
   if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, k1, v0, out, (int)n, 0, 64, st);
   hipFreeAsync(k0, st);
   hipFreeAsync(k1, st);
@@ -1319,10 +1320,10 @@ hipError_t sort_u32(uint32_t* v, int64_t n, hipStream_t st) {
   uint32_t* o = nullptr;
   void* tmp = nullptr;
   size_t tb = 0;
-  hipError_t e = hipMallocAsync((void**)&o, (size_t)n * 4, st);
+  hipError_t e = pool_malloc_async((void**)&o, (size_t)n * 4, st);
   if (e != hipSuccess) return e;
   e = hipcub::DeviceRadixSort::SortKeys(nullptr, tb, v, o, (int)n, 0, 32, st);
-  if (e == hipSuccess) e = hipMallocAsync(&tmp, tb ? tb : 16, st);
+  if (e == hipSuccess) e = pool_malloc_async(&tmp, tb ? tb : 16, st);
   if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortKeys(tmp, tb, v, o, (int)n, 0, 32, st);
   if (e == hipSuccess) e = hipMemcpyAsync(v, o, (size_t)n * 4, hipMemcpyDeviceToDevice, st);
   hipFreeAsync(o, st);

@@ -13,6 +13,7 @@
 
 #include "../../include/miann.h"
 #include "common.hpp"
+#include "pool.hpp"
 #include "knn.hpp"
 #include "mlp.hpp"
 
@@ -58,7 +59,7 @@ struct Work {
   template <typename T>
   hipError_t get(T** p, size_t bytes) {
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, bytes ? bytes : 16, st);
+    hipError_t e = pool_malloc_async(&q, bytes ? bytes : 16, st);
     if (e == hipSuccess) { v.push_back(q); *p = (T*)q; }
     return e;
   }
