@@ -275,7 +275,11 @@ miann_status miann_predictor_predict(const miann_predictor* p, const float* x_de
  * admits a batch only while the in-flight queries and device bytes stay within
  * max_inflight_queries and memory_budget_bytes, and runs batches concurrently
  * on num_streams HIP streams. Queries are searched with their index inside
- * their request as the query key, so results are the same alone and in any mix. */
+ * their request as the query key, so results are the same alone and in any mix.
+ * Each stream's host and device staging buffers are allocated by
+ * miann_server_create for a full batch with k <= 128 (fewer queries if the
+ * memory budget does not cover that); a batch beyond that grows them once, a
+ * step that blocks the scheduler. */
 typedef struct miann_server miann_server;
 
 typedef struct {

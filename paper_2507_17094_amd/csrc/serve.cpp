@@ -35,6 +35,10 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// Result width the slot buffers are allocated for up front, so that no
+// allocation (which can serialise the device) happens while serving.
+constexpr int32_t kPreallocK = 128;
+
 struct Request {
   uint64_t ticket = 0;
   int64_t nq = 0;
@@ -74,6 +78,7 @@ struct miann_server {
   const miann_index* idx = nullptr;
   miann_server_config cfg{};
   int esize = 4, d = 0;
+  int64_t prealloc_nq = 0;  // queries the slot buffers hold without growing
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -92,17 +97,14 @@ struct miann_server {
   }
 
   void loop();
+  bool reserve(Slot& s, int64_t nq, int32_t k);
   bool launch(Slot& s, std::vector<std::shared_ptr<Request>>& batch);
   void finish(Slot& s, miann_status st, const char* err);
 };
 
-bool miann_server::launch(Slot& s, std::vector<std::shared_ptr<Request>>& batch) {
-  int64_t nq = 0;
-  for (auto& r : batch) nq += r->nq;
-  const int32_t k = batch[0]->k;
+bool miann_server::reserve(Slot& s, int64_t nq, int32_t k) {
   const size_t qbytes = (size_t)nq * d * esize, kbytes = (size_t)nq * 8;
   const size_t obytes = (size_t)nq * k * 8;
-  // buffers grow to the largest batch seen on this slot
   if (qbytes + kbytes > s.cap_in) {
     if (s.h_in) hipHostFree(s.h_in);
     s.cap_in = qbytes + kbytes;
@@ -118,6 +120,16 @@ bool miann_server::launch(Slot& s, std::vector<std::shared_ptr<Request>>& batch)
     s.cap_dev = qbytes + kbytes + obytes + 1024;
     if (hipMalloc(&s.d_buf, s.cap_dev) != hipSuccess) { s.d_buf = nullptr; s.cap_dev = 0; return false; }
   }
+  return true;
+}
+
+bool miann_server::launch(Slot& s, std::vector<std::shared_ptr<Request>>& batch) {
+  int64_t nq = 0;
+  for (auto& r : batch) nq += r->nq;
+  const int32_t k = batch[0]->k;
+  const size_t qbytes = (size_t)nq * d * esize, kbytes = (size_t)nq * 8;
+  // buffers are sized at creation for a full batch of k <= kPreallocK; larger k grows them (a blocking step)
+  if (!reserve(s, std::max<int64_t>(nq, prealloc_nq), std::max<int32_t>(k, kPreallocK))) return false;
   char* hi = (char*)s.h_in;
   uint64_t* hk = (uint64_t*)(hi + qbytes);
   int64_t off = 0;
@@ -245,6 +257,22 @@ void miann_server::loop() {
   }
 }
 
+namespace {
+
+void miann_server_destroy_slots(miann_server* s) {
+  for (auto& sl : s->slots) {
+    if (sl.st) hipStreamSynchronize(sl.st);
+    if (sl.d_buf) hipFree(sl.d_buf);
+    if (sl.h_in) hipHostFree(sl.h_in);
+    if (sl.h_out) hipHostFree(sl.h_out);
+    if (sl.ev) hipEventDestroy(sl.ev);
+    if (sl.st) hipStreamDestroy(sl.st);
+  }
+  s->slots.clear();
+}
+
+}  // namespace
+
 extern "C" {
 
 void miann_server_config_default(miann_server_config* c) {
@@ -271,8 +299,19 @@ miann_status miann_server_create(const miann_index* idx, const miann_server_conf
   for (auto& sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+      miann_server_destroy_slots(s);
       delete s;
       return miann_fail(MIANN_EDEVICE, "miann_server_create: stream or event creation failed");
+    }
+  }
+  // full batches up front, as far as the memory budget covers them
+  s->prealloc_nq = std::max<int64_t>(1, std::min<int64_t>(c.max_batch_queries, c.memory_budget_bytes /
+                                                              (int64_t)s->batch_bytes(1, kPreallocK)));
+  for (auto& sl : s->slots) {
+    if (!s->reserve(sl, s->prealloc_nq, kPreallocK)) {
+      miann_server_destroy_slots(s);
+      delete s;
+      return miann_fail(MIANN_ENOMEM, "miann_server_create: slot buffer allocation failed");
     }
   }
   s->t0 = clk::now();
@@ -349,14 +388,7 @@ void miann_server_destroy(miann_server* s) {
   }
   s->cv_work.notify_all();
   if (s->th.joinable()) s->th.join();
-  for (auto& sl : s->slots) {
-    if (sl.st) hipStreamSynchronize(sl.st);
-    if (sl.d_buf) hipFree(sl.d_buf);
-    if (sl.h_in) hipHostFree(sl.h_in);
-    if (sl.h_out) hipHostFree(sl.h_out);
-    if (sl.ev) hipEventDestroy(sl.ev);
-    if (sl.st) hipStreamDestroy(sl.st);
-  }
+  miann_server_destroy_slots(s);
   delete s;
 }
 
