@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmiann.so")
-SOURCES = ["search.hip", "build.hip", "knn.hip", "mlp.hip", "capi.cpp", "predictor.cpp", "serve.cpp", "pool.cpp"]
+SOURCES = ["search_f32.hip", "search_f16.hip", "search_fp8.hip", "search_u8.hip", "search.hip", "build.hip", "knn.hip", "mlp.hip", "capi.cpp", "predictor.cpp", "serve.cpp", "pool.cpp"]
 ARCH = os.environ.get("MIANN_ARCH", "gfx950")
 
 FLAGS = [
@@ -32,7 +32,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -73,9 +73,11 @@ __device__ __forceinline__ int shfl_xor_i32(int v, int m) { return __shfl_xor(v,
 // Lane i receives v from lane i ^ J (J = 1, 2, 4, ..., 32) without the LDS
 // crossbar: DPP permutes inside 16-lane rows (quad permutes, the 8-lane
 // mirror, rotation by 8) and gfx950's row-swap permutes across rows. Every
-// mapping used is an involution, so none depends on a shift direction; the
-// row swaps return the lane's own value in one output and its partner's in
-// the other, and the partner's is the one that differs (or both are equal).
+// mapping used is an involution, so none depends on a shift direction.
+// v_permlane16_swap(v, v) exchanges the odd rows of its first result with the
+// even rows of its second, v_permlane32_swap(v, v) the upper half of the first
+// with the lower half of the second; so the second result holds the partner's
+// value in even rows (lower half) and the first result in odd rows (upper half).
 template <int J>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
   static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "J");
@@ -90,10 +92,42 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
   } else if constexpr (J == 16) {
     const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return r[0] == v ? r[1] : r[0];
+    return __builtin_amdgcn_inverse_ballot_w64(0x0000FFFF0000FFFFull) ? r[1] : r[0];
   } else {
     const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return r[0] == v ? r[1] : r[0];
+    return __builtin_amdgcn_inverse_ballot_w64(0x00000000FFFFFFFFull) ? r[1] : r[0];
+  }
+}
+// Both values of each lane pair (i, i ^ J) for J = 16 or 32, in an order that
+// differs between the two lanes: {a, b} = {own value, partner's value}. A
+// compare-exchange needs only the pair, so this skips the final select.
+template <int J>
+__device__ __forceinline__ void swap_pair_u64(uint64_t v, uint64_t& a, uint64_t& b) {
+  static_assert(J == 16 || J == 32, "J");
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  if constexpr (J == 16) {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a = ((uint64_t)rh[0] << 32) | rl[0];
+    b = ((uint64_t)rh[1] << 32) | rl[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = ((uint64_t)rh[0] << 32) | rl[0];
+    b = ((uint64_t)rh[1] << 32) | rl[1];
+  }
+}
+template <int J>
+__device__ __forceinline__ void swap_pair_u32(uint32_t v, uint32_t& a, uint32_t& b) {
+  static_assert(J == 16 || J == 32, "J");
+  if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
   }
 }
 // Lane i receives v from lane 63 - i: the row mirror (i -> 15 - i inside each
@@ -170,15 +204,39 @@ __device__ __forceinline__ T exchange(T key, T other) {
   return take ? other : key;
 }
 
+// Compare-exchange of key with lane ^ J's key under the keep-min mask WM.
+// Across rows (J >= 16) the pair comes from one row swap, and the result is
+// the pair's minimum or maximum whatever the order of the pair.
+template <uint64_t WM, int J>
+__device__ __forceinline__ uint64_t xchg_u64(uint64_t key) {
+  if constexpr (J >= 16) {
+    uint64_t a, b;
+    swap_pair_u64<J>(key, a, b);
+    return exchange<WM>(a, b);
+  } else {
+    return exchange<WM>(key, xor_lane_u64(key, J));
+  }
+}
+template <uint64_t WM, int J>
+__device__ __forceinline__ uint32_t xchg_u32(uint32_t key) {
+  if constexpr (J >= 16) {
+    uint32_t a, b;
+    swap_pair_u32<J>(key, a, b);
+    return exchange<WM>(a, b);
+  } else {
+    return exchange<WM>(key, xor_lane_u32(key, J));
+  }
+}
+
 template <int SEG, int K, int J>
 __device__ __forceinline__ void bsort_stage_u64(uint64_t& key) {
-  key = exchange<keep_min_mask(K, J, SEG, 0)>(key, xor_lane_u64(key, J));
+  key = xchg_u64<keep_min_mask(K, J, SEG, 0), J>(key);
   if constexpr (J > 1) bsort_stage_u64<SEG, K, J / 2>(key);
   else if constexpr (K < SEG) bsort_stage_u64<SEG, K * 2, K>(key);
 }
 template <int SEG, int K, int J>
 __device__ __forceinline__ void bsort_stage_u32(uint32_t& key) {
-  key = exchange<keep_min_mask(K, J, SEG, 0)>(key, xor_lane_u32(key, J));
+  key = xchg_u32<keep_min_mask(K, J, SEG, 0), J>(key);
   if constexpr (J > 1) bsort_stage_u32<SEG, K, J / 2>(key);
   else if constexpr (K < SEG) bsort_stage_u32<SEG, K * 2, K>(key);
 }
@@ -212,7 +270,7 @@ __device__ __forceinline__ void bregs_stage(uint64_t (&v)[NR]) {
         v[R | jr] = sw ? a : b;
       }
     } else {
-      v[R] = exchange<keep_min_mask(K, J, 64 * NR, R)>(v[R], xor_lane_u64(v[R], J));
+      v[R] = xchg_u64<keep_min_mask(K, J, 64 * NR, R), J>(v[R]);
     }
     bregs_stage<NR, K, J, R + 1>(v);
   }
@@ -233,7 +291,7 @@ __device__ __forceinline__ void bitonic_sort_regs(uint64_t (&v)[NR]) {
 
 template <int J>
 __device__ __forceinline__ void bmerge_stage(uint64_t& key) {
-  key = exchange<keep_min_mask(64, J, 64, 0)>(key, xor_lane_u64(key, J));
+  key = xchg_u64<keep_min_mask(64, J, 64, 0), J>(key);
   if constexpr (J > 1) bmerge_stage<J / 2>(key);
 }
 // Sorts a bitonic sequence of 64 keys (one per lane) ascending.

@@ -1,628 +1,18 @@
-// Batched beam search over fixed-degree proximity graphs on gfx950.
-//
-// One wave64 searches one query (Sec. 4 runs one query per 32-thread block;
-// here the whole CDNA wavefront is the unit). Per wave, LDS holds
-//   p     : the priority queue of l (dist, id, flag) keys, sorted (Sec. 2.2)
-//   c     : up to 64 candidate keys/ids of the current iteration
-//   hash  : an open-addressed visited set that may forget (reset from p when
-//           half full); merges reject keys already in p, so the result does
-//           not depend on what the hash forgets
-//   q     : the query, plus the query sign bits of the current parents
-// Neighbour vectors are gathered by 8-lane teams, each lane reading 16-byte
-// chunks of the row (rows are padded to 128-byte multiples). Each difference
-// q_i - x_i is a float; its square is exact in double and the squares are
-// summed in double, so a distance is the sum of the squared float differences
-// rounded once to float, whatever the order of summation.
-//
-// Stages follow path extension (Sec. 3.1.2): stage t of query q runs on shard
-// (q_key + t) mod S, seeded by the inter-shard map of the previous stage's top
-// results; stage 0 may start with the ghost graph (Sec. 3.2.2). During the
-// first T - ceil(c T) iterations the direction filter of Sec. 3.3.2 keeps only
-// the neighbours whose stored sign bits agree most with the query's.
+// Stage dispatch over vector types and the reduction over shards; the stage
+// kernel itself lives in search_impl.hpp, instantiated once per type by
+// search_f32.hip, search_f16.hip, search_fp8.hip and search_u8.hip so that
+// the four compile in parallel.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace miann {
 
-struct GraphCtx {
-  const void* store;
-  const float* scale;
-  const uint32_t* graph;
-  const uint32_t* sign;
-  uint32_t n;
-  int deg, degp;
-};
-
-__device__ __forceinline__ int hibit(int x) { return x <= 0 ? 0 : (1 << (31 - __clz(x))); }
-
-// Number of keys in a[0..n) (sorted) whose flag-less value is below x.
-__device__ __forceinline__ int count_below(const uint64_t* a, int n, uint64_t x) {
-  int pos = 0;
-  for (int step = hibit(n); step > 0; step >>= 1)
-    if (pos + step <= n && key_noflag(a[pos + step - 1]) < x) pos += step;
-  return pos;
-}
-
-template <int DT, int CPL>
-struct Searcher {
-  static constexpr int P16 = Fmt<DT>::per16;
-  static constexpr int ESZ = Fmt<DT>::esize;
-  static constexpr bool kScaled = (DT == DT_F16 || DT == DT_FP8);
-  // candidate rows gathered per batch: G rounds of 8 rows, at most 8 16-byte chunks in flight per lane
-  static constexpr int G = (8 / CPL) < 1 ? 1 : ((8 / CPL) > 4 ? 4 : (8 / CPL));
-
-  const StageArgs a;
-  uint64_t* pk;      // the priority queue p
-  uint64_t* pk_alt;  // second buffer for merges
-  uint64_t* ck;
-  uint32_t* cid;
-  uint32_t* hash;
-  float* qf;
-  uint8_t* qb;
-  uint32_t* qsign;
-  int* ppos;  // positions in p of the current parents
-  int hlog, hmask, hfill;
-  int lane, team, tl;
-  uint64_t qkey;
-  uint32_t qq8;  // sum of q^2 over this lane's u8 elements
-  long long ctr[kNumCtr];
-
-  __device__ Searcher(const StageArgs& args) : a(args) {}
-
-  // ---------------------------------------------------------------- hash
-  __device__ __forceinline__ void hash_clear() {
-    for (int i = lane; i <= hmask; i += 64) hash[i] = kNone;
-    hfill = 0;
-    wsync();
-  }
-  // true if id was already present; inserts it otherwise (if a slot is free nearby)
-  __device__ __forceinline__ bool hash_seen_insert(uint32_t id, bool& inserted) {
-    uint32_t h = (id * 0x9E3779B1u) >> (32 - hlog);
-    inserted = false;
-#pragma unroll 1
-    for (int t = 0; t < 16; t++) {
-      uint32_t s = (h + t) & hmask;
-      uint32_t old = atomicCAS(&hash[s], kNone, id);
-      if (old == kNone) { inserted = true; return false; }
-      if (old == id) return true;
-    }
-    return false;
-  }
-  // returns whether `id` passes the visited filter (not seen before)
-  __device__ __forceinline__ bool visit(bool active, uint32_t id) {
-    bool ins = false, seen = true;
-    if (active) seen = hash_seen_insert(id, ins);
-    hfill += __popcll(ballot(ins));
-    return active && !seen;
-  }
-  __device__ __forceinline__ void hash_rebuild(int l) {
-    hash_clear();
-    for (int i = 0; i < l; i += 64) {
-      uint64_t key = (i + lane < l) ? pk[i + lane] : kDummy;
-      visit(key != kDummy, key_id(key));
-    }
-    wsync();
-  }
-
-  // ---------------------------------------------------------------- p
-  __device__ __forceinline__ void p_reset(int l) {
-    for (int i = lane; i < l; i += 64) pk[i] = kDummy;
-    wsync();
-  }
-
-  // Merge this lane's candidate key (lanes sorted ascending, kDummy = none)
-  // into p[0..l). Keys whose (dist, id) is already in p, or repeats within c,
-  // are dropped (the existing entry keeps its flag). Returns bit 0 if any
-  // candidate entered p, bit 1 if one entered the first k positions.
-  __device__ __forceinline__ int merge_sorted(uint64_t c, int l) {
-    const uint64_t prev = shfl_u64(c, lane == 0 ? 0 : lane - 1);
-    const bool real = c != kDummy;
-    const uint64_t cn = key_noflag(c);
-    bool dup = real && lane > 0 && key_noflag(prev) == cn;
-    int pos = real ? count_below(pk, l, cn) : l;
-    if (real && !dup && pos < l && key_noflag(pk[pos]) == cn) dup = true;
-    const bool valid = real && !dup;
-    const uint64_t vm = ballot(valid);
-    if (vm == 0) return 0;
-    const int nv = __popcll(vm);
-    const int rank = lanes_below(vm);
-    const int newpos = pos + rank;
-    if (valid) ck[rank] = c;
-    wsync();
-    // p entries move right by the number of new keys below them; write into the other buffer
-    for (int i = lane; i < l; i += 64) {
-      const uint64_t pv = pk[i];
-      const int np = i + count_below(ck, nv, key_noflag(pv));
-      if (np < l) pk_alt[np] = pv;
-    }
-    const bool in = valid && newpos < l;
-    if (in) pk_alt[newpos] = c;
-    wsync();
-    uint64_t* t = pk;
-    pk = pk_alt;
-    pk_alt = t;
-    return (ballot(in) != 0 ? 1 : 0) | (ballot(in && newpos < a.k) != 0 ? 2 : 0);
-  }
-
-  // The same merge for l <= 64 without LDS searches: p (one entry per lane)
-  // and the reversed candidates form a bitonic sequence; the elementwise
-  // minimum and maximum are its lower and upper 64 keys, each sorted by a
-  // half-cleaner network. In the sorted 128 keys a key whose (dist, id)
-  // equals the next one's is dropped (the later copy has the larger flag:
-  // p's entry), and the first l survivors become the new p.
-  __device__ __forceinline__ int merge_sorted_small(uint64_t c, int l) {
-    const uint64_t pv = lane < l ? pk[lane] : kDummy;
-    const uint64_t cr = reverse_lanes_u64(c);
-    uint64_t lo = pv < cr ? pv : cr;
-    uint64_t hi = pv < cr ? cr : pv;
-    lo = bitonic_merge_u64(lo);
-    hi = bitonic_merge_u64(hi);
-    // the next key of the sorted 128: lo[i+1], hi[0] after lo[63], hi[i+1]
-    const int nx = (lane + 1) & 63;
-    const uint64_t lo_n = shfl_u64(lo, nx), hi_n = shfl_u64(hi, nx);
-    const uint64_t lo_next = lane == 63 ? hi_n : lo_n;  // hi_n at lane 63 is hi[0]
-    const uint64_t hi_next = lane == 63 ? kDummy : hi_n;
-    const bool keep_lo = lo == kDummy || key_noflag(lo) != key_noflag(lo_next);
-    const bool keep_hi = hi == kDummy || key_noflag(hi) != key_noflag(hi_next);
-    const uint64_t mlo = ballot(keep_lo), mhi = ballot(keep_hi);
-    const int pos_lo = lanes_below(mlo);
-    const int pos_hi = __popcll(mlo) + lanes_below(mhi);
-    if (keep_lo && pos_lo < l) pk_alt[pos_lo] = lo;
-    if (keep_hi && pos_hi < l) pk_alt[pos_hi] = hi;
-    wsync();
-    const uint64_t nv = lane < l ? pk_alt[lane] : kDummy;
-    const bool diff = nv != pv;
-    const int changed = (ballot(diff) != 0 ? 1 : 0) | (ballot(diff && lane < a.k) != 0 ? 2 : 0);
-    uint64_t* t = pk;
-    pk = pk_alt;
-    pk_alt = t;
-    return changed;
-  }
-
-  __device__ __forceinline__ int merge(uint64_t c, int l) {
-    return l <= 64 ? merge_sorted_small(c, l) : merge_sorted(c, l);
-  }
-
-  // ---------------------------------------------------------------- distances
-  __device__ __forceinline__ void load_query(const void* qptr) {
-    const int d = a.d;
-    if constexpr (DT == DT_U8) {
-      const uint8_t* q = (const uint8_t*)qptr;
-      for (int i = lane; i < a.d_pad; i += 64) qb[i] = i < d ? q[i] : 0;
-    } else {
-      const float* q = (const float*)qptr;
-      for (int i = lane; i < a.d_pad; i += 64) qf[i] = i < d ? q[i] : 0.f;
-    }
-    wsync();
-    if constexpr (DT == DT_U8) {
-      qq8 = 0;
-#pragma unroll
-      for (int m = 0; m < CPL; m++) {
-        const uint4 qv = ((const uint4*)qb)[tl + 8 * m];
-        qq8 = __builtin_amdgcn_udot4(qv.x, qv.x, qq8, false);
-        qq8 = __builtin_amdgcn_udot4(qv.y, qv.y, qq8, false);
-        qq8 = __builtin_amdgcn_udot4(qv.z, qv.z, qq8, false);
-        qq8 = __builtin_amdgcn_udot4(qv.w, qv.w, qq8, false);
-      }
-    }
-  }
-
-  // Keys (dist, id, fresh) of the candidate ids cid[0..nc) into ck[0..nc).
-  __device__ __forceinline__ void compute_dists(const GraphCtx& g, int nc) {
-    const size_t row_bytes = (size_t)a.d_pad * ESZ;
-    for (int r0 = 0; r0 < nc; r0 += 8 * G) {
-      uint4 buf[G][CPL];
-      float sc[G];
-      uint32_t ids[G];
-      bool ok[G];
-#pragma unroll
-      for (int gi = 0; gi < G; gi++) {
-        // every lane loads (row 0 for the unused teams), so the gathers need no branches
-        const int ci = r0 + gi * 8 + team;
-        ok[gi] = ci < nc;
-        ids[gi] = cid[ci < nc ? ci : 0];
-        const uint32_t lid = ok[gi] ? ids[gi] : 0u;
-        const gptr<u32x4_t> row = as_global((const u32x4_t*)((const char*)g.store + (size_t)lid * row_bytes));
-#pragma unroll
-        for (int m = 0; m < CPL; m++) buf[gi][m] = load16(row, tl + 8 * m);
-        if constexpr (kScaled) sc[gi] = as_global(g.scale)[lid];
-      }
-#pragma unroll
-      for (int gi = 0; gi < G; gi++) {
-        asm volatile("" ::: "memory");  // re-read the query slice from LDS rather than pinning it in registers
-        uint32_t dbits;
-        if constexpr (DT == DT_U8) {
-          uint32_t xx = 0, qx = 0;
-#pragma unroll
-          for (int m = 0; m < CPL; m++) {
-            xx = __builtin_amdgcn_udot4(buf[gi][m].x, buf[gi][m].x, xx, false);
-            xx = __builtin_amdgcn_udot4(buf[gi][m].y, buf[gi][m].y, xx, false);
-            xx = __builtin_amdgcn_udot4(buf[gi][m].z, buf[gi][m].z, xx, false);
-            xx = __builtin_amdgcn_udot4(buf[gi][m].w, buf[gi][m].w, xx, false);
-            const uint4 qv = ((const uint4*)qb)[tl + 8 * m];
-            qx = __builtin_amdgcn_udot4(buf[gi][m].x, qv.x, qx, false);
-            qx = __builtin_amdgcn_udot4(buf[gi][m].y, qv.y, qx, false);
-            qx = __builtin_amdgcn_udot4(buf[gi][m].z, qv.z, qx, false);
-            qx = __builtin_amdgcn_udot4(buf[gi][m].w, qv.w, qx, false);
-          }
-          int part = (int)(qq8 + xx - 2u * qx);
-          part += xor_lane_i32(part, 1);
-          part += xor_lane_i32(part, 2);
-          part += xor_lane_i32(part, 4);
-          dbits = (uint32_t)part;
-        } else {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < CPL; m++) {
-            float x[P16];
-            decode16<DT>(buf[gi][m], x);
-            const float* qc = qf + (tl + 8 * m) * P16;
-#pragma unroll
-            for (int e = 0; e < P16; e++) {
-              const float xe = kScaled ? sc[gi] * x[e] : x[e];
-              const float t = qc[e] - xe;  // float difference; its square is exact in double
-              acc = __builtin_fma((double)t, (double)t, acc);
-            }
-          }
-          acc += xor_lane_f64(acc, 1);
-          acc += xor_lane_f64(acc, 2);
-          acc += xor_lane_f64(acc, 4);
-          dbits = __float_as_uint((float)acc);
-        }
-        const int ci = r0 + gi * 8 + team;
-        if (tl == 0 && ok[gi]) ck[ci] = make_key(dbits, ids[gi], kFresh);
-      }
-    }
-    wsync();
-  }
-
-  // Filter ids (one per lane, active lanes only) through the visited set,
-  // evaluate the new ones, and merge them into p.
-  __device__ __forceinline__ int add_ids(const GraphCtx& g, bool active, uint32_t id, int l) {
-    const bool take = visit(active, id);
-    const uint64_t tm = ballot(take);
-    const int nc = __popcll(tm);
-    if (nc == 0) return 0;
-    if (take) cid[lanes_below(tm)] = id;
-    wsync();
-    compute_dists(g, nc);
-    ctr[0] += nc;
-    uint64_t key = lane < nc ? ck[lane] : kDummy;
-    wsync();
-    key = nc > 32 ? bitonic_sort_u64<64>(key) : (nc > 16 ? bitonic_sort_u64<32>(key) : bitonic_sort_u64<16>(key));
-    return merge(key, l);
-  }
-
-  // Seeds whose distance is already known (one key per lane, kDummy = none).
-  __device__ __forceinline__ void add_keys(uint64_t key, int l) {
-    const bool take = visit(key != kDummy, key_id(key));
-    key = take ? key : kDummy;
-    key = bitonic_sort_u64<64>(key);
-    merge(key, l);
-  }
-
-  __device__ __forceinline__ void random_init(const GraphCtx& g, uint64_t stream, int n_init, int l) {
-    for (int b = 0; b < n_init; b += 64) {
-      if (hfill > ((hmask + 1) >> 1)) hash_rebuild(l);
-      const int j = b + lane;
-      uint32_t id = 0;
-      if (j < n_init) id = (uint32_t)(sm_at(stream, qkey * (uint64_t)n_init + (uint64_t)j + 1) % (uint64_t)g.n);
-      add_ids(g, j < n_init, id, l);
-    }
-  }
-
-  // ---------------------------------------------------------------- the loop
-  // Steps 3-4 of Sec. 2.2 until no parent is eligible or T iterations ran.
-  __device__ __forceinline__ void beam_loop(const GraphCtx& g, int l, int T, bool dgs_on, bool stop_nc, uint64_t stream,
-                            long long& n_exp, long long& n_iter, long long& last_topk) {
-    const int r = a.r;
-    const int n_cool = (a.cooldown_pm * T + 999) / 1000;
-    const int t_dgs = T - n_cool;
-    const int W = a.W;
-    bool forced = false;
-    int it = 0;
-    while (it < T) {
-      const bool dgs_phase = dgs_on && !forced && it < t_dgs;
-      // parents: the first r eligible entries of p, in p order
-      int npar = 0;
-      for (int b = 0; b < l && npar < r; b += 64) {
-        const int i = b + lane;
-        const uint64_t key = i < l ? pk[i] : kDummy;
-        const uint32_t fl = key_flag(key);
-        const bool el = key != kDummy && (dgs_phase ? fl == kFresh : fl != kDone);
-        const uint64_t m = ballot(el);
-        const int below = lanes_below(m);
-        if (el && npar + below < r) ppos[npar + below] = i;
-        npar += __popcll(m);
-      }
-      npar = npar < r ? npar : r;
-      wsync();
-      if (npar == 0) {
-        if (dgs_phase) { forced = true; continue; }
-        break;
-      }
-      if (hfill > ((hmask + 1) >> 1)) hash_rebuild(l);
-      const int keep = dgs_phase ? a.n_keep : g.deg;
-      const uint32_t newflag = (dgs_phase && keep < g.deg) ? kPartial : kDone;
-      uint32_t pid[kMaxR];
-#pragma unroll
-      for (int t = 0; t < kMaxR; t++) pid[t] = t < npar ? key_id(pk[ppos[t]]) : 0u;
-      wsync();
-      if (lane < npar) pk[ppos[lane]] = (pk[ppos[lane]] & ~3ull) | newflag;
-      // lane -> (parent, slot)
-      const int pa = lane / g.degp, slot = lane % g.degp;
-      const bool act = pa < npar && slot < g.deg;
-      uint32_t u = 0;
-#pragma unroll
-      for (int t = 0; t < kMaxR; t++)
-        if (t == pa) u = pid[t];
-      uint32_t nb = as_global(g.graph)[(size_t)u * g.deg + (act ? slot : 0)];
-      nb = act ? nb : kNone;
-      if (dgs_phase) {
-        // this lane's direction-table words, loaded in the same round trip as the adjacency row
-        constexpr int kSW = 8;
-        // inactive lanes read slot 0 of a valid row (slots beyond deg would run past the table)
-        const uint32_t* srow = g.sign + (size_t)u * W * g.deg + (act ? slot : 0);
-        uint32_t sw[kSW];
-#pragma unroll
-        for (int w = 0; w < kSW; w++)
-          sw[w] = (!a.random_discard && w < W) ? as_global(srow)[(size_t)w * g.deg] : 0u;
-        // query sign bits against each parent: bit i = [q_i > x_parent,i]
-#pragma unroll
-        for (int t = 0; t < kMaxR; t++) {
-          if (t >= npar) break;
-          const void* row = (const char*)g.store + (size_t)pid[t] * a.d_pad * ESZ;
-          const float su = kScaled ? g.scale[pid[t]] : 1.f;
-          for (int w2 = 0; w2 < W; w2 += 2) {
-            const int i = w2 * 32 + lane;
-            bool gt = false;
-            if (i < a.d) {
-              if constexpr (DT == DT_U8) gt = qb[i] > ((const uint8_t*)row)[i];
-              else {
-                const float x = load_elem<DT>((const void*)as_global((const char*)row), i);
-                gt = qf[i] > (kScaled ? su * x : x);
-              }
-            }
-            const uint64_t bits = ballot(gt);
-            if (lane == 0) {
-              qsign[t * W + w2] = (uint32_t)bits;
-              if (w2 + 1 < W) qsign[t * W + w2 + 1] = (uint32_t)(bits >> 32);
-            }
-          }
-        }
-        wsync();
-        uint32_t rk = 0xFFFFFFFFu;
-        if (act) {
-          if (a.random_discard) {
-            const uint64_t h1 = sm_at(stream, qkey + 1);
-            rk = ((uint32_t)(sm_mix(h1 ^ (((uint64_t)u << 8) | (uint64_t)slot)) >> 40) << 8) | (uint32_t)slot;
-          } else {
-            int mm = 0;
-#pragma unroll
-            for (int w = 0; w < kSW; w++)
-              if (w < W) mm += __popc(qsign[pa * W + w] ^ sw[w]);
-            for (int w = kSW; w < W; w++) mm += __popc(qsign[pa * W + w] ^ srow[(size_t)w * g.deg]);
-            rk = ((uint32_t)mm << 8) | (uint32_t)slot;
-          }
-        }
-        rk = bitonic_sort_u32_seg(rk, g.degp);
-        const bool kept = act && slot < keep && rk != 0xFFFFFFFFu;
-        const int src = pa * g.degp + (int)(rk & 0xFFu);
-        const uint32_t nb_sel = shfl_u32(nb, kept ? src : lane);
-        nb = kept ? nb_sel : kNone;
-        ctr[3] += (long long)(g.deg - keep) * npar;
-      }
-      const int changed = add_ids(g, nb != kNone, nb, l);
-      n_exp += npar;
-      it++;
-      if (changed & 2) last_topk = it;
-      if (stop_nc && !(changed & 1)) break;
-    }
-    n_iter += it;
-  }
-
-  // FP32 rerank of p[0..m) (low-precision stores): exact distances against the
-  // FP32 originals, then sort.
-  __device__ __forceinline__ void rerank(const float* orig, int m) {
-    const int dpf = a.d_pad_f32;
-    for (int r0 = 0; r0 < m; r0 += 8) {
-      const int ci = r0 + team;
-      const bool ok = ci < m && pk[ci] != kDummy;
-      const uint32_t id = ok ? key_id(pk[ci]) : 0u;
-      const float4* row = (const float4*)(orig + (size_t)id * dpf);
-      double acc = 0.0;
-      if (ok)
-        for (int c = tl; c < dpf / 4; c += 8) {
-          const float4 x = row[c];
-          const float xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-          for (int e = 0; e < 4; e++) {
-            const float t = qf[4 * c + e] - xs[e];
-            acc = __builtin_fma((double)t, (double)t, acc);
-          }
-        }
-      acc += xor_lane_f64(acc, 1);
-      acc += xor_lane_f64(acc, 2);
-      acc += xor_lane_f64(acc, 4);
-      wsync();
-      if (tl == 0 && ci < m && ok) pk[ci] = make_key(__float_as_uint((float)acc), id, kDone);
-    }
-    wsync();
-    sort_p(m);
-  }
-
-  // Sorts pk[0..m) ascending (entries m..pow2(m) are padded with dummies).
-  __device__ __forceinline__ void sort_p(int m) {
-    int n = 1;
-    while (n < m) n <<= 1;
-    for (int i = m + lane; i < n; i += 64) pk[i] = kDummy;
-    wsync();
-    for (int kk = 2; kk <= n; kk <<= 1)
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = lane; i < n; i += 64) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const uint64_t x = pk[i], y = pk[ixj];
-            const bool up = (i & kk) == 0;
-            if ((x > y) == up) { pk[i] = y; pk[ixj] = x; }
-          }
-        }
-        wsync();
-      }
-  }
-};
-
-// Occupancy target of the stage kernel (waves per SIMD); 0 leaves the choice to the compiler.
-#ifndef MIANN_STAGE_WAVES_PER_EU
-#define MIANN_STAGE_WAVES_PER_EU 0
-#endif
-#if MIANN_STAGE_WAVES_PER_EU > 0
-#define MIANN_STAGE_ATTR __attribute__((amdgpu_waves_per_eu(MIANN_STAGE_WAVES_PER_EU)))
-#else
-#define MIANN_STAGE_ATTR
-#endif
-
-template <int DT, int CPL>
-__global__ __launch_bounds__(256) MIANN_STAGE_ATTR void stage_kernel(StageArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const int wave = threadIdx.x >> 6;
-  const int64_t q = (int64_t)blockIdx.x * a.waves_per_block + wave;
-  if (q >= a.nq) return;
-
-  Searcher<DT, CPL> S(a);
-  S.lane = lane_id();
-  S.team = S.lane >> 3;
-  S.tl = S.lane & 7;
-  char* base = smem + (size_t)wave * a.per_wave_lds;
-  S.pk = (uint64_t*)base;
-  base += (size_t)a.lp_pow2 * 8;
-  S.pk_alt = (uint64_t*)base;
-  base += (size_t)a.lp_pow2 * 8;
-  S.ck = (uint64_t*)base;
-  base += 64 * 8;
-  S.cid = (uint32_t*)base;
-  base += 64 * 4;
-  S.hlog = a.hash_log2;
-  S.hmask = (1 << a.hash_log2) - 1;
-  S.hash = (uint32_t*)base;
-  base += (size_t)4 << a.hash_log2;
-  S.qf = (float*)base;
-  S.qb = (uint8_t*)base;
-  base += (size_t)a.d_pad * 4;
-  S.qsign = (uint32_t*)base;
-  base += (size_t)kMaxR * a.W * 4;
-  S.ppos = (int*)base;
-#pragma unroll
-  for (int i = 0; i < kNumCtr; i++) S.ctr[i] = 0;
-
-  S.qkey = a.qkeys ? a.qkeys[q] : (uint64_t)q;
-  const int Sh = a.S;
-  const int s0 = (int)(S.qkey % (uint64_t)Sh);
-  const int t = a.stage;
-  const int s = (s0 + t) % Sh;
-  const ShardDev sh = a.sh[s];
-  const uint64_t stream_main = sm_at(a.seed, (uint64_t)(2 * s + 1));
-  const uint64_t stream_ghost = sm_at(a.seed, (uint64_t)(2 * s + 2));
-  const int T = a.Tq ? a.Tq[q] : a.T;
-  const size_t qbytes = (size_t)a.d * (DT == DT_U8 ? 1 : 4);
-  S.load_query((const char*)a.queries + (size_t)q * qbytes);
-
-  GraphCtx gm{sh.store, sh.scale, sh.graph, sh.sign, sh.n, a.deg, a.degp};
-  S.hash_clear();
-  S.p_reset(a.l);
-  const bool use_entry = (t == 0) || !a.ppe;
-  long long n_exp = 0, n_iter = 0;
-  // predicted entry: the row's seeds, or the ghost graph when the predictor was not confident
-  int entry = a.entry;
-  if (entry == 4) entry = (t == 0 && a.seeds[(size_t)q * a.n_seeds] != kNone) ? 3 : 1;
-  const bool ghost = entry == 1 || entry == 2;
-  if (ghost && (use_entry || a.ghost_every)) {
-    uint64_t seed = kDummy;
-    if (entry == 1) {
-      // ghost staging: a short search on the ghost graph (p and the hash serve as scratch)
-      GraphCtx gg{sh.g_store, sh.g_scale, sh.g_graph, nullptr, sh.R, a.deg_g, a.degp_g};
-      S.p_reset(a.l_g);
-      long long ge = 0, gi = 0, gl = 0;
-      const long long nd0 = S.ctr[0];
-      S.random_init(gg, stream_ghost, a.deg_g, a.l_g);
-      S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi, gl);
-      S.ctr[4] += S.ctr[0] - nd0;
-      S.ctr[0] = nd0;
-      S.ctr[5] += ge;
-      const uint64_t gk = S.lane < a.t_seeds ? S.pk[S.lane] : kDummy;
-      if (gk != kDummy) seed = make_key(key_dist(gk), sh.g_map[key_id(gk)], kFresh);
-      wsync();
-      S.hash_clear();
-      S.p_reset(a.l);
-    } else {
-      const uint64_t dk = S.lane < a.t_seeds ? a.dense[((size_t)q * Sh + s) * a.t_seeds + S.lane] : kDummy;
-      if (dk != kDummy) seed = make_key((uint32_t)(dk >> 32), (uint32_t)dk, kFresh);
-      S.ctr[4] += sh.R;
-    }
-    // the ghost seeds' distances are those of the nodes they copy
-    S.add_keys(seed, a.l);
-  }
-  if (!use_entry) {
-    // path extension: continue from I(z) of the previous stage's first f results
-    const uint32_t id = S.lane < a.f ? a.hand_in[(size_t)q * a.f + S.lane] : kNone;
-    S.add_ids(gm, id != kNone, id, a.l);
-  } else if (!ghost) {
-    if (entry == 3 && t == 0 && a.seeds) {
-      for (int b = 0; b < a.n_seeds; b += 64) {
-        const int j = b + S.lane;
-        const uint32_t id = j < a.n_seeds ? a.seeds[(size_t)q * a.n_seeds + j] : kNone;
-        S.add_ids(gm, id != kNone && id < sh.n, id, a.l);
-      }
-    } else {
-      S.random_init(gm, stream_main, a.n_init, a.l);
-    }
-  }
-  long long last_topk = 0;
-  S.beam_loop(gm, a.l, T, a.dgs != 0, a.stop_on_no_change != 0, stream_main, n_exp, n_iter, last_topk);
-  S.ctr[1] += n_exp;
-  S.ctr[2] += n_iter;
-  S.ctr[7] += last_topk;
-
-  // hand-off to the next shard: I(z) for the first f entries
-  if (Sh > 1 && a.ppe && t + 1 < Sh && S.lane < a.f) {
-    const uint64_t key = S.pk[S.lane];
-    a.hand_out[(size_t)q * a.f + S.lane] = key != kDummy ? sh.next[key_id(key)] : kNone;
-  }
-  wsync();
-  if (a.lowp) {
-    int m = a.rerank_m * a.k;
-    if (m > a.l) m = a.l;
-    int real = 0;
-    for (int i = 0; i < m; i += 64) real += __popcll(ballot(i + S.lane < m && S.pk[i + S.lane] != kDummy));
-    S.ctr[6] += real;
-    S.rerank(sh.orig, m);
-  }
-  // the stage's k results, ordered by (dist, global id) for the reduction over shards
-  for (int i = S.lane; i < a.k; i += 64) {
-    const uint64_t key = S.pk[i];
-    const uint32_t lid = key_id(key);
-    S.pk[i] = key != kDummy ? (((uint64_t)key_dist(key) << 32) | (sh.gmap ? sh.gmap[lid] : lid)) : kDummy;
-  }
-  wsync();
-  S.sort_p(a.k);
-  for (int i = S.lane; i < a.k; i += 64) {
-    const uint64_t key = S.pk[i];
-    const bool ok = key != kDummy;
-    if (Sh == 1) {
-      a.out_ids[(size_t)q * a.k + i] = ok ? (uint32_t)key : kNone;
-      if (DT == DT_U8)
-        ((int32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? (int32_t)(key >> 32) : 0x7FFFFFFF;
-      else
-        ((uint32_t*)a.out_d)[(size_t)q * a.k + i] = ok ? (uint32_t)(key >> 32) : 0x7F800000u;
-    } else {
-      a.stage_out[((size_t)q * Sh + t) * a.k + i] = key;
-    }
-  }
-  if (a.ctr && S.lane == 0) {
-    long long* c = (long long*)a.ctr + (size_t)q * kNumCtr;
-    for (int i = 0; i < kNumCtr; i++) c[i] = (t == 0 ? 0 : c[i]) + S.ctr[i];
-  }
-}
+template <int DT>
+hipError_t launch_dt(int cpl, const StageArgs& a, hipStream_t st);
+extern template hipError_t launch_dt<DT_F32>(int, const StageArgs&, hipStream_t);
+extern template hipError_t launch_dt<DT_F16>(int, const StageArgs&, hipStream_t);
+extern template hipError_t launch_dt<DT_FP8>(int, const StageArgs&, hipStream_t);
+extern template hipError_t launch_dt<DT_U8>(int, const StageArgs&, hipStream_t);
 
 // Reduction over shards (Sec. 3.1.2): first k of the union of the S sorted
 // per-stage lists, by (dist, global id). One wave per query.
@@ -655,37 +45,8 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
 }
 
 int stage_lds_bytes(const StageArgs& a) {
-  int b = 2 * a.lp_pow2 * 8 + 64 * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + kMaxR * 4;
+  int b = 2 * a.lp_pow2 * 8 + 64 * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + 2 * kMaxR * 4;
   return (b + 15) & ~15;
-}
-
-template <int DT, int CPL>
-static hipError_t launch_t(const StageArgs& a, hipStream_t st) {
-  const int wpb = a.waves_per_block;
-  const int64_t blocks = (a.nq + wpb - 1) / wpb;
-  const size_t lds = (size_t)a.per_wave_lds * wpb;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)stage_kernel<DT, CPL>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((stage_kernel<DT, CPL>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int DT>
-static hipError_t launch_dt(int cpl, const StageArgs& a, hipStream_t st) {
-  switch (cpl) {
-    case 1: return launch_t<DT, 1>(a, st);
-    case 2: return launch_t<DT, 2>(a, st);
-    case 3: return launch_t<DT, 3>(a, st);
-    case 4: return launch_t<DT, 4>(a, st);
-    case 5: return launch_t<DT, 5>(a, st);
-    case 6: return launch_t<DT, 6>(a, st);
-    case 7: return launch_t<DT, 7>(a, st);
-    case 8: return launch_t<DT, 8>(a, st);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_stage(int dtype, int cpl, const StageArgs& a, hipStream_t st) {
