@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
 }
 
 int stage_lds_bytes(const StageArgs& a) {
-  int b = 2 * a.lp_pow2 * 8 + 64 * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + 2 * kMaxR * 4;
+  int b = 2 * a.lp_pow2 * 8 + 64 * 8 + kNumCtr * 8 + 64 * 4 + (4 << a.hash_log2) + a.d_pad * 4 + kMaxR * a.W * 4 + 2 * kMaxR * 4;
   return (b + 15) & ~15;
 }
 

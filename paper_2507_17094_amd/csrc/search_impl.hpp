@@ -68,9 +68,15 @@ struct Searcher {
   int lane, team, tl;
   uint64_t qkey;
   uint32_t qq8;  // sum of q^2 over this lane's u8 elements
-  long long ctr[kNumCtr];
+  unsigned long long* ctr;  // per-query counters (LDS), see kernels.hpp
+  int dist_ctr;             // the counter distance evaluations go to
 
   __device__ Searcher(const StageArgs& args) : a(args) {}
+
+  // counters live in LDS so that they hold no scalar registers in the loops
+  __device__ __forceinline__ void ctr_add(int i, long long v) {
+    if (lane == 0) __hip_atomic_fetch_add(ctr + i, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
 
   // ---------------------------------------------------------------- hash
   __device__ __forceinline__ void hash_clear() {
@@ -305,7 +311,7 @@ struct Searcher {
     if (take) cid[lanes_below(tm)] = id;
     wsync();
     compute_dists(g, nc);
-    ctr[0] += nc;
+    ctr_add(dist_ctr, nc);
     uint64_t key = lane < nc ? ck[lane] : kDummy;
     wsync();
     key = nc > 32 ? bitonic_sort_u64<64>(key) : (nc > 16 ? bitonic_sort_u64<32>(key) : bitonic_sort_u64<16>(key));
@@ -330,10 +336,58 @@ struct Searcher {
     }
   }
 
+  // Query sign bits against each parent: bit i of word w is [q_j > x_j] for
+  // element j = 32 w + i of the parent's (decoded, scaled) row, 0 for j >= d;
+  // written to qsign[t * W + w]. Team t reads parent t's row in 16-byte chunks
+  // like the distance gathers, so every parent arrives in one round trip; the
+  // 32 / P16 chunks of a word sit in adjacent lanes and are OR-ed together.
+  __device__ __forceinline__ void parent_signs(const GraphCtx& g, int npar) {
+    const int W = a.W;
+    const size_t row_bytes = (size_t)a.d_pad * ESZ;
+    const bool mine = team < npar;
+    const uint32_t pt = pids[mine ? team : 0];
+    const gptr<u32x4_t> row = as_global((const u32x4_t*)((const char*)g.store + (size_t)pt * row_bytes));
+    uint4 buf[CPL];
+#pragma unroll
+    for (int m = 0; m < CPL; m++) buf[m] = load16(row, tl + 8 * m);
+    float su = 1.f;
+    if constexpr (kScaled) su = as_global(g.scale)[pt];
+    constexpr int LPW = 32 / P16;  // lanes (chunks) per 32-bit word
+#pragma unroll
+    for (int m = 0; m < CPL; m++) {
+      const int c = tl + 8 * m;
+      uint32_t bits = 0;
+      if constexpr (DT == DT_U8) {
+        const uint4 qv = ((const uint4*)qb)[c];
+        const uint32_t xw[4] = {buf[m].x, buf[m].y, buf[m].z, buf[m].w};
+        const uint32_t qw[4] = {qv.x, qv.y, qv.z, qv.w};
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+          const uint32_t qe = (qw[e >> 2] >> (8 * (e & 3))) & 0xFFu, xe = (xw[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+          bits |= (uint32_t)(qe > xe) << e;
+        }
+      } else {
+        float x[P16];
+        decode16<DT>(buf[m], x);
+        const float* qc = qf + c * P16;
+#pragma unroll
+        for (int e = 0; e < P16; e++) bits |= (uint32_t)(qc[e] > (kScaled ? su * x[e] : x[e])) << e;
+      }
+      const int valid = a.d - c * P16;
+      if (valid < P16) bits &= valid <= 0 ? 0u : ((1u << valid) - 1u);
+      uint32_t wv = bits << (P16 * (tl % LPW));
+      if constexpr (LPW >= 2) wv |= xor_lane<1>(wv);
+      if constexpr (LPW >= 4) wv |= xor_lane<2>(wv);
+      if constexpr (LPW >= 8) wv |= xor_lane<4>(wv);
+      const int w = c / LPW;
+      if (mine && tl % LPW == 0 && w < W) qsign[team * W + w] = wv;
+    }
+  }
+
   // ---------------------------------------------------------------- the loop
   // Steps 3-4 of Sec. 2.2 until no parent is eligible or T iterations ran.
   __device__ __forceinline__ void beam_loop(const GraphCtx& g, int l, int T, bool dgs_on, bool stop_nc, uint64_t stream,
-                            long long& n_exp, long long& n_iter, long long& last_topk) {
+                            int& n_exp, int& n_iter, int& last_topk) {
     const int r = a.r;
     const int n_cool = (a.cooldown_pm * T + 999) / 1000;
     const int t_dgs = T - n_cool;
@@ -382,30 +436,7 @@ struct Searcher {
 #pragma unroll
         for (int w = 0; w < kSW; w++)
           sw[w] = (!a.random_discard && w < W) ? as_global(srow)[(size_t)w * g.deg] : 0u;
-        // query sign bits against each parent: bit i = [q_i > x_parent,i]
-#pragma unroll
-        for (int t = 0; t < kMaxR; t++) {
-          if (t >= npar) break;
-          const uint32_t pt = pids[t];
-          const void* row = (const char*)g.store + (size_t)pt * a.d_pad * ESZ;
-          const float su = kScaled ? g.scale[pt] : 1.f;
-          for (int w2 = 0; w2 < W; w2 += 2) {
-            const int i = w2 * 32 + lane;
-            bool gt = false;
-            if (i < a.d) {
-              if constexpr (DT == DT_U8) gt = qb[i] > ((const uint8_t*)row)[i];
-              else {
-                const float x = load_elem<DT>((const void*)as_global((const char*)row), i);
-                gt = qf[i] > (kScaled ? su * x : x);
-              }
-            }
-            const uint64_t bits = ballot(gt);
-            if (lane == 0) {
-              qsign[t * W + w2] = (uint32_t)bits;
-              if (w2 + 1 < W) qsign[t * W + w2 + 1] = (uint32_t)(bits >> 32);
-            }
-          }
-        }
+        if (!a.random_discard) parent_signs(g, npar);
         wsync();
         uint32_t rk = 0xFFFFFFFFu;
         if (act) {
@@ -426,7 +457,7 @@ struct Searcher {
         const int src = pa * g.degp + (int)(rk & 0xFFu);
         const uint32_t nb_sel = shfl_u32(nb, kept ? src : lane);
         nb = kept ? nb_sel : kNone;
-        ctr[3] += (long long)(g.deg - keep) * npar;
+        ctr_add(3, (g.deg - keep) * npar);
       }
       const int changed = add_ids(g, nb != kNone, nb, l);
       n_exp += npar;
@@ -515,6 +546,8 @@ void stage_kernel(StageArgs a) {
   base += (size_t)a.lp_pow2 * 8;
   S.ck = (uint64_t*)base;
   base += 64 * 8;
+  S.ctr = (unsigned long long*)base;
+  base += kNumCtr * 8;
   S.cid = (uint32_t*)base;
   base += 64 * 4;
   S.hlog = a.hash_log2;
@@ -529,8 +562,8 @@ void stage_kernel(StageArgs a) {
   S.ppos = (int*)base;
   base += kMaxR * 4;
   S.pids = (uint32_t*)base;
-#pragma unroll
-  for (int i = 0; i < kNumCtr; i++) S.ctr[i] = 0;
+  if (S.lane < kNumCtr) S.ctr[S.lane] = 0;
+  S.dist_ctr = 0;
 
   S.qkey = a.qkeys ? a.qkeys[q] : (uint64_t)q;
   const int Sh = a.S;
@@ -548,7 +581,7 @@ void stage_kernel(StageArgs a) {
   S.hash_clear();
   S.p_reset(a.l);
   const bool use_entry = (t == 0) || !a.ppe;
-  long long n_exp = 0, n_iter = 0;
+  int n_exp = 0, n_iter = 0;
   // predicted entry: the row's seeds, or the ghost graph when the predictor was not confident
   int entry = a.entry;
   if (entry == 4) entry = (t == 0 && a.seeds[(size_t)q * a.n_seeds] != kNone) ? 3 : 1;
@@ -559,13 +592,12 @@ void stage_kernel(StageArgs a) {
       // ghost staging: a short search on the ghost graph (p and the hash serve as scratch)
       GraphCtx gg{sh.g_store, sh.g_scale, sh.g_graph, nullptr, sh.R, a.deg_g, a.degp_g};
       S.p_reset(a.l_g);
-      long long ge = 0, gi = 0, gl = 0;
-      const long long nd0 = S.ctr[0];
+      int ge = 0, gi = 0, gl = 0;
+      S.dist_ctr = 4;
       S.random_init(gg, stream_ghost, a.deg_g, a.l_g);
       S.beam_loop(gg, a.l_g, a.T_g, false, false, stream_ghost, ge, gi, gl);
-      S.ctr[4] += S.ctr[0] - nd0;
-      S.ctr[0] = nd0;
-      S.ctr[5] += ge;
+      S.dist_ctr = 0;
+      S.ctr_add(5, ge);
       const uint64_t gk = S.lane < a.t_seeds ? S.pk[S.lane] : kDummy;
       if (gk != kDummy) seed = make_key(key_dist(gk), sh.g_map[key_id(gk)], kFresh);
       wsync();
@@ -574,7 +606,7 @@ void stage_kernel(StageArgs a) {
     } else {
       const uint64_t dk = S.lane < a.t_seeds ? a.dense[((size_t)q * Sh + s) * a.t_seeds + S.lane] : kDummy;
       if (dk != kDummy) seed = make_key((uint32_t)(dk >> 32), (uint32_t)dk, kFresh);
-      S.ctr[4] += sh.R;
+      S.ctr_add(4, sh.R);
     }
     // the ghost seeds' distances are those of the nodes they copy
     S.add_keys(seed, a.l);
@@ -594,11 +626,11 @@ void stage_kernel(StageArgs a) {
       S.random_init(gm, stream_main, a.n_init, a.l);
     }
   }
-  long long last_topk = 0;
+  int last_topk = 0;
   S.beam_loop(gm, a.l, T, a.dgs != 0, a.stop_on_no_change != 0, stream_main, n_exp, n_iter, last_topk);
-  S.ctr[1] += n_exp;
-  S.ctr[2] += n_iter;
-  S.ctr[7] += last_topk;
+  S.ctr_add(1, n_exp);
+  S.ctr_add(2, n_iter);
+  S.ctr_add(7, last_topk);
 
   // hand-off to the next shard: I(z) for the first f entries
   if (Sh > 1 && a.ppe && t + 1 < Sh && S.lane < a.f) {
@@ -611,7 +643,7 @@ void stage_kernel(StageArgs a) {
     if (m > a.l) m = a.l;
     int real = 0;
     for (int i = 0; i < m; i += 64) real += __popcll(ballot(i + S.lane < m && S.pk[i + S.lane] != kDummy));
-    S.ctr[6] += real;
+    S.ctr_add(6, real);
     S.rerank(sh.orig, m);
   }
   // the stage's k results, ordered by (dist, global id) for the reduction over shards
@@ -635,9 +667,10 @@ void stage_kernel(StageArgs a) {
       a.stage_out[((size_t)q * Sh + t) * a.k + i] = key;
     }
   }
-  if (a.ctr && S.lane == 0) {
-    long long* c = (long long*)a.ctr + (size_t)q * kNumCtr;
-    for (int i = 0; i < kNumCtr; i++) c[i] = (t == 0 ? 0 : c[i]) + S.ctr[i];
+  wsync();
+  if (a.ctr && S.lane < kNumCtr) {
+    long long* c = (long long*)a.ctr + (size_t)q * kNumCtr + S.lane;
+    *c = (t == 0 ? 0 : *c) + (long long)S.ctr[S.lane];
   }
 }
 
