@@ -602,7 +602,8 @@ def main():
                      "with_ghost_GBps": (bytes_total + ghost_bytes) / (stage_total_ms * 1e-3) / 1e9},
         "counters_per_query": {"n_dist": float(ctr[:, 0].mean()), "n_exp": float(ctr[:, 1].mean()),
                                "iters": float(ctr[:, 2].mean()), "dgs_skipped": float(ctr[:, 3].mean()),
-                               "n_dist_ghost": float(ctr[:, 4].mean()), "n_exp_ghost": float(ctr[:, 5].mean())},
+                               "n_dist_ghost": float(ctr[:, 4].mean()), "n_exp_ghost": float(ctr[:, 5].mean()),
+                               "n_rerank": float(ctr[:, 6].mean()), "last_topk_iter": float(ctr[:, 7].mean())},
         "build_s": {"graph": t_graph, "ghost": t_ghost, "ground_truth": t_gt},
         "plain": plain,
         "sweep": [{k_: r[k_] for k_ in ("form", "variant", "itopk", "T", "recall", "qps")} for r in tuned_rows],

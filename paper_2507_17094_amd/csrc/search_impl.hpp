@@ -232,31 +232,74 @@ struct Searcher {
     }
   }
 
+  // Sums of the 8 lanes of each team for G rows at once (G = 1, 2, 4): each
+  // step halves the rows a lane carries, sending the half its partner keeps
+  // (the 8-lane mirror pairs lane i with 7 - i, then xor 2, then xor 1). Row
+  // ρ ends in lanes tl with tl / (8 / G) == ρ; every lane of those holds it.
+  template <typename V>
+  static __device__ __forceinline__ V mirror8(V v) {
+    if constexpr (sizeof(V) == 8) {
+      const uint64_t u = __builtin_bit_cast(uint64_t, v);
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x141, 0xF, 0xF, false);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x141, 0xF, 0xF, false);
+      return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+    } else {
+      return __builtin_bit_cast(V, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    }
+  }
+  template <typename V>
+  static __device__ __forceinline__ V xor_any(V v, int j) {
+    if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, xor_lane_u64(__builtin_bit_cast(uint64_t, v), j));
+    else return __builtin_bit_cast(V, xor_lane_u32(__builtin_bit_cast(uint32_t, v), j));
+  }
+  template <typename V>
+  __device__ __forceinline__ V team_reduce(V (&acc)[G]) const {
+    const bool b2 = (tl & 4) != 0, b1 = (tl & 2) != 0;
+    if constexpr (G == 1) {
+      V v = acc[0];
+      v += mirror8(v);
+      v += xor_any(v, 2);
+      v += xor_any(v, 1);
+      return v;
+    } else if constexpr (G == 2) {
+      V v = b2 ? acc[1] : acc[0];
+      v += mirror8(b2 ? acc[0] : acc[1]);
+      v += xor_any(v, 2);
+      v += xor_any(v, 1);
+      return v;
+    } else {
+      V k0 = b2 ? acc[2] : acc[0], k1 = b2 ? acc[3] : acc[1];
+      k0 += mirror8(b2 ? acc[0] : acc[2]);
+      k1 += mirror8(b2 ? acc[1] : acc[3]);
+      V v = b1 ? k1 : k0;
+      v += xor_any(b1 ? k0 : k1, 2);
+      v += xor_any(v, 1);
+      return v;
+    }
+  }
+
   // Keys (dist, id, fresh) of the candidate ids cid[0..nc) into ck[0..nc).
   __device__ __forceinline__ void compute_dists(const GraphCtx& g, int nc) {
-    const size_t row_bytes = (size_t)a.d_pad * ESZ;
+    const uint32_t row_bytes = (uint32_t)a.d_pad * ESZ;  // at most 1 KB
+    constexpr int LPR = 8 / G;  // lanes of a team that end with one row's sum
     for (int r0 = 0; r0 < nc; r0 += 8 * G) {
       uint4 buf[G][CPL];
       float sc[G];
-      uint32_t ids[G];
-      bool ok[G];
 #pragma unroll
       for (int gi = 0; gi < G; gi++) {
         // every lane loads (row 0 for the unused teams), so the gathers need no branches
         const int ci = r0 + gi * 8 + team;
-        ok[gi] = ci < nc;
-        ids[gi] = cid[ci < nc ? ci : 0];
-        const uint32_t lid = ok[gi] ? ids[gi] : 0u;
-        const gptr<u32x4_t> row = as_global((const u32x4_t*)((const char*)g.store + (size_t)lid * row_bytes));
+        const uint32_t lid = ci < nc ? cid[ci] : 0u;
+        const gptr<u32x4_t> row = as_global((const u32x4_t*)((const char*)g.store + (uint64_t)lid * row_bytes));
 #pragma unroll
         for (int m = 0; m < CPL; m++) buf[gi][m] = load16(row, tl + 8 * m);
         if constexpr (kScaled) sc[gi] = as_global(g.scale)[lid];
       }
+      uint32_t dbits;
+      if constexpr (DT == DT_U8) {
+        int part[G];
 #pragma unroll
-      for (int gi = 0; gi < G; gi++) {
-        asm volatile("" ::: "memory");  // re-read the query slice from LDS rather than pinning it in registers
-        uint32_t dbits;
-        if constexpr (DT == DT_U8) {
+        for (int gi = 0; gi < G; gi++) {
           uint32_t xx = 0, qx = 0;
 #pragma unroll
           for (int m = 0; m < CPL; m++) {
@@ -270,33 +313,45 @@ struct Searcher {
             qx = __builtin_amdgcn_udot4(buf[gi][m].z, qv.z, qx, false);
             qx = __builtin_amdgcn_udot4(buf[gi][m].w, qv.w, qx, false);
           }
-          int part = (int)(qq8 + xx - 2u * qx);
-          part += xor_lane_i32(part, 1);
-          part += xor_lane_i32(part, 2);
-          part += xor_lane_i32(part, 4);
-          dbits = (uint32_t)part;
-        } else {
-          double acc = 0.0;
+          part[gi] = (int)(qq8 + xx - 2u * qx);
+        }
+        dbits = (uint32_t)team_reduce(part);
+      } else {
+        double acc[G];
 #pragma unroll
-          for (int m = 0; m < CPL; m++) {
+        for (int gi = 0; gi < G; gi++) acc[gi] = 0.0;
+        // query chunk m once for the G rows
+#pragma unroll
+        for (int m = 0; m < CPL; m++) {
+          asm volatile("" ::: "memory");  // read each query chunk where it is used, not all up front
+          float qe[P16];
+          const float4* qc = (const float4*)(qf + (tl + 8 * m) * P16);
+#pragma unroll
+          for (int e4 = 0; e4 < P16 / 4; e4++) {
+            const float4 qv = qc[e4];
+            qe[4 * e4] = qv.x;
+            qe[4 * e4 + 1] = qv.y;
+            qe[4 * e4 + 2] = qv.z;
+            qe[4 * e4 + 3] = qv.w;
+          }
+#pragma unroll
+          for (int gi = 0; gi < G; gi++) {
             float x[P16];
             decode16<DT>(buf[gi][m], x);
-            const float* qc = qf + (tl + 8 * m) * P16;
 #pragma unroll
             for (int e = 0; e < P16; e++) {
               const float xe = kScaled ? sc[gi] * x[e] : x[e];
-              const float t = qc[e] - xe;  // float difference; its square is exact in double
-              acc = __builtin_fma((double)t, (double)t, acc);
+              const float t = qe[e] - xe;  // float difference; its square is exact in double
+              acc[gi] = __builtin_fma((double)t, (double)t, acc[gi]);
             }
           }
-          acc += xor_lane_f64(acc, 1);
-          acc += xor_lane_f64(acc, 2);
-          acc += xor_lane_f64(acc, 4);
-          dbits = __float_as_uint((float)acc);
         }
-        const int ci = r0 + gi * 8 + team;
-        if (tl == 0 && ok[gi]) ck[ci] = make_key(dbits, ids[gi], kFresh);
+        dbits = __float_as_uint((float)team_reduce(acc));
       }
+      // lane tl = rho * LPR writes row rho of its team
+      const int rho = tl / LPR;
+      const int ci = r0 + rho * 8 + team;
+      if (tl % LPR == 0 && ci < nc) ck[ci] = make_key(dbits, cid[ci], kFresh);
     }
     wsync();
   }
