@@ -722,146 +722,197 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
   return hipGetLastError();
 }
 
-constexpr int SK = 32;        // k-chunk (elements) staged in LDS
-constexpr int SKP = SK + 8;   // padded LDS row
-
 constexpr int DG = 8;     // columns per group minimum (pass 1)
-constexpr int SMAX = 16;  // candidate slots per (query, shard, 64-column tile) (pass 2)
+constexpr int SMAXH = 8;  // candidate slots per (query, shard, 32-column half tile) (pass 2)
 constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
 
-// The shard owning column gc of the concatenated ghost matrix (shards s0 .. s0 + nseg - 1).
-__device__ __forceinline__ int shard_of_col(const int64_t* __restrict__ off, int s0, int nseg, int64_t gc) {
-  int s = s0;
-  for (int i = 1; i < nseg; i++)
-    if (gc >= off[s0 + i]) s = s0 + i;
-  return s;
-}
+// LDS of the tile kernels: hi and lo bf16 copies of 64 query rows and of 64
+// ghost columns, each row padded by 8 elements (16 bytes) against bank conflicts.
+__host__ __device__ constexpr int dense_lds_stride(int dk) { return dk + 8; }
+inline size_t dense_tiles_lds(int dk) { return (size_t)4 * 64 * dense_lds_stride(dk) * 2; }
 
-// GEMM-form distances of a 64-row x 64-column tile (three bf16 products), then
-// MODE 0: the smallest distance of every 8 columns -> M;
-// MODE 1: the keys (dist bits << 32 | ghost index) at or below the row's bound for the tile's shard, into the
-// SMAX slots of (row, shard, tile); the four threads of a row place their keys by a prefix sum over the quad,
-// and the first writes the tile's count (which may exceed SMAX).
-template <int MODE>
-__global__ __launch_bounds__(256) void dense_pass_kernel(
+// 64 rows x DK bf16 (hi and lo) staged by 256 threads: thread t owns row t / 4
+// and the 16-byte chunks c = t % 4 + 4 m of it (DK / 32 chunks per array).
+template <int DK>
+struct Stage64 {
+  static constexpr int NCH = DK / 32;
+  u32x4_t h[NCH], l[NCH];  // ext-vector registers (a struct-typed uint4 array would live in scratch)
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ H, const uint16_t* __restrict__ L, int64_t row,
+                                       int c0) {
+    const u32x4_t* hp = (const u32x4_t*)(H + row * DK) + c0;
+    const u32x4_t* lp = (const u32x4_t*)(L + row * DK) + c0;
+#pragma unroll
+    for (int m = 0; m < NCH; m++) {
+      h[m] = hp[4 * m];
+      l[m] = lp[4 * m];
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t* Sh, uint16_t* Sl, int r, int c0) const {
+    constexpr int P = dense_lds_stride(DK);
+#pragma unroll
+    for (int m = 0; m < NCH; m++) {
+      *(u32x4_t*)&Sh[r * P + (c0 + 4 * m) * 8] = h[m];
+      *(u32x4_t*)&Sl[r * P + (c0 + 4 * m) * 8] = l[m];
+    }
+  }
+};
+
+// GEMM-form distances qn + gn - 2 q.g (three bf16 products: hi.hi + hi.lo + lo.hi)
+// of a block's 64 query rows against a run of 64-column tiles of one shard;
+// each wave owns a 32 x 32 quarter of every tile, and the accumulators are
+// consumed where the MFMA leaves them (lane = column, register = row):
+//   MODE 0: the minimum of every 8 columns (three DPP steps over 8 lanes) -> M;
+//   MODE 1: the keys (dist bits << 32 | ghost index) at or below the row's
+//   bound, placed by ballot into the SMAXH slots of (row, shard, 32-column half
+//   tile); the half tile's count (which may exceed SMAXH) goes to tcnt.
+// The next tile's columns are loaded into registers while the current one is
+// multiplied. Distances are clamped at 0 and handled as their bit patterns
+// (non-negative floats order like unsigned ints). Padding columns carry norm
+// +inf, so they never enter a minimum; MODE 1 also excludes them by index (the
+// bound may be +inf). Rows without a query get a NaN norm and never qualify.
+template <int MODE, int DK>
+__global__ __launch_bounds__(256) void dense_tiles_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
-    int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl, const float* __restrict__ gn,
-    int64_t col0, int64_t ncols, int dk, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0,
-    int nseg, int ntmax, float* __restrict__ M, const float* __restrict__ bound, int* __restrict__ tcnt,
-    uint64_t* __restrict__ slots) {
-  constexpr int TS = 64 + 4;
-  __shared__ __align__(16) char smem[4 * 64 * SKP * 2 > 64 * TS * 4 ? 4 * 64 * SKP * 2 : 64 * TS * 4];
+    int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
+    const float* __restrict__ gn, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0, int nseg,
+    int gps, int cg, int nht, int64_t mcols, int64_t mcol0, float* __restrict__ M, const float* __restrict__ bound,
+    int* __restrict__ tcnt, uint64_t* __restrict__ slots) {
+  constexpr int P = dense_lds_stride(DK);
+  extern __shared__ __align__(16) char dsm[];
   __shared__ int64_t qrow[64];
-  __shared__ float qnl[64];
-  uint16_t* Ah = (uint16_t*)smem;
-  uint16_t* Al = Ah + 64 * SKP;
-  uint16_t* Bh = Al + 64 * SKP;
-  uint16_t* Bl = Bh + 64 * SKP;
-  float* T = (float*)smem;  // reused after the products
+  __shared__ float qnl[64], bnl[64];
+  uint16_t* Ah = (uint16_t*)dsm;
+  uint16_t* Al = Ah + 64 * P;
+  uint16_t* Bh = Al + 64 * P;
+  uint16_t* Bl = Bh + 64 * P;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   const int64_t rl0 = (int64_t)blockIdx.y * 64;
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk) return;
-  for (int r = tid; r < 64; r += 256) {
-    const int64_t gr = row0 + rl0 + r;
-    const bool ok = gr < n_rows && rl0 + r < rows_chunk;
+  const int sl = (int)(blockIdx.x / (unsigned)gps), grp = (int)(blockIdx.x % (unsigned)gps);
+  const int s = s0 + sl;
+  const int64_t cb = off[s];  // first column of the shard's block
+  const int ntiles = (int)((off[s + 1] - cb) / 64);
+  const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
+  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
+  const int64_t R = Rs[s];
+  if (tid < 64) {
+    const int64_t gr = row0 + rl0 + tid;
+    const bool ok = gr < n_rows && rl0 + tid < rows_chunk;
     const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
-    qrow[r] = q;
-    qnl[r] = ok ? qn[q] : 0.f;
+    qrow[tid] = q;
+    qnl[tid] = ok ? qn[q] : __builtin_nanf("");
+    if constexpr (MODE == 1) bnl[tid] = ok ? bound[(rl0 + tid) * nseg + sl] : 0.f;
+  }
+  const int sr = tid >> 2, sc0 = tid & 3;
+  Stage64<DK> nb;
+  nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
+  __syncthreads();
+  {
+    Stage64<DK> a;
+    const int64_t q = qrow[sr];
+    a.load(Qh, Ql, q < 0 ? 0 : q, sc0);  // rows without a query read row 0
+    a.store(Ah, Al, sr, sc0);
   }
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  f32x16_t acc;
+  const int h = lane >> 5, col = lane & 31;
+  // this lane's 16 output rows: wr + 8 (j / 4) + 4 h + j % 4 (rows without a query still write M and counts:
+  // inside the chunk's buffers, never read)
+  float qr[16], br[16];
 #pragma unroll
-  for (int j = 0; j < 16; j++) acc[j] = 0.f;
-  // staging: thread -> (row tid / 4, 8 elements at (tid % 4) * 8) of each 64 x 32 operand block
-  const int sr = tid >> 2, sc = (tid & 3) * 8;
-  for (int k0 = 0; k0 < dk; k0 += SK) {
+  for (int j = 0; j < 16; j++) {
+    const int row = wr + 8 * (j >> 2) + 4 * h + (j & 3);
+    qr[j] = qnl[row];
+    br[j] = MODE == 1 ? bnl[row] : 0.f;
+  }
+  const int ra = (wr + col) * P + h * 8, rb = (wc + col) * P + h * 8;
+  for (int tt = tt0; tt < tt1; tt++) {
+    __syncthreads();  // the previous tile's B is consumed
+    nb.store(Bh, Bl, sr, sc0);
+    nb.load(Gh, Gl, cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr, sc0);  // (the last tile reloads itself)
     __syncthreads();
-    {
-      // rows without a query load row 0: an output row depends only on its own operand row
-      const int64_t q = qrow[sr] >= 0 ? qrow[sr] : 0;
-      *(uint4*)&Ah[sr * SKP + sc] = *(const uint4*)&Qh[q * dk + k0 + sc];
-      *(uint4*)&Al[sr * SKP + sc] = *(const uint4*)&Ql[q * dk + k0 + sc];
-      const int64_t g = col0 + c0 + sr;
-      *(uint4*)&Bh[sr * SKP + sc] = *(const uint4*)&Gh[g * dk + k0 + sc];
-      *(uint4*)&Bl[sr * SKP + sc] = *(const uint4*)&Gl[g * dk + k0 + sc];
-    }
-    __syncthreads();
+    f32x16_t acc;
 #pragma unroll
-    for (int kk = 0; kk < SK; kk += 16) {
-      const int ra = (wr + (lane & 31)) * SKP + kk + (lane >> 5) * 8;
-      const int rb = (wc + (lane & 31)) * SKP + kk + (lane >> 5) * 8;
-      const bf16x8_t ah = *(const bf16x8_t*)&Ah[ra], al = *(const bf16x8_t*)&Al[ra];
-      const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb], bl = *(const bf16x8_t*)&Bl[rb];
+    for (int j = 0; j < 16; j++) acc[j] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < DK; kk += 16) {
+      const bf16x8_t ah = *(const bf16x8_t*)&Ah[ra + kk], al = *(const bf16x8_t*)&Al[ra + kk];
+      const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb + kk], bl = *(const bf16x8_t*)&Bl[rb + kk];
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
     }
-  }
-  __syncthreads();
-  {
-    const int col = wc + (lane & 31);
-    const float gcol = gn[col0 + c0 + col];
+    const int jc = tt * 64 + wc + col;  // ghost index of this lane's column
+    const float gcol = gn[cb + jc];
+    if constexpr (MODE == 0) {
+      float* mrow = M + (rl0 + wr + 4 * h) * mcols + (cb - mcol0 + tt * 64 + wc) / DG + (col >> 3);
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-      const int row = wr + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-      const float dv = qnl[row] + gcol - 2.f * acc[j];
-      T[row * TS + col] = dv < 0.f ? 0.f : dv;
-    }
-  }
-  __syncthreads();
-  // the tile lies inside one shard's block (blocks are multiples of 64 columns)
-  const int s = shard_of_col(off, s0, nseg, col0 + c0);
-  const int sl = s - s0;
-  const int64_t jb = col0 + c0 - off[s];  // ghost index of the tile's first column
-  const int64_t R = Rs[s];
-  const int row = tid >> 2, c4 = tid & 3, cq = c4 * 16;
-  if (qrow[row] < 0) return;  // whole quads leave together (one row per quad)
-  const int64_t rr = rl0 + row;  // row within the chunk
-  if constexpr (MODE == 0) {
-#pragma unroll
-    for (int g = 0; g < 16 / DG; g++) {
-      float m = INFINITY;
-#pragma unroll
-      for (int e = 0; e < DG; e++) {
-        const int64_t j = jb + cq + g * DG + e;
-        if (j < R) m = fminf(m, T[row * TS + cq + g * DG + e]);
+      for (int j = 0; j < 16; j++) {
+        const float v = qr[j] + gcol - 2.f * acc[j];
+        uint32_t u = (uint32_t)max(__float_as_int(v), 0);
+        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, false));
+        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, false));
+        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xF, 0xF, false));
+        if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
       }
-      M[rr * (ncols / DG) + (c0 + cq) / DG + g] = m;
-    }
-  } else {
-    const float b = bound[rr * nseg + sl];
-    uint32_t pm = 0;
+    } else {
+      const bool cok = jc < R;
+      const int ht = tt * 2 + (wc >> 5);
+      const uint32_t below = (1u << col) - 1u;
+      const int64_t rbase = ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
 #pragma unroll
-    for (int e = 0; e < 16; e++) {
-      const int64_t j = jb + cq + e;
-      pm |= (j < R && T[row * TS + cq + e] <= b) ? (1u << e) : 0u;
-    }
-    // prefix over the quad (lanes 4 row .. 4 row + 3): quad_perm broadcasts of each lane's count
-    const int np = __popc(pm);
-    const int n0 = __builtin_amdgcn_mov_dpp(np, 0x00, 0xF, 0xF, false);
-    const int n1 = __builtin_amdgcn_mov_dpp(np, 0x55, 0xF, 0xF, false);
-    const int n2 = __builtin_amdgcn_mov_dpp(np, 0xAA, 0xF, 0xF, false);
-    const int n3 = __builtin_amdgcn_mov_dpp(np, 0xFF, 0xF, 0xF, false);
-    int at = (c4 > 0 ? n0 : 0) + (c4 > 1 ? n1 : 0) + (c4 > 2 ? n2 : 0);
-    const int64_t tile = jb / 64;
-    const int64_t base = (rr * nseg + sl) * ntmax + tile;
-    if (c4 == 0) tcnt[base] = n0 + n1 + n2 + n3;
-    uint64_t* L = slots + base * SMAX;
-    while (pm) {
-      const int e = __ffs(pm) - 1;
-      pm &= pm - 1;
-      if (at < SMAX) L[at] = ((uint64_t)__float_as_uint(T[row * TS + cq + e]) << 32) | (uint64_t)(jb + cq + e);
-      at++;
+      for (int j = 0; j < 16; j++) {
+        const float v = qr[j] + gcol - 2.f * acc[j];
+        const int vb = max(__float_as_int(v), 0);
+        const bool cand = cok && __int_as_float(vb) <= br[j];
+        const uint64_t bm = __ballot(cand);
+        const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
+        const int64_t base = rbase + (int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht;
+        const int pos = __popc(half & below);
+        if (cand && pos < SMAXH) slots[base * SMAXH + pos] = ((uint64_t)(uint32_t)vb << 32) | (uint64_t)jc;
+        if (col == 0) tcnt[base] = __popc(half);
+      }
     }
   }
 }
 
-// One wave per (row, shard): the bound for pass 2 = the kp-th smallest of the 4 smallest 8-column minima of
-// every lane (a subset of the shard's distances, so at least kp distances lie at or below it; +inf when the
-// shard has fewer than kp groups).
+template <int MODE>
+static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
+                               const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
+                               int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
+                               int64_t mcols, int64_t mcol0, float* Mg, const float* bnd, int* tcnt, uint64_t* slots) {
+#define MIANN_DENSE_TILES(KC)                                                                                        \
+  case KC: {                                                                                                         \
+    static bool set = false;                                                                                         \
+    if (!set) {                                                                                                      \
+      (void)hipFuncSetAttribute((const void*)dense_tiles_kernel<MODE, 32 * KC>,                                      \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
+      set = true;                                                                                                    \
+    }                                                                                                                \
+    hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
+                       chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, bnd,  \
+                       tcnt, slots);                                                                                 \
+    break;                                                                                                           \
+  }
+  switch (dk / 32) {
+    MIANN_DENSE_TILES(1)
+    MIANN_DENSE_TILES(2)
+    MIANN_DENSE_TILES(3)
+    MIANN_DENSE_TILES(4)
+    MIANN_DENSE_TILES(5)
+    MIANN_DENSE_TILES(6)
+    MIANN_DENSE_TILES(7)
+    MIANN_DENSE_TILES(8)
+    default: break;
+  }
+#undef MIANN_DENSE_TILES
+}
+
+// One wave per (row, shard): a bound for pass 2 such that at least kp of the
+// shard's distances lie at or below it. Every lane takes the smallest of its
+// 8-column minima (distinct columns); the kp-th smallest of those 64 values is
+// such a bound (kp <= 64), else the kp-th smallest of each lane's two smallest
+// (kp <= 128). +inf when the shard has fewer than kp groups.
 __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int64_t ncols,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ Rs, int s0, int nseg,
@@ -879,25 +930,26 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   const int kp = (int)(t + 16 < R ? t + 16 : R);
   const int64_t ng = (R + DG - 1) / DG;
   const float* m = M + rl * (ncols / DG) + (off[s] - col0) / DG;
-  // keys = distance bits (non-negative floats order like their bits); 0xFFFFFFFF = none
-  uint64_t v[4] = {kDummy, kDummy, kDummy, kDummy};
+  // float bits of non-negative values order like the values; 0xFFFFFFFF = none
+  uint32_t v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
   for (int64_t g = lane; g < ng; g += 64) {
-    uint64_t x = ((uint64_t)__float_as_uint(m[g]) << 32) | (uint64_t)g;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {  // insertion into the lane's 4 smallest
-      const uint64_t lo = x < v[i] ? x : v[i];
-      x = x < v[i] ? v[i] : x;
-      v[i] = lo;
-    }
+    const uint32_t x = __float_as_uint(m[g]);
+    const uint32_t lo = x < v0 ? x : v0;
+    v1 = x < v0 ? v0 : (x < v1 ? x : v1);
+    v0 = lo;
   }
-  bitonic_sort_regs<4>(v);
-  const int rk = (kp - 1) >> 6, lk = (kp - 1) & 63;
-  uint64_t x = v[0];
-#pragma unroll
-  for (int r = 1; r < 4; r++)
-    if (r == rk) x = v[r];
-  const uint64_t b = shfl_u64(x, lk);
-  if (lane == 0) bound[rl * nseg + sl] = b == kDummy ? INFINITY : __uint_as_float((uint32_t)(b >> 32));
+  uint32_t b;
+  if (kp <= 64) {
+    const uint32_t srt = bitonic_sort_u32<64>(v0);
+    b = (uint32_t)__builtin_amdgcn_readlane((int)srt, kp - 1);
+  } else {
+    uint64_t w[2] = {(uint64_t)v0, (uint64_t)v1};
+    bitonic_sort_regs<2>(w);
+    const int lk = (kp - 1) & 63;
+    const uint64_t x = (kp - 1) >= 64 ? w[1] : w[0];
+    b = (uint32_t)shfl_u32((uint32_t)x, lk);
+  }
+  if (lane == 0) bound[rl * nseg + sl] = b == 0xFFFFFFFFu ? INFINITY : __uint_as_float(b);
 }
 
 // Exact distance (the search's definition) of query row q to a stored row, by an 8-lane team; every lane of the
@@ -946,11 +998,12 @@ __device__ __forceinline__ uint32_t exact_dist_team(const void* __restrict__ Q, 
 }
 
 // One wave per (row, shard): sort the list's keys, rescore the kp smallest exactly, and write the exact top-t
-// seeds (dist bits << 32 | node id) to out[(q * S + s) * t + i]. A list that overflowed is replaced by an exact
-// scan of all the shard's ghosts, which gives the same exact top-t.
+// seeds (dist bits << 32 | node id) to out[(q * S + s) * t + i]. A half tile whose candidates overflowed its
+// slots enters with all its columns, rescored here; a list longer than CAPG is replaced by an exact scan of all
+// the shard's ghosts. Both give the same exact top-t.
 template <int DT>
 __global__ __launch_bounds__(256) void dense_final_kernel(
-    const uint64_t* __restrict__ slots, const int* __restrict__ tcnt, int ntmax, const uint32_t* __restrict__ list,
+    const uint64_t* __restrict__ slots, const int* __restrict__ tcnt, int nht, const uint32_t* __restrict__ list,
     const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
     const int64_t* __restrict__ Rs, int s0, int nseg, int t, const DenseShardDev* __restrict__ shd,
     const void* __restrict__ qraw, int d_pad, int S, uint64_t* __restrict__ out) {
@@ -969,28 +1022,54 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   const DenseShardDev sh = shd[s];
   uint64_t* ebuf = ebufs + wave * CAPG;
   const size_t row_bytes = (size_t)d_pad * ESZ;
-  // gather the tiles' slots: tile i (one per lane and round) holds min(tcnt, SMAX) keys
-  const int nt = (int)((R + 63) / 64);
-  const int64_t base = (rl * nseg + sl) * ntmax;
+  // gather the half tiles' slots: half tile i (one per lane and round) holds min(tcnt, SMAXH) keys; a half tile
+  // whose count overflowed its slots contributes all its 32 columns, with exact keys computed here
+  const int nt = (int)((R + 31) / 32);
+  const int64_t base = (rl * nseg + sl) * nht;
   int n = 0;
-  bool over = false;
   for (int i0 = 0; i0 < nt; i0 += 64) {
     const int i = i0 + lane;
     const int c = i < nt ? tcnt[base + i] : 0;
-    over |= __ballot(c > SMAX) != 0;
-    // inclusive prefix of c over the lanes
-    int pre = c;
+    const bool ovf = c > SMAXH;
+    const int ce = ovf ? 32 : c;
+    // inclusive prefix of ce over the lanes
+    int pre = ce;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = (int)shfl_u32((uint32_t)pre, lane >= o ? lane - o : lane);
       pre += lane >= o ? y : 0;
     }
-    const int at = n + pre - c;
-    if (!over)
-      for (int e = 0; e < c && at + e < CAPG; e++) ebuf[at + e] = slots[(base + i) * SMAX + e];
+    const int at = n + pre - ce;
+    if (c > 0 && !ovf) {
+      // the half tile's SMAXH slots in four 16-byte loads issued together
+      const u32x4_t* sp = (const u32x4_t*)(slots + (base + i) * SMAXH);
+      u32x4_t w[SMAXH / 2];
+#pragma unroll
+      for (int e2 = 0; e2 < SMAXH / 2; e2++) w[e2] = sp[e2];
+#pragma unroll
+      for (int e2 = 0; e2 < SMAXH / 2; e2++) {
+        if (2 * e2 < c && at + 2 * e2 < CAPG) ebuf[at + 2 * e2] = ((uint64_t)w[e2][1] << 32) | w[e2][0];
+        if (2 * e2 + 1 < c && at + 2 * e2 + 1 < CAPG) ebuf[at + 2 * e2 + 1] = ((uint64_t)w[e2][3] << 32) | w[e2][2];
+      }
+    }
+    uint64_t om = __ballot(ovf && at + 32 <= CAPG);
+    while (om) {
+      const int src = __ffsll((long long)om) - 1;
+      om &= om - 1;
+      const int hti = i0 + src;
+      const int ato = (int)shfl_u32((uint32_t)at, src);
+      for (int r0 = 0; r0 < 32; r0 += 8) {
+        const int64_t j = (int64_t)hti * 32 + r0 + team;
+        const bool ok = j < R;
+        const uint32_t jj = ok ? (uint32_t)j : 0u;
+        const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[jj] : 1.f;
+        const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)jj * row_bytes, sc, d_pad, tl);
+        if (tl == 0) ebuf[ato + r0 + team] = ok ? (((uint64_t)db << 32) | jj) : kDummy;
+      }
+    }
     n += (int)shfl_u32((uint32_t)pre, 63);
   }
-  over |= n > CAPG;
+  bool over = n > CAPG;
   wsync();
   uint64_t best;  // exact keys, ascending, one per lane (the first t are the result)
   if (!over) {
@@ -1023,10 +1102,13 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
       if (tl == 0 && ci < kp) ebuf[ci] = ok ? (((uint64_t)db << 32) | j) : kDummy;
       wsync();
     }
-    uint64_t w[2] = {ebuf[lane], 64 + lane < kp ? ebuf[64 + lane] : kDummy};
-    if (lane >= kp) w[0] = kDummy;
-    bitonic_sort_regs<2>(w);
-    best = w[0];
+    if (kp <= 64) {
+      best = bitonic_sort_u64<64>(lane < kp ? ebuf[lane] : kDummy);
+    } else {
+      uint64_t w[2] = {ebuf[lane], 64 + lane < kp ? ebuf[64 + lane] : kDummy};
+      bitonic_sort_regs<2>(w);
+      best = w[0];
+    }
   } else {
     // a tile or the row overflowed its slots: exact scan, 64 ghosts per round, merged into the running 64 best
     best = kDummy;
@@ -1100,11 +1182,12 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       rl = list;
       rc = qcnt;
     }
-    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], tile counts [rows][nseg][ntmax],
-    // slots [rows][nseg][ntmax][SMAX]
+    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], half-tile counts
+    // [rows][nseg][nht], slots [rows][nseg][nht][SMAXH]
     int64_t ntmax = 0;
     for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
-    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)ntmax * (4 + SMAX * 8));
+    const int64_t nht = 2 * ntmax;
+    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)nht * (4 + SMAXH * 8));
     int64_t chunk = ((int64_t)1 << 29) / (int64_t)per_row;  // at most 512 MB of scratch
     chunk = chunk < 64 ? 64 : chunk / 64 * 64;
     if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
@@ -1112,34 +1195,41 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     e = pool_malloc_async((void**)&wb, (size_t)chunk * per_row + 4096, st);
     if (e != hipSuccess) break;
     uint64_t* slots = (uint64_t*)wb;
-    float* Mg = (float*)(slots + (size_t)chunk * nseg * ntmax * SMAX);
+    float* Mg = (float*)(slots + (size_t)chunk * nseg * nht * SMAXH);
     float* bnd = Mg + (size_t)chunk * (ncols / DG);
     int* tcnt = (int*)(bnd + (size_t)chunk * nseg);
-    const dim3 gg((unsigned)(ncols / 64), (unsigned)(chunk / 64));
+    // column groups of cg tiles per block: enough blocks to fill the chip, each reusing its staged rows
+    const int64_t rtiles = chunk / 64;
+    int64_t gps = (2048 + rtiles * nseg - 1) / (rtiles * nseg);
+    gps = std::max<int64_t>(1, std::min<int64_t>(gps, ntmax));
+    const int cg = (int)((ntmax + gps - 1) / gps);
+    gps = (ntmax + cg - 1) / cg;
+    const dim3 gg((unsigned)(nseg * gps), (unsigned)rtiles);
+    const size_t lds = dense_tiles_lds(dk);
     const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
-    const int ntm = (int)ntmax;
+    const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
-      hipLaunchKernelGGL(dense_pass_kernel<0>, gg, dim3(256), 0, st, qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo,
-                         G.norm, col0, ncols, dk, G.off_dev, G.R_dev, s0, nseg, ntm, Mg, bnd, tcnt, slots);
+      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+                            ncols / DG, col0, Mg, bnd, tcnt, slots);
       hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, ncols, G.off_dev, G.R_dev, s0, nseg,
                          col0, rc, nq, row0, chunk, t, bnd);
-      hipLaunchKernelGGL(dense_pass_kernel<1>, gg, dim3(256), 0, st, qh, ql, qn, rl, rc, nq, row0, chunk, G.hi, G.lo,
-                         G.norm, col0, ncols, dk, G.off_dev, G.R_dev, s0, nseg, ntm, Mg, bnd, tcnt, slots);
+      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+                            ncols / DG, col0, Mg, bnd, tcnt, slots);
       switch (store_dt) {
         case DT_F32:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_F16:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_FP8:
-          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         default:
-          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, slots, tcnt, ntm, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
       }
