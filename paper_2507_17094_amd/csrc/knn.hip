@@ -723,7 +723,6 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
 }
 
 constexpr int DG = 8;     // columns per group minimum (pass 1)
-constexpr int SMAXH = 8;  // candidate slots per (query, shard, 32-column half tile) (pass 2)
 constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
 
 // LDS of the tile kernels: hi and lo bf16 copies of 64 query rows and of 64
@@ -762,9 +761,8 @@ struct Stage64 {
 // each wave owns a 32 x 32 quarter of every tile, and the accumulators are
 // consumed where the MFMA leaves them (lane = column, register = row):
 //   MODE 0: the minimum of every 8 columns (three DPP steps over 8 lanes) -> M;
-//   MODE 1: the keys (dist bits << 32 | ghost index) at or below the row's
-//   bound, placed by ballot into the SMAXH slots of (row, shard, 32-column half
-//   tile); the half tile's count (which may exceed SMAXH) goes to tcnt.
+//   MODE 1: the mask of the columns at or below the row's bound, one 32-bit
+//   ballot half per (row, shard, 32-column half tile) -> cmask.
 // The next tile's columns are loaded into registers while the current one is
 // multiplied. Distances are clamped at 0 and handled as their bit patterns
 // (non-negative floats order like unsigned ints). Padding columns carry norm
@@ -777,7 +775,7 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0, int nseg,
     int gps, int cg, int nht, int64_t mcols, int64_t mcol0, float* __restrict__ M, const float* __restrict__ bound,
-    int* __restrict__ tcnt, uint64_t* __restrict__ slots) {
+    uint32_t* __restrict__ cmask) {
   constexpr int P = dense_lds_stride(DK);
   extern __shared__ __align__(16) char dsm[];
   __shared__ int64_t qrow[64];
@@ -858,19 +856,133 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
     } else {
       const bool cok = jc < R;
       const int ht = tt * 2 + (wc >> 5);
-      const uint32_t below = (1u << col) - 1u;
-      const int64_t rbase = ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
+      uint32_t* mrow = cmask + ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
 #pragma unroll
       for (int j = 0; j < 16; j++) {
         const float v = qr[j] + gcol - 2.f * acc[j];
-        const int vb = max(__float_as_int(v), 0);
-        const bool cand = cok && __int_as_float(vb) <= br[j];
+        const bool cand = cok && v <= br[j];
         const uint64_t bm = __ballot(cand);
         const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
-        const int64_t base = rbase + (int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht;
-        const int pos = __popc(half & below);
-        if (cand && pos < SMAXH) slots[base * SMAXH + pos] = ((uint64_t)(uint32_t)vb << 32) | (uint64_t)jc;
-        if (col == 0) tcnt[base] = __popc(half);
+        if (col == 0) mrow[(int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht] = half;
+      }
+    }
+  }
+}
+
+// The same passes for rows of at most 128 elements, with twice the rows per
+// staged ghost tile: a block of 4 waves owns 128 query rows, each wave keeps its
+// 32 rows' hi and lo fragments in registers for the whole run of tiles and
+// multiplies them with both 32-column halves of every 64-column tile (six
+// MFMAs per 16-element k step). Only the ghost tile goes through LDS.
+template <int MODE, int DK>
+__global__ __launch_bounds__(256) void dense_tiles_wide_kernel(
+    const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
+    const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
+    int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
+    const float* __restrict__ gn, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0, int nseg,
+    int gps, int cg, int nht, int64_t mcols, int64_t mcol0, float* __restrict__ M, const float* __restrict__ bound,
+    uint32_t* __restrict__ cmask) {
+  static_assert(DK % 32 == 0 && DK <= 128, "DK");
+  constexpr int P = dense_lds_stride(DK);
+  constexpr int KB = DK / 16;
+  __shared__ __align__(16) uint16_t Bh[64 * P], Bl[64 * P];
+  __shared__ float qnl[128], bnl[128];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  const int64_t rl0 = (int64_t)blockIdx.y * 128;
+  const int sl = (int)(blockIdx.x / (unsigned)gps), grp = (int)(blockIdx.x % (unsigned)gps);
+  const int s = s0 + sl;
+  const int64_t cb = off[s];  // first column of the shard's block
+  const int ntiles = (int)((off[s + 1] - cb) / 64);
+  const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
+  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
+  const int64_t R = Rs[s];
+  const int h = lane >> 5, col = lane & 31, wr = wave * 32;
+  // this lane's A row (fragments of row wr + col) and the block's row norms and bounds
+  int64_t qa;
+  {
+    const int64_t gr = row0 + rl0 + wr + col;
+    const bool ok = gr < n_rows && rl0 + wr + col < rows_chunk;
+    qa = ok ? (list ? (int64_t)list[gr] : gr) : -1;
+  }
+  if (tid < 128) {
+    const int64_t gr = row0 + rl0 + tid;
+    const bool ok = gr < n_rows && rl0 + tid < rows_chunk;
+    const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
+    qnl[tid] = ok ? qn[q] : __builtin_nanf("");  // absent rows: NaN distances, never a candidate
+    if constexpr (MODE == 1) bnl[tid] = ok ? bound[(rl0 + tid) * nseg + sl] : 0.f;
+  }
+  bf16x8_t ah[KB], al[KB];
+  {
+    const int64_t q = qa < 0 ? 0 : qa;  // rows without a query read row 0
+    const bf16x8_t* hp = (const bf16x8_t*)(Qh + q * DK + h * 8);
+    const bf16x8_t* lp = (const bf16x8_t*)(Ql + q * DK + h * 8);
+#pragma unroll
+    for (int kb = 0; kb < KB; kb++) {
+      ah[kb] = hp[2 * kb];
+      al[kb] = lp[2 * kb];
+    }
+  }
+  const int sr = tid >> 2, sc0 = tid & 3;
+  Stage64<DK> nb;
+  nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
+  __syncthreads();
+  float qr[16], br[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int row = wr + 8 * (j >> 2) + 4 * h + (j & 3);
+    qr[j] = qnl[row];
+    br[j] = MODE == 1 ? bnl[row] : 0.f;
+  }
+  for (int tt = tt0; tt < tt1; tt++) {
+    __syncthreads();  // the previous tile is consumed
+    nb.store(Bh, Bl, sr, sc0);
+    nb.load(Gh, Gl, cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr, sc0);  // (the last tile reloads itself)
+    __syncthreads();
+    f32x16_t acc[2];
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+      for (int j = 0; j < 16; j++) acc[c][j] = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < KB; kb++) {
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        const int rb = (32 * c + col) * P + kb * 16 + h * 8;
+        const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb], bl = *(const bf16x8_t*)&Bl[rb];
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bh, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bl, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kb], bh, acc[c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const int wc = 32 * c;
+      const int jc = tt * 64 + wc + col;  // ghost index of this lane's column
+      const float gcol = gn[cb + jc];
+      if constexpr (MODE == 0) {
+        float* mrow = M + (rl0 + wr + 4 * h) * mcols + (cb - mcol0 + tt * 64 + wc) / DG + (col >> 3);
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+          const float v = qr[j] + gcol - 2.f * acc[c][j];
+          uint32_t u = (uint32_t)max(__float_as_int(v), 0);
+          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, false));
+          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, false));
+          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xF, 0xF, false));
+          if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
+        }
+      } else {
+        const bool cok = jc < R;
+        const int ht = tt * 2 + c;
+        uint32_t* mrow = cmask + ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+          const float v = qr[j] + gcol - 2.f * acc[c][j];
+          const bool cand = cok && v <= br[j];
+          const uint64_t bm = __ballot(cand);
+          const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
+          if (col == 0) mrow[(int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht] = half;
+        }
       }
     }
   }
@@ -880,7 +992,13 @@ template <int MODE>
 static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
                                const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
                                int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
-                               int64_t mcols, int64_t mcol0, float* Mg, const float* bnd, int* tcnt, uint64_t* slots) {
+                               int64_t mcols, int64_t mcol0, float* Mg, const float* bnd, uint32_t* cmask) {
+#define MIANN_DENSE_WIDE(KC)                                                                                         \
+  case KC:                                                                                                           \
+    hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
+                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, \
+                       bnd, cmask);                                                                                  \
+    break;
 #define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
     static bool set = false;                                                                                         \
@@ -891,14 +1009,14 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
     }                                                                                                                \
     hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
                        chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, bnd,  \
-                       tcnt, slots);                                                                                 \
+                       cmask);                                                                                       \
     break;                                                                                                           \
   }
   switch (dk / 32) {
-    MIANN_DENSE_TILES(1)
-    MIANN_DENSE_TILES(2)
-    MIANN_DENSE_TILES(3)
-    MIANN_DENSE_TILES(4)
+    MIANN_DENSE_WIDE(1)
+    MIANN_DENSE_WIDE(2)
+    MIANN_DENSE_WIDE(3)
+    MIANN_DENSE_WIDE(4)
     MIANN_DENSE_TILES(5)
     MIANN_DENSE_TILES(6)
     MIANN_DENSE_TILES(7)
@@ -906,13 +1024,17 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
     default: break;
   }
 #undef MIANN_DENSE_TILES
+#undef MIANN_DENSE_WIDE
 }
 
+// Rows per block of the tile passes for rows of dk elements.
+static int dense_block_rows(int dk) { return dk <= 128 ? 128 : 64; }
+
 // One wave per (row, shard): a bound for pass 2 such that at least kp of the
-// shard's distances lie at or below it. Every lane takes the smallest of its
-// 8-column minima (distinct columns); the kp-th smallest of those 64 values is
-// such a bound (kp <= 64), else the kp-th smallest of each lane's two smallest
-// (kp <= 128). +inf when the shard has fewer than kp groups.
+// shard's distances lie at or below it. Every lane keeps the two smallest of
+// its 8-column minima (distinct columns); the kp-th smallest of those 128
+// values is such a bound (kp <= 128), and nearly as tight as the kp-th
+// smallest of all the minima. +inf when the shard has fewer than kp groups.
 __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int64_t ncols,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ Rs, int s0, int nseg,
@@ -938,17 +1060,10 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
     v1 = x < v0 ? v0 : (x < v1 ? x : v1);
     v0 = lo;
   }
-  uint32_t b;
-  if (kp <= 64) {
-    const uint32_t srt = bitonic_sort_u32<64>(v0);
-    b = (uint32_t)__builtin_amdgcn_readlane((int)srt, kp - 1);
-  } else {
-    uint64_t w[2] = {(uint64_t)v0, (uint64_t)v1};
-    bitonic_sort_regs<2>(w);
-    const int lk = (kp - 1) & 63;
-    const uint64_t x = (kp - 1) >= 64 ? w[1] : w[0];
-    b = (uint32_t)shfl_u32((uint32_t)x, lk);
-  }
+  uint64_t w[2] = {(uint64_t)v0, (uint64_t)v1};
+  bitonic_sort_regs<2>(w);
+  const uint64_t x = (kp - 1) >= 64 ? w[1] : w[0];
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (kp - 1) & 63);
   if (lane == 0) bound[rl * nseg + sl] = b == 0xFFFFFFFFu ? INFINITY : __uint_as_float(b);
 }
 
@@ -997,17 +1112,77 @@ __device__ __forceinline__ uint32_t exact_dist_team(const void* __restrict__ Q, 
   }
 }
 
-// One wave per (row, shard): sort the list's keys, rescore the kp smallest exactly, and write the exact top-t
-// seeds (dist bits << 32 | node id) to out[(q * S + s) * t + i]. A half tile whose candidates overflowed its
-// slots enters with all its columns, rescored here; a list longer than CAPG is replaced by an exact scan of all
-// the shard's ghosts. Both give the same exact top-t.
+// Exact distances of two stored rows to query row qi by an 8-lane team (every lane of the team returns both).
+template <int DT>
+__device__ __forceinline__ void exact_dist_team2(const void* __restrict__ Q, int64_t qi, const void* __restrict__ brow0,
+                                                 float sc0, const void* __restrict__ brow1, float sc1, int bpad, int tl,
+                                                 uint32_t& d0, uint32_t& d1) {
+  constexpr int P16 = Fmt<DT>::per16;
+  constexpr int ESZ = Fmt<DT>::esize;
+  const int row16 = bpad * ESZ / 16;
+  const uint4* b0 = (const uint4*)brow0;
+  const uint4* b1 = (const uint4*)brow1;
+  if constexpr (DT == DT_U8) {
+    const uint4* q4 = (const uint4*)((const uint8_t*)Q + (size_t)qi * bpad);
+    int a0 = 0, a1 = 0;
+    for (int c = tl; c < row16; c += 8) {
+      const uint4 x0 = b0[c], x1 = b1[c], qb = q4[c];
+      const uint32_t w0[4] = {x0.x, x0.y, x0.z, x0.w}, w1[4] = {x1.x, x1.y, x1.z, x1.w};
+      const uint32_t qw[4] = {qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int qe = (int)((qw[e >> 2] >> (8 * (e & 3))) & 0xFF);
+        const int t0 = qe - (int)((w0[e >> 2] >> (8 * (e & 3))) & 0xFF);
+        const int t1 = qe - (int)((w1[e >> 2] >> (8 * (e & 3))) & 0xFF);
+        a0 += t0 * t0;
+        a1 += t1 * t1;
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      a0 += xor_lane_i32(a0, o);
+      a1 += xor_lane_i32(a1, o);
+    }
+    d0 = (uint32_t)a0;
+    d1 = (uint32_t)a1;
+  } else {
+    const float* qrow = (const float*)Q + (size_t)qi * bpad;
+    double a0 = 0.0, a1 = 0.0;
+    for (int c = tl; c < row16; c += 8) {
+      float x0[P16], x1[P16];
+      decode16<DT>(b0[c], x0);
+      decode16<DT>(b1[c], x1);
+#pragma unroll
+      for (int e = 0; e < P16; e++) {
+        const float qe = qrow[c * P16 + e];
+        const float t0 = qe - ((DT == DT_F16 || DT == DT_FP8) ? sc0 * x0[e] : x0[e]);
+        const float t1 = qe - ((DT == DT_F16 || DT == DT_FP8) ? sc1 * x1[e] : x1[e]);
+        a0 = __builtin_fma((double)t0, (double)t0, a0);
+        a1 = __builtin_fma((double)t1, (double)t1, a1);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      a0 += xor_lane_f64(a0, o);
+      a1 += xor_lane_f64(a1, o);
+    }
+    d0 = __float_as_uint((float)a0);
+    d1 = __float_as_uint((float)a1);
+  }
+}
+
+// One wave per (row, shard): expand the candidate masks of the shard's half tiles into a column list, compute
+// every candidate's exact distance, sort, and write the exact top-t seeds (dist bits << 32 | node id) to
+// out[(q * S + s) * t + i]. A list longer than CAPG is replaced by an exact scan of all the shard's ghosts;
+// both give the exact top-t.
 template <int DT>
 __global__ __launch_bounds__(256) void dense_final_kernel(
-    const uint64_t* __restrict__ slots, const int* __restrict__ tcnt, int nht, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
     const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
     const int64_t* __restrict__ Rs, int s0, int nseg, int t, const DenseShardDev* __restrict__ shd,
     const void* __restrict__ qraw, int d_pad, int S, uint64_t* __restrict__ out) {
   constexpr int ESZ = Fmt<DT>::esize;
+  constexpr bool kScaled = DT == DT_F16 || DT == DT_FP8;
   __shared__ uint64_t ebufs[4 * CAPG];
   const int wave = threadIdx.x >> 6, lane = lane_id(), team = lane >> 3, tl = lane & 7;
   const int64_t item = (int64_t)blockIdx.x * 4 + wave;
@@ -1017,107 +1192,71 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   if (rl >= rows_chunk || row0 + rl >= n_rows) return;
   const int s = s0 + sl;
   const int64_t R = Rs[s];
-  const int kp = (int)(t + 16 < R ? t + 16 : R);
   const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
   const DenseShardDev sh = shd[s];
   uint64_t* ebuf = ebufs + wave * CAPG;
   const size_t row_bytes = (size_t)d_pad * ESZ;
-  // gather the half tiles' slots: half tile i (one per lane and round) holds min(tcnt, SMAXH) keys; a half tile
-  // whose count overflowed its slots contributes all its 32 columns, with exact keys computed here
+  // candidate columns: half tile i (one per lane and round) contributes the set bits of its mask
   const int nt = (int)((R + 31) / 32);
-  const int64_t base = (rl * nseg + sl) * nht;
+  const uint32_t* mrow = cmask + (rl * nseg + sl) * nht;
   int n = 0;
   for (int i0 = 0; i0 < nt; i0 += 64) {
     const int i = i0 + lane;
-    const int c = i < nt ? tcnt[base + i] : 0;
-    const bool ovf = c > SMAXH;
-    const int ce = ovf ? 32 : c;
-    // inclusive prefix of ce over the lanes
-    int pre = ce;
+    uint32_t m = i < nt ? mrow[i] : 0u;
+    const int c = __popc(m);
+    int pre = c;  // inclusive prefix over the lanes
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = (int)shfl_u32((uint32_t)pre, lane >= o ? lane - o : lane);
       pre += lane >= o ? y : 0;
     }
-    const int at = n + pre - ce;
-    if (c > 0 && !ovf) {
-      // the half tile's SMAXH slots in four 16-byte loads issued together
-      const u32x4_t* sp = (const u32x4_t*)(slots + (base + i) * SMAXH);
-      u32x4_t w[SMAXH / 2];
-#pragma unroll
-      for (int e2 = 0; e2 < SMAXH / 2; e2++) w[e2] = sp[e2];
-#pragma unroll
-      for (int e2 = 0; e2 < SMAXH / 2; e2++) {
-        if (2 * e2 < c && at + 2 * e2 < CAPG) ebuf[at + 2 * e2] = ((uint64_t)w[e2][1] << 32) | w[e2][0];
-        if (2 * e2 + 1 < c && at + 2 * e2 + 1 < CAPG) ebuf[at + 2 * e2 + 1] = ((uint64_t)w[e2][3] << 32) | w[e2][2];
-      }
-    }
-    uint64_t om = __ballot(ovf && at + 32 <= CAPG);
-    while (om) {
-      const int src = __ffsll((long long)om) - 1;
-      om &= om - 1;
-      const int hti = i0 + src;
-      const int ato = (int)shfl_u32((uint32_t)at, src);
-      for (int r0 = 0; r0 < 32; r0 += 8) {
-        const int64_t j = (int64_t)hti * 32 + r0 + team;
-        const bool ok = j < R;
-        const uint32_t jj = ok ? (uint32_t)j : 0u;
-        const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[jj] : 1.f;
-        const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)jj * row_bytes, sc, d_pad, tl);
-        if (tl == 0) ebuf[ato + r0 + team] = ok ? (((uint64_t)db << 32) | jj) : kDummy;
-      }
+    int at = n + pre - c;
+    while (m) {
+      const int b = __ffs(m) - 1;
+      m &= m - 1;
+      if (at < CAPG) ebuf[at] = (uint64_t)(i * 32 + b);
+      at++;
     }
     n += (int)shfl_u32((uint32_t)pre, 63);
   }
-  bool over = n > CAPG;
   wsync();
   uint64_t best;  // exact keys, ascending, one per lane (the first t are the result)
-  if (!over) {
+  if (n <= CAPG) {
+    // exact distances, two candidates per 8-lane team and round
+    for (int r0 = 0; r0 < n; r0 += 16) {
+      const int c0 = r0 + team, c1 = r0 + 8 + team;
+      const uint32_t j0 = c0 < n ? (uint32_t)ebuf[c0] : 0u, j1 = c1 < n ? (uint32_t)ebuf[c1] : 0u;
+      const float sc0 = kScaled ? sh.g_scale[j0] : 1.f, sc1 = kScaled ? sh.g_scale[j1] : 1.f;
+      uint32_t d0, d1;
+      exact_dist_team2<DT>(qraw, qi, (const char*)sh.g_store + (size_t)j0 * row_bytes, sc0,
+                           (const char*)sh.g_store + (size_t)j1 * row_bytes, sc1, d_pad, tl, d0, d1);
+      wsync();
+      if (tl == 0 && c0 < n) ebuf[c0] = ((uint64_t)d0 << 32) | j0;
+      if (tl == 0 && c1 < n) ebuf[c1] = ((uint64_t)d1 << 32) | j1;
+      wsync();
+    }
     uint64_t v[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < n ? ebuf[r * 64 + lane] : kDummy;
-    wsync();
     if (n <= 64) {
       v[0] = bitonic_sort_u64<64>(v[0]);
     } else if (n <= 128) {
       uint64_t w[2] = {v[0], v[1]};
       bitonic_sort_regs<2>(w);
       v[0] = w[0];
-      v[1] = w[1];
     } else {
       bitonic_sort_regs<4>(v);
     }
-    // the kp smallest GEMM-form keys, rescored exactly in rounds of 8 rows
-    ebuf[lane] = lane < kp ? v[0] : kDummy;
-    ebuf[64 + lane] = 64 + lane < kp ? v[1] : kDummy;
-    wsync();
-    for (int r0 = 0; r0 < kp; r0 += 8) {
-      const int ci = r0 + team;
-      const uint64_t key = ci < kp ? ebuf[ci] : kDummy;
-      const bool ok = key != kDummy;
-      const uint32_t j = ok ? (uint32_t)key : 0u;
-      const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[j] : 1.f;
-      const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)j * row_bytes, sc, d_pad, tl);
-      wsync();
-      if (tl == 0 && ci < kp) ebuf[ci] = ok ? (((uint64_t)db << 32) | j) : kDummy;
-      wsync();
-    }
-    if (kp <= 64) {
-      best = bitonic_sort_u64<64>(lane < kp ? ebuf[lane] : kDummy);
-    } else {
-      uint64_t w[2] = {ebuf[lane], 64 + lane < kp ? ebuf[64 + lane] : kDummy};
-      bitonic_sort_regs<2>(w);
-      best = w[0];
-    }
+    best = v[0];
   } else {
-    // a tile or the row overflowed its slots: exact scan, 64 ghosts per round, merged into the running 64 best
+    // too many candidates: exact scan, 64 ghosts per round, merged into the running 64 best
     best = kDummy;
     for (int64_t g0 = 0; g0 < R; g0 += 64) {
       for (int r0 = 0; r0 < 64; r0 += 8) {
         const int64_t j = g0 + r0 + team;
         const bool ok = j < R;
         const uint32_t jj = ok ? (uint32_t)j : 0u;
-        const float sc = (DT == DT_F16 || DT == DT_FP8) ? sh.g_scale[jj] : 1.f;
+        const float sc = kScaled ? sh.g_scale[jj] : 1.f;
         const uint32_t db = exact_dist_team<DT>(qraw, qi, (const char*)sh.g_store + (size_t)jj * row_bytes, sc, d_pad, tl);
         if (tl == 0) ebuf[r0 + team] = ok ? (((uint64_t)db << 32) | jj) : kDummy;
       }
@@ -1182,24 +1321,23 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       rl = list;
       rc = qcnt;
     }
-    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], half-tile counts
-    // [rows][nseg][nht], slots [rows][nseg][nht][SMAXH]
+    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], candidate masks [rows][nseg][nht]
     int64_t ntmax = 0;
     for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
     const int64_t nht = 2 * ntmax;
-    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)nht * (4 + SMAXH * 8));
+    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)nht * 4);
+    const int brows = dense_block_rows(dk);
     int64_t chunk = ((int64_t)1 << 29) / (int64_t)per_row;  // at most 512 MB of scratch
-    chunk = chunk < 64 ? 64 : chunk / 64 * 64;
-    if (chunk > (nq + 63) / 64 * 64) chunk = (nq + 63) / 64 * 64;
+    chunk = chunk < brows ? brows : chunk / brows * brows;
+    if (chunk > (nq + brows - 1) / brows * brows) chunk = (nq + brows - 1) / brows * brows;
     char* wb = nullptr;
     e = pool_malloc_async((void**)&wb, (size_t)chunk * per_row + 4096, st);
     if (e != hipSuccess) break;
-    uint64_t* slots = (uint64_t*)wb;
-    float* Mg = (float*)(slots + (size_t)chunk * nseg * nht * SMAXH);
+    uint32_t* cmask = (uint32_t*)wb;
+    float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
     float* bnd = Mg + (size_t)chunk * (ncols / DG);
-    int* tcnt = (int*)(bnd + (size_t)chunk * nseg);
     // column groups of cg tiles per block: enough blocks to fill the chip, each reusing its staged rows
-    const int64_t rtiles = chunk / 64;
+    const int64_t rtiles = chunk / brows;
     int64_t gps = (2048 + rtiles * nseg - 1) / (rtiles * nseg);
     gps = std::max<int64_t>(1, std::min<int64_t>(gps, ntmax));
     const int cg = (int)((ntmax + gps - 1) / gps);
@@ -1210,26 +1348,26 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
       launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
-                            ncols / DG, col0, Mg, bnd, tcnt, slots);
+                            ncols / DG, col0, Mg, bnd, cmask);
       hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, ncols, G.off_dev, G.R_dev, s0, nseg,
                          col0, rc, nq, row0, chunk, t, bnd);
       launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
-                            ncols / DG, col0, Mg, bnd, tcnt, slots);
+                            ncols / DG, col0, Mg, bnd, cmask);
       switch (store_dt) {
         case DT_F32:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_F16:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_FP8:
-          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         default:
-          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, slots, tcnt, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
       }
