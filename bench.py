@@ -105,6 +105,51 @@ def measured_traffic(workload, itopk, T, opts):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"] if same else None
 
 
+TRAFFIC_SOURCES = ["paper_2507_17094_amd/csrc/search_impl.hpp", "paper_2507_17094_amd/csrc/search_f32.hip",
+                   "paper_2507_17094_amd/csrc/search.hip", "paper_2507_17094_amd/csrc/common.hpp",
+                   "paper_2507_17094_amd/csrc/kernels.hpp"]
+
+
+def _pmc_per_dispatch(db, counter, name_like):
+    """Mean over dispatches of a counter (summed over its instances) for kernels whose name matches."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    per = {}
+    for disp, v in con.execute("select dispatch_id, counter_value from pmc_events where counter_name = ? and "
+                               "name like ?", (counter, name_like)):
+        per[disp] = per.get(disp, 0.0) + v
+    return (sum(per.values()) / len(per), len(per)) if per else (0.0, 0)
+
+
+def record_traffic(args):
+    """Writes the calibrated FETCH_SIZE + WRITE_SIZE bytes per stage launch of the --fixed setting (the counters are
+    KiB per dispatch; each is scaled by what it reads for a plain copy of known size)."""
+    import hashlib
+    fdb, wdb, cfdb, cwdb = args.record_traffic
+    f = args.fixed.split(",")
+    fetch_kib, n_f = _pmc_per_dispatch(fdb, "FETCH_SIZE", "void miann::stage_kernel%")
+    write_kib, n_w = _pmc_per_dispatch(wdb, "WRITE_SIZE", "void miann::stage_kernel%")
+    # the copies only (the run also fills the source tensor once)
+    cal_f, _ = _pmc_per_dispatch(cfdb, "FETCH_SIZE", "%copyBuffer%")
+    cal_w, _ = _pmc_per_dispatch(cwdb, "WRITE_SIZE", "%copyBuffer%")
+    copy_kib = 1024 * 1024  # --copy-calibration 1024: one copy reads and writes 1 GiB
+    f_scale, w_scale = copy_kib / cal_f, copy_kib / cal_w
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    rec = {"kernel": "stage_kernel<f32, 3 chunks per row>", "sources": TRAFFIC_SOURCES,
+           "sources_sha256": h.hexdigest(), "workload": args.workload,
+           "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
+                       "ghost_every_stage": bool(int(f[4]))},
+           "fetch_bytes_per_launch": fetch_kib * 1024 * f_scale, "write_bytes_per_launch": write_kib * 1024 * w_scale,
+           "fetch_scale": f_scale, "write_scale": w_scale, "launches": min(n_f, n_w)}
+    path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_stage):
     """Bytes the stage kernel must move per batch, from the per-query counters.
     HBM-resident arrays: gathered vectors (n_dist rows), adjacency rows (n_exp),
@@ -428,7 +473,14 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the reference for the HBM "
                          "byte counters")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "CAL_FETCH_DB", "CAL_WRITE_DB"),
+                    help="only write the stage kernel's calibrated HBM traffic for the --fixed setting from four "
+                         "rocprofv3 --pmc databases (FETCH_SIZE and WRITE_SIZE of the setting, then of "
+                         "--copy-calibration 1024) to the profiles record")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
