@@ -300,6 +300,32 @@ __device__ __forceinline__ uint64_t bitonic_merge_u64(uint64_t key) {
   return key;
 }
 
+// The smaller half of each segment of SEG keys, unordered, in the segment's
+// lower SEG/2 lanes: the halves are sorted in opposite directions and one
+// compare-exchange across them keeps the minima below (the first step of the
+// final bitonic merge; the remaining log2(SEG) - 1 steps would only order them).
+template <int SEG, int K, int J>
+__device__ __forceinline__ void bsel_stage_u32(uint32_t& key) {
+  key = xchg_u32<keep_min_mask(K, J, SEG, 0), J>(key);
+  if constexpr (J > 1) bsel_stage_u32<SEG, K, J / 2>(key);
+  else if constexpr (K < SEG / 2) bsel_stage_u32<SEG, K * 2, K>(key);
+}
+template <int SEG>
+__device__ __forceinline__ uint32_t bitonic_lower_half_u32(uint32_t key) {
+  if constexpr (SEG > 2) bsel_stage_u32<SEG, 2, 1>(key);
+  return xchg_u32<keep_min_mask(SEG, SEG / 2, SEG, 0), SEG / 2>(key);
+}
+__device__ __forceinline__ uint32_t bitonic_lower_half_u32_seg(uint32_t key, int seg) {
+  switch (seg) {
+    case 2: return bitonic_lower_half_u32<2>(key);
+    case 4: return bitonic_lower_half_u32<4>(key);
+    case 8: return bitonic_lower_half_u32<8>(key);
+    case 16: return bitonic_lower_half_u32<16>(key);
+    case 32: return bitonic_lower_half_u32<32>(key);
+    default: return bitonic_lower_half_u32<64>(key);
+  }
+}
+
 // Runtime-segment dispatch (seg in {2,4,...,64}).
 __device__ __forceinline__ uint32_t bitonic_sort_u32_seg(uint32_t key, int seg) {
   switch (seg) {

@@ -874,8 +874,9 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
 // 32 rows' hi and lo fragments in registers for the whole run of tiles and
 // multiplies them with both 32-column halves of every 64-column tile (six
 // MFMAs per 16-element k step). Only the ghost tile goes through LDS.
+// (3 waves per SIMD fit without spills up to 96-element rows; wider rows keep the compiler's budget)
 template <int MODE, int DK>
-__global__ __launch_bounds__(256) void dense_tiles_wide_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 3 : 1))) void dense_tiles_wide_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
@@ -927,12 +928,13 @@ __global__ __launch_bounds__(256) void dense_tiles_wide_kernel(
   Stage64<DK> nb;
   nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
   __syncthreads();
-  float qr[16], br[16];
+  // MODE 0: the row norms; MODE 1: per row, bound - norm (a column qualifies iff gn - 2 q.g <= it; NaN for
+  // absent rows, so they never qualify)
+  float qr[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     const int row = wr + 8 * (j >> 2) + 4 * h + (j & 3);
-    qr[j] = qnl[row];
-    br[j] = MODE == 1 ? bnl[row] : 0.f;
+    qr[j] = MODE == 1 ? bnl[row] - qnl[row] : qnl[row];
   }
   for (int tt = tt0; tt < tt1; tt++) {
     __syncthreads();  // the previous tile is consumed
@@ -977,8 +979,7 @@ __global__ __launch_bounds__(256) void dense_tiles_wide_kernel(
         uint32_t* mrow = cmask + ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
 #pragma unroll
         for (int j = 0; j < 16; j++) {
-          const float v = qr[j] + gcol - 2.f * acc[c][j];
-          const bool cand = cok && v <= br[j];
+          const bool cand = cok && gcol - 2.f * acc[c][j] <= qr[j];
           const uint64_t bm = __ballot(cand);
           const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
           if (col == 0) mrow[(int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht] = half;

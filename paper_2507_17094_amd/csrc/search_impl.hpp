@@ -507,7 +507,8 @@ struct Searcher {
             rk = ((uint32_t)mm << 8) | (uint32_t)slot;
           }
         }
-        rk = bitonic_sort_u32_seg(rk, g.degp);
+        // the kept slots: the keep smallest (mismatch, slot) keys of each parent's segment, first in it
+        rk = 2 * keep == g.degp ? bitonic_lower_half_u32_seg(rk, g.degp) : bitonic_sort_u32_seg(rk, g.degp);
         const bool kept = act && slot < keep && rk != 0xFFFFFFFFu;
         const int src = pa * g.degp + (int)(rk & 0xFFu);
         const uint32_t nb_sel = shfl_u32(nb, kept ? src : lane);
