@@ -340,12 +340,18 @@ def form_learned(args):
                 log(f"  learned tau={tau:4.2f} x{bs:.0f} itopk={itopk:3d} T={T:3d} recall={rp:.4f} "
                     f"qps={W['nq'] / secp:,.0f} dists={ndp:.0f} fallback={fb:.3f}")
 
+    # The ghost-entry cap (a query whose nearest neighbours' component holds no ghost is not reached) keeps every
+    # form below 0.95 here, so the forms are compared at a matched recall: 99% of the best recall any row reached.
+    # A form that never reaches it is reported at its own highest recall, marked "reached": false.
+    r_match = 0.99 * max(r["recall"] for r in rows)
+
     def best(form):
         rr = [r for r in rows if r["form"] == form or (form == "learned" and r["form"].startswith("learned"))]
-        ok = [r for r in rr if r["recall"] >= 0.95]
-        return max(ok, key=lambda r: r["qps"]) if ok else max(rr, key=lambda r: r["recall"])
+        ok = [r for r in rr if r["recall"] >= r_match]
+        if ok:
+            return dict(max(ok, key=lambda r: r["qps"]), reached=True)
+        return dict(max(rr, key=lambda r: r["recall"]), reached=False)
 
-    # the ghost-entry cap: a query whose nearest neighbours' component holds no ghost is not reached
     bg, bd, bl = best("ghost"), best("ghost_dense"), best("learned")
     out = {
         "metric": METRIC, "value": bl["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
@@ -354,7 +360,8 @@ def form_learned(args):
         "config": {"workload": f"learned1m: N={W['N']} d={W['d']} f32 ({W['C']}-component mixture), degree "
                                f"{W['deg']}, {W['R']} ghosts; BF16 MLP {W['d']}-{W['hidden']}-{W['hidden']}-"
                                f"{W['R'] + 1} trained on {W['n_train']} queries, {W['nq']} held-out queries"},
-        "ghost_staging": bg, "ghost_staging_dense": bd, "learned": bl, "gain_qps": bl["qps"] / bg["qps"],
+        "matched_recall": r_match, "ghost_staging": bg, "ghost_staging_dense": bd, "learned": bl,
+        "gain_qps_vs_dense": bl["qps"] / bd["qps"], "gain_dists_vs_dense": bd["n_dist"] / bl["n_dist"],
         "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "predict_ms": t_predict * 1e3,
         "sweep": rows, "build_s": t_build,
     }

@@ -747,9 +747,15 @@ static hipError_t launch_occ(const StageArgs& a, hipStream_t st) {
 
 template <int DT, int CPL>
 static hipError_t launch_t(const StageArgs& a, hipStream_t st) {
-  // 5 waves per SIMD = 20 per CU must fit the CU's 160 KB of LDS
-  if ((int64_t)a.per_wave_lds * 20 <= 160 * 1024) return launch_occ<DT, CPL, 5>(a, st);
-  return launch_occ<DT, CPL, 0>(a, st);
+  // FP8 rows decode into 16 floats per chunk: at 96 VGPRs that kernel spills inside its loops (88 to 236 bytes
+  // per lane) and is slower than at 4 waves, so it keeps the compiler's budget
+  if constexpr (DT == DT_FP8) {
+    return launch_occ<DT, CPL, 0>(a, st);
+  } else {
+    // 5 waves per SIMD = 20 per CU must fit the CU's 160 KB of LDS
+    if ((int64_t)a.per_wave_lds * 20 <= 160 * 1024) return launch_occ<DT, CPL, 5>(a, st);
+    return launch_occ<DT, CPL, 0>(a, st);
+  }
 }
 
 template <int DT>
