@@ -75,6 +75,24 @@ def test_search_parity_odd_dims(d):
         compare(g, o, label=f"d{d}-{kw}", ndist_check=not ghost_entry(opts))
 
 
+def test_dense_entry_equidistant_ghosts():
+    """Dense entry when every ghost is equidistant from the query: sign vectors in {-1, 1}^32 (all of squared norm
+    32 exactly) and queries at the origin. Every ghost passes the GEMM-form bound, so each list is longer than the
+    rescoring capacity and the kernel falls back to its exact scan; the seeds must still be the exact top-t by
+    (dist, id). Half-scaled copies of data points as queries exercise the ordinary path on the same index."""
+    say("dense entry, equidistant ghosts")
+    rng = np.random.default_rng(61)
+    d = 32
+    X = rng.choice(np.array([-1.0, 1.0], dtype=np.float32), size=(2000, d))
+    Q = np.concatenate([np.zeros((16, d), np.float32), 0.5 * X[:16]]).astype(np.float32)
+    ox = oracle.build_index(X, deg=16, dgs=True, ghost_R=400, deg_g=8)
+    gx = to_device_index(ox)
+    for kw in (dict(entry="ghost_dense"), dict(entry="ghost_dense", dgs=True, t_seeds=48)):
+        opts = miann.SearchOptions(**kw)
+        g, o = run_both(ox, gx, Q, K, 48, 20, opts)
+        compare(g, o, label=f"signs-{kw}", ndist_check=False)
+
+
 @pytest.mark.parametrize("S", [2, 3])
 def test_path_extension_parity(S):
     """Path extension across S resident shards (Sec. 3.1.2) and naive sharding."""
