@@ -36,6 +36,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
   // row-major B along N) and the tile lies inside the matrix; element-wise staging otherwise
   const bool a_vec = sac == 1 && (sar & 7) == 0 && (K & 7) == 0 && i0 + GT <= M;
   const bool b_vec = sbc == 1 && (sbr & 7) == 0 && (N & 7) == 0 && j0 + GT <= N;
+  // B stored column by column ([N][K], contiguous along K): staged like A
+  const bool b_kvec = sbr == 1 && (sbc & 7) == 0 && (K & 7) == 0 && j0 + GT <= N;
   for (int k0 = 0; k0 < K; k0 += GK) {
     __syncthreads();
     const bool kfull = k0 + GK <= K;
@@ -49,7 +51,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
         As[r * GKP + c] = (gi < M && gk < K) ? A[(int64_t)gi * sar + (int64_t)gk * sac] : (uint16_t)0;
       }
     }
-    if (b_vec && kfull) {
+    if (b_kvec && kfull) {
+      const int r = tid >> 2, c = (tid & 3) * 8;  // 64 columns x 32 k: one 8-element vector per thread
+      *(uint4*)&Bs[r * GKP + c] = *(const uint4*)&B[(int64_t)(j0 + r) * sbc + k0 + c];
+    } else if (b_vec && kfull) {
       // 32 k x 64 columns: thread -> (k = tid / 8, 8 consecutive columns), stored transposed
       const int kk = tid >> 3, c = (tid & 7) * 8;
       const uint4 v = *(const uint4*)&B[(int64_t)(k0 + kk) * sbr + j0 + c];
@@ -93,6 +98,22 @@ hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sar, int64_
   dim3 g((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
   hipLaunchKernelGGL(gemm_bf16_kernel, g, dim3(256), 0, st, M, N, K, A, sar, sac, B, sbr, sbc, bias, relu, mask, Cf, Cb,
                      ldc);
+  return hipGetLastError();
+}
+
+// out[j][k] = in[k][j] for a [K][N] bf16 matrix, rows j in [N, n_pad) of out zero.
+__global__ void transpose_bf16_kernel(const uint16_t* __restrict__ in, int K, int N, int n_pad,
+                                      uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)n_pad * K) return;
+  const int j = (int)(i / K), k = (int)(i % K);
+  out[i] = j < N ? in[(int64_t)k * N + j] : (uint16_t)0;
+}
+
+hipError_t transpose_bf16(const uint16_t* in, int K, int N, int n_pad, uint16_t* out, hipStream_t st) {
+  const int64_t n = (int64_t)n_pad * K;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, K, N, n_pad, out);
   return hipGetLastError();
 }
 
@@ -218,6 +239,7 @@ hipError_t adam(float* w, const float* g, float* m, float* v, int64_t n, float l
 // index); budget = clamp(ceil(budget_scale (exp(z_R) - 1)), t_min, t_max). Rows whose
 // confidence is below tau get seeds[0] = none (fall back to ghost staging) and
 // the budget t_max.
+template <int NPL>
 __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ Z, int n, int R, int t, float tau,
                                                       const uint32_t* __restrict__ gmap, int t_min, int t_max,
                                                       float budget_scale,
@@ -228,45 +250,71 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
   if (b >= n) return;
   const int lane = threadIdx.x & 63;
   uint64_t* sel = sels + (threadIdx.x >> 6) * 256;
-  const float* z = Z + (int64_t)b * (R + 1);
+  const float* zg = Z + (int64_t)b * (R + 1);
+  // NPL > 0: the row's R logits are read once into registers (logit j = lane + 64 i in zr[i]); every pass below
+  // reads them through zv(), in the same per-lane order either way
+  float zr[NPL > 0 ? NPL : 1];
+  if constexpr (NPL > 0) {
+#pragma unroll
+    for (int i = 0; i < NPL; i++) {
+      const int j = lane + 64 * i;
+      zr[i] = j < R ? zg[j] : 0.f;
+    }
+  }
+  // f(j, z_j) for this lane's logits j = lane, lane + 64, ... < R, in increasing j
+  auto each = [&](auto&& f) {
+    if constexpr (NPL > 0) {
+#pragma unroll
+      for (int i = 0; i < NPL; i++)
+        if (lane + 64 * i < R) f(lane + 64 * i, zr[i]);
+    } else {
+      for (int j = lane; j < R; j += 64) f(j, zg[j]);
+    }
+  };
   float mx = -INFINITY;
-  for (int j = lane; j < R; j += 64) mx = fmaxf(mx, z[j]);
+  each([&](int, float v) { mx = fmaxf(mx, v); });
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
   float s = 0.f;
-  for (int j = lane; j < R; j += 64) s += expf(z[j] - mx);
+  each([&](int, float v) { s += expf(v - mx); });
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
   const float c = 1.f / s;
   // the t largest logits by (value desc, index asc), as ascending keys ((~ord(value)) << 32 | index)
-  auto key_of = [&](int j) {
-    const uint32_t fb = __float_as_uint(z[j]);
+  auto key_of = [&](int j, float v) {
+    const uint32_t fb = __float_as_uint(v);
     const uint32_t ord = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);  // order-preserving
     return ((uint64_t)(~ord) << 32) | (uint64_t)j;
   };
   // bound: the t-th smallest of the two smallest keys of every lane (a subset of the keys)
   uint64_t m2[2] = {~0ull, ~0ull};
-  for (int j = lane; j < R; j += 64) {
-    uint64_t x = key_of(j);
+  each([&](int j, float v) {
+    uint64_t x = key_of(j, v);
 #pragma unroll
     for (int i = 0; i < 2; i++) {
       const uint64_t lo = x < m2[i] ? x : m2[i];
       x = x < m2[i] ? m2[i] : x;
       m2[i] = lo;
     }
-  }
+  });
   bitonic_sort_regs<2>(m2);
   const uint64_t bound = shfl_u64(t > 64 ? m2[1] : m2[0], (t - 1) & 63);
   // collect the keys at or below the bound (at least t of them) and sort them
   int cnt = 0;
-  for (int j0 = 0; j0 < R; j0 += 64) {
-    const int j = j0 + lane;
-    const uint64_t key = j < R ? key_of(j) : ~0ull;
+  auto collect = [&](int j, float v) {
+    const uint64_t key = j < R ? key_of(j, v) : ~0ull;
     const bool pass = j < R && key <= bound;
     const uint64_t bm = __ballot(pass);
     const int pos = cnt + lanes_below(bm);
     if (pass && pos < 256) sel[pos] = key;
     cnt += __popcll(bm);
+  };
+  if constexpr (NPL > 0) {
+    // every lane takes part in each round's ballot (rounds beyond R carry no keys)
+#pragma unroll
+    for (int i = 0; i < NPL; i++) collect(lane + 64 * i, zr[i]);
+  } else {
+    for (int j0 = 0; j0 < R; j0 += 64) collect(j0 + lane, j0 + lane < R ? zg[j0 + lane] : 0.f);
   }
   __builtin_amdgcn_wave_barrier();
   uint64_t v[4];
@@ -278,10 +326,10 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
     uint64_t prev = 0;  // keys strictly increase
     for (int r = 0; r < t; r++) {
       uint64_t best = ~0ull;
-      for (int j = lane; j < R; j += 64) {
-        const uint64_t key = key_of(j);
+      each([&](int j, float v) {
+        const uint64_t key = key_of(j, v);
         if ((r == 0 || key > prev) && key < best) best = key;
-      }
+      });
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
         const uint64_t other = shfl_xor_u64(best, o);
@@ -299,7 +347,7 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
     seeds[(int64_t)b * t + lane] = (lane == 0 && c < tau) ? kNone : gmap[j];
   }
   if (lane == 0) {
-    const float yb = z[R];
+    const float yb = zg[R];
     float tb = ceilf(budget_scale * (expf(yb) - 1.f));
     if (!(tb >= (float)t_min)) tb = (float)t_min;
     if (tb > (float)t_max) tb = (float)t_max;
@@ -311,8 +359,16 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
 hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_t* gmap, int t_min, int t_max,
                    float budget_scale, uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(readout_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min,
-                     t_max, budget_scale, seeds, iters, conf, top_idx);
+  const dim3 g((unsigned)((n + 3) / 4));
+  if (R <= 1024)
+    hipLaunchKernelGGL(readout_kernel<16>, g, dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min, t_max, budget_scale,
+                       seeds, iters, conf, top_idx);
+  else if (R <= 4096)
+    hipLaunchKernelGGL(readout_kernel<64>, g, dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min, t_max, budget_scale,
+                       seeds, iters, conf, top_idx);
+  else
+    hipLaunchKernelGGL(readout_kernel<0>, g, dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min, t_max, budget_scale,
+                       seeds, iters, conf, top_idx);
   return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@ hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sar, int64_
                      int64_t sbc, const float* bias, int relu, const uint16_t* mask, float* Cf, uint16_t* Cb, int ldc,
                      hipStream_t st);
 hipError_t to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
+// out[j][k] = in[k][j] for a [K][N] bf16 matrix; rows N .. n_pad - 1 of out are zero.
+hipError_t transpose_bf16(const uint16_t* in, int K, int N, int n_pad, uint16_t* out, hipStream_t st);
 hipError_t gather_batch(const float* x, int d, const uint32_t* idx, int B, const int32_t* lab, const float* y,
                         uint16_t* xb, int32_t* lb, float* yb, hipStream_t st);
 hipError_t loss_grad(const float* Z, int B, int R, const int32_t* lab, const float* y, float lambda, uint16_t* dZ,
