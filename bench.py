@@ -87,22 +87,24 @@ def oracle_from_device(gx, X):
 
 
 def measured_traffic(workload, itopk, T, opts):
-    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE) per stage launch from the committed rocprofv3 record, when
+    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE) per stage launch from the committed rocprofv3 records, when
     the stage kernel's sources and the setting are those the counters were taken on; None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    st = rec["setting"]
-    same = (h.hexdigest() == rec["sources_sha256"] and workload == rec["workload"] and itopk == st["itopk"] and
-            T == st["T"] and opts.entry == st["entry"] and opts.search_width == st["search_width"] and
-            bool(opts.ghost_every_stage) == st["ghost_every_stage"])
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"] if same else None
+    recs = json.load(open(path))
+    for rec in recs if isinstance(recs, list) else [recs]:
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        st = rec["setting"]
+        if (h.hexdigest() == rec["sources_sha256"] and workload == rec["workload"] and itopk == st["itopk"] and
+                T == st["T"] and opts.entry == st["entry"] and opts.search_width == st["search_width"] and
+                bool(opts.ghost_every_stage) == st["ghost_every_stage"] and opts.t_seeds == st.get("t_seeds", 0)):
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
 
 
 TRAFFIC_SOURCES = ["paper_2507_17094_amd/csrc/search_impl.hpp", "paper_2507_17094_amd/csrc/search_f32.hip",
@@ -141,12 +143,20 @@ def record_traffic(args):
     rec = {"kernel": "stage_kernel<f32, 3 chunks per row>", "sources": TRAFFIC_SOURCES,
            "sources_sha256": h.hexdigest(), "workload": args.workload,
            "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
-                       "ghost_every_stage": bool(int(f[4]))},
+                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0},
            "fetch_bytes_per_launch": fetch_kib * 1024 * f_scale, "write_bytes_per_launch": write_kib * 1024 * w_scale,
            "fetch_scale": f_scale, "write_scale": w_scale, "launches": min(n_f, n_w)}
+    # one record per setting: a record of the same setting is replaced, records of other settings are kept while
+    # the sources they were taken on are unchanged
     path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_traffic.json")
+    recs = []
+    if os.path.exists(path):
+        old = json.load(open(path))
+        recs = [r for r in (old if isinstance(old, list) else [old])
+                if r.get("sources_sha256") == rec["sources_sha256"] and r.get("setting") != rec["setting"]]
+    recs.append(rec)
     with open(path, "w") as fh:
-        json.dump(rec, fh, indent=1)
+        json.dump(recs, fh, indent=1)
     print(json.dumps(rec), flush=True)
 
 
@@ -476,7 +486,8 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle leg (0 = all)")
     ap.add_argument("--plain", type=int, default=1, help="also sweep the plain (unsharded, random-entry) search")
-    ap.add_argument("--fixed", default="", help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage[,ghost_iters]")
+    ap.add_argument("--fixed", default="",
+                    help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage[,ghost_iters[,t_seeds]]")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the reference for the HBM "
                          "byte counters")
@@ -544,7 +555,7 @@ def main():
     def run(ix, itopk, T, opts, counters=False):
         return ix.search(Qd, k, itopk, T, opts, counters=counters)
 
-    def timed(ix, itopk, T, opts, reps=2):
+    def timed(ix, itopk, T, opts, reps=4):
         run(ix, itopk, T, opts)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -576,13 +587,15 @@ def main():
                                                                 ghost_every_stage=True)),
                        (f"gsdense-all+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r,
                                                                      ghost_every_stage=True))]
-    tuned_opts += [("gs-all+dgs r2 Tg4", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2,
+    tuned_opts += [("gsdense-all+dgs r2 t8", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=2,
+                                                                 ghost_every_stage=True, t_seeds=8)),
+                   ("gs-all+dgs r2 Tg4", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2,
                                                              ghost_every_stage=True, ghost_iters=4)),
                    ("gs+dgs r2", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2))]
     if args.fixed:
         f = args.fixed.split(",")
         fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])),
-                                 ghost_iters=int(f[5]) if len(f) > 5 else 8)
+                                 ghost_iters=int(f[5]) if len(f) > 5 else 8, t_seeds=int(f[6]) if len(f) > 6 else 0)
         ids, _ = run(gx, int(f[0]), int(f[1]), fo)
         torch.cuda.synchronize()
         best = dict(form="tuned", variant="fixed", itopk=int(f[0]), T=int(f[1]), opts=fo,
@@ -648,6 +661,7 @@ def main():
                                f"ghost ratio {W['ghost_ratio']}, direction filter", "nq": nq, "k": k,
                    "itopk": itopk, "max_iters": T, "entry": opts.entry, "dgs": bool(opts.dgs),
                    "search_width": opts.search_width, "ghost_every_stage": bool(opts.ghost_every_stage),
+                   "t_seeds": opts.t_seeds or min(opts.ghost_itopk, itopk),
                    "recall@10": best["recall"], "distance_accumulation": "f64 of f32 inputs"},
         "latency_ms": {"batch_p50": float(np.percentile(step_ms, 50)), "batch_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -672,7 +686,7 @@ def main():
         ox = oracle_from_device(gx, X)
         m = args.cpu_sample or nq
         okw = dict(k=k, l=itopk, T=T, entry=opts.entry, dgs_on=opts.dgs, l_g=opts.ghost_itopk, T_g=opts.ghost_iters,
-                   r=opts.search_width, ghost_every_stage=opts.ghost_every_stage)
+                   r=opts.search_width, ghost_every_stage=opts.ghost_every_stage, t_seeds=opts.t_seeds or None)
         t0 = time.perf_counter()
         oi, od, _ = oracle.search(ox, Q[:m], **okw)
         t_cpu = time.perf_counter() - t0
