@@ -297,8 +297,15 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
       m2[i] = lo;
     }
   });
-  bitonic_sort_regs<2>(m2);
-  const uint64_t bound = shfl_u64(t > 64 ? m2[1] : m2[0], (t - 1) & 63);
+  uint64_t bound;
+  if (t <= 32) {
+    // the t-th smallest of the 64 lane minima (a subset of the keys, so at least t keys are at or below it)
+    const uint64_t srt = bitonic_sort_u64<64>(m2[0]);
+    bound = shfl_u64(srt, t - 1);
+  } else {
+    bitonic_sort_regs<2>(m2);
+    bound = shfl_u64(t > 64 ? m2[1] : m2[0], (t - 1) & 63);
+  }
   // collect the keys at or below the bound (at least t of them) and sort them
   int cnt = 0;
   auto collect = [&](int j, float v) {
@@ -320,7 +327,8 @@ __global__ __launch_bounds__(256) void readout_kernel(const float* __restrict__ 
   uint64_t v[4];
 #pragma unroll
   for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < cnt && r * 64 + lane < 256 ? sel[r * 64 + lane] : ~0ull;
-  bitonic_sort_regs<4>(v);
+  if (cnt <= 64) v[0] = bitonic_sort_u64<64>(v[0]);  // the usual case: one register
+  else bitonic_sort_regs<4>(v);
   if (cnt > 256) {
     // more than 256 keys at the bound: t rounds of argmax instead
     uint64_t prev = 0;  // keys strictly increase
