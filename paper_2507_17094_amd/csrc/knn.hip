@@ -848,9 +848,9 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
       for (int j = 0; j < 16; j++) {
         const float v = qr[j] + gcol - 2.f * acc[j];
         uint32_t u = (uint32_t)max(__float_as_int(v), 0);
-        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, false));
-        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, false));
-        u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xF, 0xF, false));
+        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0xB1, 0xF, 0xF, false));
+        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x4E, 0xF, 0xF, false));
+        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x141, 0xF, 0xF, false));
         if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
       }
     } else {
@@ -941,6 +941,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
     nb.store(Bh, Bl, sr, sc0);
     nb.load(Gh, Gl, cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr, sc0);  // (the last tile reloads itself)
     __syncthreads();
+    // the tile's column norms, loaded while the products run
+    float gcols[2];
+#pragma unroll
+    for (int c = 0; c < 2; c++) gcols[c] = gn[cb + tt * 64 + 32 * c + col];
     f32x16_t acc[2];
 #pragma unroll
     for (int c = 0; c < 2; c++)
@@ -961,16 +965,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
     for (int c = 0; c < 2; c++) {
       const int wc = 32 * c;
       const int jc = tt * 64 + wc + col;  // ghost index of this lane's column
-      const float gcol = gn[cb + jc];
+      const float gcol = gcols[c];
       if constexpr (MODE == 0) {
         float* mrow = M + (rl0 + wr + 4 * h) * mcols + (cb - mcol0 + tt * 64 + wc) / DG + (col >> 3);
 #pragma unroll
         for (int j = 0; j < 16; j++) {
           const float v = qr[j] + gcol - 2.f * acc[c][j];
           uint32_t u = (uint32_t)max(__float_as_int(v), 0);
-          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, false));
-          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, false));
-          u = min(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xF, 0xF, false));
+          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0xB1, 0xF, 0xF, false));
+          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x4E, 0xF, 0xF, false));
+          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x141, 0xF, 0xF, false));
           if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
         }
       } else {
