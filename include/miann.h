@@ -154,6 +154,20 @@ miann_status miann_index_info(const miann_index* idx, int32_t* num_shards, int64
                               int32_t* degree, int32_t* store_dtype);
 void miann_index_free(miann_index* idx);
 
+/* Writes an index to a file at `path` (host file I/O; synchronises the
+ * device): per shard the originals, graph, global ids, inter-shard map, ghost
+ * ids and ghost graph, with the index's dimensions and types. EINVAL if the
+ * file cannot be opened, EDEVICE if a copy or a write fails. */
+miann_status miann_index_save(const miann_index* idx, const char* path);
+/* Reads a file written by miann_index_save and imports it as with
+ * miann_index_import (the store, sign table and dense ghost arrays are
+ * rebuilt on the device), so the loaded index searches exactly like the saved
+ * one. EINVAL for a missing, foreign, truncated or inconsistent file (all
+ * checked on the host before any device allocation), EDEVICE if a device
+ * allocation or copy fails; on any error *out is left unchanged.
+ * Synchronises `stream`. */
+miann_status miann_index_load(const char* path, void* stream, miann_index** out);
+
 /* ------------------------------------------------------------------------ */
 /* Search                                                                    */
 /* ------------------------------------------------------------------------ */

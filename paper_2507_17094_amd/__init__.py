@@ -29,7 +29,7 @@ EXPORTS = [
     "miann_version", "miann_nearest_ghost", "miann_predictor_create", "miann_predictor_free",
     "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step", "miann_predictor_train",
     "miann_predictor_predict", "miann_server_config_default", "miann_server_create", "miann_server_submit",
-    "miann_server_wait", "miann_server_get_stats", "miann_server_destroy",
+    "miann_server_wait", "miann_server_get_stats", "miann_server_destroy", "miann_index_save", "miann_index_load",
 ]
 
 
@@ -107,6 +107,8 @@ def load():
     L.miann_index_import.argtypes = [C.POINTER(ShardDesc), i32, i32, i32, i32, i32, i32, i32, vp, C.POINTER(vp)]
     L.miann_index_shard.argtypes = [vp, i32, C.POINTER(ShardView)]
     L.miann_index_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.miann_index_save.argtypes = [vp, C.c_char_p]
+    L.miann_index_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
     L.miann_index_free.argtypes = [vp]
     L.miann_index_free.restype = None
     L.miann_search_params_default.argtypes = [C.POINTER(SearchParams)]
@@ -238,6 +240,19 @@ class Index:
         S, n, d, deg, st = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().miann_index_info(self._h, C.byref(S), C.byref(n), C.byref(d), C.byref(deg), C.byref(st)))
         return dict(num_shards=S.value, n=n.value, d=d.value, degree=deg.value, store_dtype=st.value)
+
+    def save(self, path: str) -> None:
+        """Writes the index to a file (originals, graphs, maps and ghost shards)."""
+        _check(load().miann_index_save(self._h, os.fsencode(path)))
+
+    @staticmethod
+    def load(path: str, stream=None) -> "Index":
+        """Reads a file written by save(); the store, sign table and dense ghost arrays are rebuilt."""
+        h = C.c_void_p()
+        _check(load().miann_index_load(os.fsencode(path), _stream_ptr(stream), C.byref(h)))
+        v = ShardView()
+        _check(load().miann_index_shard(h, 0, C.byref(v)))
+        return Index(h.value, v.in_dtype)
 
     def shard(self, s: int) -> ShardView:
         v = ShardView()

@@ -43,3 +43,31 @@ def test_version_and_host_side_validation():
     assert rc == 1 and b"null index" in L.miann_last_error()
     rc = L.miann_index_info(None, None, None, None, None, None)
     assert rc == 1
+
+
+@pytest.mark.skipif(not os.path.exists(miann.LIB_PATH), reason="libmiann.so not built")
+def test_index_file_errors_are_host_side(tmp_path):
+    """Saving a null index and loading a missing, foreign, truncated or oversized file fail
+    with EINVAL before any device call."""
+    L = miann.load()
+    h = ctypes.c_void_p()
+    assert L.miann_index_save(None, str(tmp_path / "x").encode()) == 1
+    assert L.miann_index_load(str(tmp_path / "missing").encode(), None, ctypes.byref(h)) == 1
+    assert b"cannot open" in L.miann_last_error()
+    foreign = tmp_path / "foreign"
+    foreign.write_bytes(b"NOTANIDX" + bytes(64))
+    assert L.miann_index_load(str(foreign).encode(), None, ctypes.byref(h)) == 1
+    assert b"not an index file" in L.miann_last_error()
+    import struct
+    hdr = b"MIANNIX1" + struct.pack("<I7i", 1, 1, 8, 0, 0, 4, 4, 0)
+    # a shard that claims more rows than the file holds
+    big = tmp_path / "big"
+    big.write_bytes(hdr + struct.pack("<qqi", 1 << 40, 0, 0))
+    assert L.miann_index_load(str(big).encode(), None, ctypes.byref(h)) == 1
+    assert b"bad shard 0 header" in L.miann_last_error()
+    # a shard whose arrays stop early
+    short = tmp_path / "short"
+    short.write_bytes(hdr + struct.pack("<qqi", 4, 0, 0) + bytes(4 * 8 * 4 + 8))
+    assert L.miann_index_load(str(short).encode(), None, ctypes.byref(h)) == 1
+    assert b"truncated" in L.miann_last_error()
+    assert not h.value
