@@ -1061,12 +1061,22 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   const int64_t ng = (R + DG - 1) / DG;
   const float* m = M + rl * (ncols / DG) + (off[s] - col0) / DG;
   // float bits of non-negative values order like the values; 0xFFFFFFFF = none
+  // all of a lane's loads of one round are issued before the first is consumed (one memory latency per round)
+  constexpr int U = 8;
   uint32_t v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
-  for (int64_t g = lane; g < ng; g += 64) {
-    const uint32_t x = __float_as_uint(m[g]);
-    const uint32_t lo = x < v0 ? x : v0;
-    v1 = x < v0 ? v0 : (x < v1 ? x : v1);
-    v0 = lo;
+  for (int64_t g0 = lane; g0 < ng; g0 += 64 * U) {
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t g = g0 + (int64_t)u * 64;
+      x[u] = g < ng ? __float_as_uint(m[g]) : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t lo = x[u] < v0 ? x[u] : v0;
+      v1 = x[u] < v0 ? v0 : (x[u] < v1 ? x[u] : v1);
+      v0 = lo;
+    }
   }
   uint32_t b;
   if (kp <= 32) {
