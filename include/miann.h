@@ -199,6 +199,10 @@ typedef struct {
   float* phase_ms;          /* host [2 + S] or NULL: when set, the call records HIP events around
                                its launches, synchronises `stream` and writes the milliseconds of
                                [dense ghost entry, stage 0 .. stage S-1, shard merge] */
+  void* const* phase_events;/* host [4] hipEvent_t (each may be NULL) or NULL: recorded on `stream` before the
+                               ghost entry, before stage 0, after the last stage and after the shard merge,
+                               without synchronising, so that back-to-back calls stay pipelined; the caller
+                               reads the intervals with hipEventElapsedTime once the events completed */
 } miann_search_params;
 
 /* Fills the documented defaults: r = 1, n_init = degree, random entry,
@@ -315,7 +319,7 @@ void miann_server_config_default(miann_server_config* cfg);
 miann_status miann_server_create(const miann_index* idx, const miann_server_config* cfg, miann_server** out);
 /* Queues one request: queries_host [nq][d] host rows of the index's input type (copied by the call),
  * k, itopk, max_iters and parameters as for miann_search (sp may be NULL; its qkeys, seeds,
- * max_iters_per_query and phase_ms must be NULL). Validates like miann_search; a request larger than
+ * max_iters_per_query, phase_ms and phase_events must be NULL). Validates like miann_search; a request larger than
  * the server's limits is EINVAL. Thread-safe. *ticket identifies the request. */
 miann_status miann_server_submit(miann_server* srv, const void* queries_host, int64_t nq, int32_t k, int32_t itopk,
                                  int32_t max_iters, const miann_search_params* sp, uint64_t* ticket);

@@ -68,7 +68,8 @@ class SearchParams(C.Structure):
                 ("rerank_mult", C.c_int32), ("stop_on_no_change", C.c_int32), ("hash_log2", C.c_int32),
                 ("n_seeds", C.c_int32), ("ghost_every_stage", C.c_int32), ("reserved", C.c_int32),
                 ("seed", C.c_uint64), ("qkeys", C.c_void_p), ("seeds", C.c_void_p),
-                ("max_iters_per_query", C.c_void_p), ("phase_ms", C.c_void_p)]
+                ("max_iters_per_query", C.c_void_p), ("phase_ms", C.c_void_p),
+                ("phase_events", C.c_void_p)]
 
 
 class ServerConfig(C.Structure):
@@ -307,10 +308,12 @@ class Index:
     # -- search -----------------------------------------------------------
     def search(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None,
                qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None,
-               phase_ms=None):
+               phase_ms=None, phase_events=None):
         """Returns (ids [nq,k] int32 view of uint32, dists [nq,k] float32|int32[, counters [nq,8] int64]).
         phase_ms: optional list that receives per-launch milliseconds [dense, stage 0..S-1, merge]
-        (the call then synchronises the stream)."""
+        (the call then synchronises the stream).
+        phase_events: optional 4 raw hipEvent_t handles (ints or None), recorded before the ghost entry,
+        before stage 0, after the last stage and after the merge; the call does not wait for them."""
         torch = _torch()
         for n_, t_ in (("queries", queries), ("qkeys", qkeys), ("seeds", seeds), ("max_iters_per_query", max_iters_per_query)):
             _require_cuda(t_, n_)
@@ -328,6 +331,12 @@ class Index:
         if phase_ms is not None:
             tbuf = (C.c_float * (2 + self.info()["num_shards"]))()
             p.phase_ms = C.cast(tbuf, C.c_void_p)
+        evbuf = None
+        if phase_events is not None:
+            if len(phase_events) != 4:
+                raise ValueError("phase_events needs 4 event handles")
+            evbuf = (C.c_void_p * 4)(*[e or None for e in phase_events])
+            p.phase_events = C.cast(evbuf, C.c_void_p)
         _check(load().miann_search(self._h, queries.data_ptr(), nq, k, itopk, max_iters, C.byref(p), ids.data_ptr(),
                                    dists.data_ptr(), _ptr(ctr), _stream_ptr(stream)))
         if tbuf is not None:

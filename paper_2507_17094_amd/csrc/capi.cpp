@@ -530,6 +530,14 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   auto mark = [&](int phase, int end) {
     if (!ev.empty()) hipEventRecord(ev[2 * phase + end], st);
   };
+  // the caller's events: recorded in stream order, never waited on here
+  auto mark_caller = [&](int i) {
+    if (!sp.phase_events || !sp.phase_events[i]) return;
+    const hipError_t e = hipEventRecord((hipEvent_t)sp.phase_events[i], st);
+    if (e != hipSuccess && rc == MIANN_OK)
+      rc = fail(MIANN_EINVAL, "miann_search: phase_events[%d]: %s", i, hipGetErrorString(e));
+  };
+  mark_caller(0);
   if (sp.entry == MIANN_ENTRY_GHOST_DENSE) {
     a.dense = (const uint64_t*)(sb + off_dense);
     mark(0, 0);
@@ -550,17 +558,20 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
       a.out_ids = ids;
       a.out_d = dists;
     }
+    if (t == 0) mark_caller(1);
     mark(1 + t, 0);
     hipError_t e = launch_stage(ix->store_dtype, cpl, a, st);
     mark(1 + t, 1);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: stage %d launch: %s", t, hipGetErrorString(e));
   }
+  if (rc == MIANN_OK) mark_caller(2);
   if (rc == MIANN_OK && ix->S > 1) {
     mark(nph - 1, 0);
     hipError_t e = launch_merge((const uint64_t*)(sb + off_stage), nq, ix->S, k, ix->store_dtype == MIANN_U8, ids, dists, st);
     mark(nph - 1, 1);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: merge launch: %s", hipGetErrorString(e));
   }
+  if (rc == MIANN_OK) mark_caller(3);
   if (scratch) hipFreeAsync(scratch, st);
   if (!ev.empty()) {
     hipError_t e = hipStreamSynchronize(st);

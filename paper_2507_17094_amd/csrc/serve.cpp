@@ -330,7 +330,7 @@ miann_status miann_server_submit(miann_server* s, const void* queries, int64_t n
                       (long long)nq);
   auto r = std::make_shared<Request>();
   if (sp) r->sp = *sp; else miann_search_params_default(&r->sp);
-  if (r->sp.qkeys || r->sp.seeds || r->sp.max_iters_per_query || r->sp.phase_ms)
+  if (r->sp.qkeys || r->sp.seeds || r->sp.max_iters_per_query || r->sp.phase_ms || r->sp.phase_events)
     return miann_fail(MIANN_EINVAL, "miann_server_submit: per-query device arrays are not accepted by the server");
   // validate the shape with a zero-query search (no device work)
   miann_status rc = miann_search(s->idx, nullptr, 0, k, itopk, max_iters, &r->sp, nullptr, nullptr, nullptr, nullptr);

@@ -167,6 +167,38 @@ def test_batch_independence_and_query_keys(small):
     assert np.array_equal(full[1].cpu().numpy()[sub], part[1].cpu().numpy())
 
 
+def test_phase_events_pipelined(small):
+    """Caller events recorded in stream order around the entry, the stages and the merge: three
+    back-to-back calls without a wait return the results of a plain call, and the intervals are
+    ordered and non-negative."""
+    import ctypes
+    X, Q, ox, gx = small
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    evs = []
+    for _ in range(12):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e.value)
+    opts = miann.SearchOptions(dgs=True, entry="ghost_dense", search_width=2)
+    qd = dev(Q)
+    ref = gx.search(qd, K, 64, 40, opts)
+    outs = [gx.search(qd, K, 64, 40, opts, phase_events=evs[4 * i:4 * i + 4]) for i in range(3)]
+    torch.cuda.synchronize()
+    for ids, dists in outs:
+        assert torch.equal(ids, ref[0]) and torch.equal(dists, ref[1])
+    ms = ctypes.c_float()
+    for i in range(3):
+        for j in range(3):
+            assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[4 * i + j], evs[4 * i + j + 1]) == 0
+            assert ms.value >= 0.0
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[4 * i], evs[4 * i + 3]) == 0 and ms.value > 0.0
+    for e in evs:
+        hip.hipEventDestroy(e)
+
+
 def test_per_query_budget_and_seed_entry(small):
     X, Q, ox, gx = small
     rng = np.random.default_rng(3)
