@@ -722,6 +722,45 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
   return hipGetLastError();
 }
 
+// Query preparation of the dense entry in one pass, one wave per row: the hi/lo bf16 split and f32 norm over dk
+// columns (as split_rows_kernel computes them from the f32 row padded to dk), and the exact-distance copy of the
+// row padded to d_pad (f32, or u8 for u8 queries).
+__global__ __launch_bounds__(256) void dense_queries_kernel(const void* __restrict__ q, int q_dt, int64_t nq, int d,
+                                                            int dk, int d_pad, uint16_t* __restrict__ hi,
+                                                            uint16_t* __restrict__ lo, float* __restrict__ norm,
+                                                            void* __restrict__ qraw) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= nq) return;
+  const int lane = threadIdx.x & 63;
+  const int cmax = dk > d_pad ? dk : d_pad;
+  double s = 0.0;
+  for (int c = lane; c < cmax; c += 64) {
+    float v = 0.f;
+    uint8_t b = 0;
+    if (c < d) {
+      if (q_dt == DT_U8) {
+        b = ((const uint8_t*)q)[r * d + c];
+        v = (float)b;
+      } else {
+        v = ((const float*)q)[r * d + c];
+      }
+    }
+    if (c < dk) {
+      const uint16_t h = f32_to_bf16(v);
+      hi[r * dk + c] = h;
+      lo[r * dk + c] = f32_to_bf16(v - bf16_to_f32(h));
+      s += (double)v * (double)v;
+    }
+    if (c < d_pad) {
+      if (q_dt == DT_U8) ((uint8_t*)qraw)[r * d_pad + c] = b;
+      else ((float*)qraw)[r * d_pad + c] = v;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += xor_lane_f64(s, o);
+  if (lane == 0) norm[r] = (float)s;
+}
+
 constexpr int DG = 8;     // columns per group minimum (pass 1)
 constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
 
@@ -1303,32 +1342,23 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   if (nq == 0) return hipSuccess;
   const int qdt = store_dt == DT_U8 ? DT_U8 : DT_F32;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t sz_qf = al((size_t)nq * dk * 4), sz_qb = al((size_t)nq * dk * 2), sz_qn = al((size_t)nq * 4);
+  const size_t sz_qb = al((size_t)nq * dk * 2), sz_qn = al((size_t)nq * 4);
   const size_t sz_qraw = al((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4));
   const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
-  const size_t total = sz_qf + 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
+  const size_t total = 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
   char* buf = nullptr;
   hipError_t e = pool_malloc_async((void**)&buf, total, st);
   if (e != hipSuccess) return e;
   char* p = buf;
-  float* qf = (float*)p; p += sz_qf;
   uint16_t* qh = (uint16_t*)p; p += sz_qb;
   uint16_t* ql = (uint16_t*)p; p += sz_qb;
   float* qn = (float*)p; p += sz_qn;
   void* qraw = p; p += sz_qraw;
   uint32_t* list = (uint32_t*)p; p += sz_list;
   int* qcnt = (int*)p;
-  e = queries_to_f32(queries, qdt, nq, d, dk, qf, st);
-  if (e == hipSuccess) e = split_rows(qf, nq, nq, dk, qh, ql, qn, st);
-  if (e == hipSuccess) {
-    if (qdt == DT_U8) {
-      hipLaunchKernelGGL(pad_u8_kernel, dim3((unsigned)((nq * d_pad + 255) / 256)), dim3(256), 0, st,
-                         (const uint8_t*)queries, nq, d, d_pad, (uint8_t*)qraw);
-      e = hipGetLastError();
-    } else {
-      e = queries_to_f32(queries, DT_F32, nq, d, d_pad, (float*)qraw, st);
-    }
-  }
+  hipLaunchKernelGGL(dense_queries_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, queries, qdt, nq, d, dk,
+                     d_pad, qh, ql, qn, qraw);
+  e = hipGetLastError();
   // (rows, shard range) passes: every query against every shard, or each shard against the queries starting there
   const int npass = start_only ? S : 1;
   for (int ps = 0; ps < npass && e == hipSuccess; ps++) {
