@@ -363,6 +363,7 @@ miann_status miann_index_import(const miann_shard_desc* shards, int32_t S, int32
   }
   if (rc == MIANN_OK) rc = build_dense_ghosts(ix, st);
   if (rc != MIANN_OK) {
+    hipStreamSynchronize(st);  // queued copies and kernels may still use the index's buffers
     delete ix;
     return rc;
   }
@@ -538,7 +539,7 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
       rc = fail(MIANN_EINVAL, "miann_search: phase_events[%d]: %s", i, hipGetErrorString(e));
   };
   mark_caller(0);
-  if (sp.entry == MIANN_ENTRY_GHOST_DENSE) {
+  if (rc == MIANN_OK && sp.entry == MIANN_ENTRY_GHOST_DENSE) {
     a.dense = (const uint64_t*)(sb + off_dense);
     mark(0, 0);
     // dense seeds are needed for the start shard only, unless every stage takes a ghost entry

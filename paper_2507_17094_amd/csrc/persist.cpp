@@ -179,8 +179,10 @@ miann_status miann_index_load(const char* path, void* stream, miann_index** out)
     }
     if (!ok) return miann_fail(MIANN_EDEVICE, "miann_index_load: reading %s or copying it to the device failed", path);
   }
-  // the import synchronises the stream, so the staging buffers can be freed on return
-  return miann_index_import(desc.data(), S, d, in_dt, store_dt, degree, deg_g, has_sign, stream, out);
+  const miann_status rc = miann_index_import(desc.data(), S, d, in_dt, store_dt, degree, deg_g, has_sign, stream, out);
+  // nothing queued may still read the staging buffers when they are freed on return
+  hipStreamSynchronize((hipStream_t)stream);
+  return rc;
 }
 
 }  // extern "C"
