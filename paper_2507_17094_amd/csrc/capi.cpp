@@ -517,7 +517,14 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     off_dense = total;
     total += (size_t)nq * ix->S * t_seeds * 8;
   }
-  if (total) HIP_TRY(pool_malloc_async(&scratch, total, st));
+  ScratchLease lease;
+  if (total) HIP_TRY(scratch_lease(kSlotSearch, total, st, &lease));
+  struct LeaseGuard {
+    const ScratchLease& l;
+    hipStream_t st;
+    ~LeaseGuard() { scratch_release(kSlotSearch, l, st); }
+  } lease_guard{lease, st};
+  scratch = lease.p;
   char* sb = (char*)scratch;
   miann_status rc = MIANN_OK;
   // optional timing: events around [dense, stage 0..S-1, merge]
@@ -573,7 +580,6 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: merge launch: %s", hipGetErrorString(e));
   }
   if (rc == MIANN_OK) mark_caller(3);
-  if (scratch) hipFreeAsync(scratch, st);
   if (!ev.empty()) {
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess && rc == MIANN_OK) rc = fail(MIANN_EDEVICE, "miann_search: %s", hipGetErrorString(e));

@@ -1346,9 +1346,10 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   const size_t sz_qraw = al((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4));
   const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
   const size_t total = 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
-  char* buf = nullptr;
-  hipError_t e = pool_malloc_async((void**)&buf, total, st);
+  ScratchLease lq;
+  hipError_t e = scratch_lease(kSlotDenseQueries, total, st, &lq);
   if (e != hipSuccess) return e;
+  char* buf = (char*)lq.p;
   char* p = buf;
   uint16_t* qh = (uint16_t*)p; p += sz_qb;
   uint16_t* ql = (uint16_t*)p; p += sz_qb;
@@ -1385,7 +1386,9 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     chunk = chunk < brows ? brows : chunk / brows * brows;
     if (chunk > (nq + brows - 1) / brows * brows) chunk = (nq + brows - 1) / brows * brows;
     char* wb = nullptr;
-    e = pool_malloc_async((void**)&wb, (size_t)chunk * per_row + 4096, st);
+    ScratchLease lw;
+    e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
+    wb = (char*)lw.p;
     if (e != hipSuccess) break;
     uint32_t* cmask = (uint32_t*)wb;
     float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
@@ -1427,9 +1430,9 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       }
       e = hipGetLastError();
     }
-    hipFreeAsync(wb, st);
+    scratch_release(kSlotDenseWork, lw, st);
   }
-  hipFreeAsync(buf, st);
+  scratch_release(kSlotDenseQueries, lq, st);
   return e;
 }
 

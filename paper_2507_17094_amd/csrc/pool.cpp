@@ -2,7 +2,9 @@
 #include "pool.hpp"
 
 #include <cstdint>
+#include <map>
 #include <mutex>
+#include <tuple>
 
 namespace miann {
 
@@ -25,6 +27,59 @@ hipMemPool_t lib_pool() {
     pools[dev] = p;
   }
   return pools[dev];
+}
+
+namespace {
+struct Kept {
+  void* p = nullptr;
+  size_t cap = 0;
+  bool busy = false;
+};
+std::mutex kept_mu;
+std::map<std::tuple<int, hipStream_t, int>, Kept> kept;
+}  // namespace
+
+hipError_t scratch_lease(int slot, size_t bytes, hipStream_t st, ScratchLease* out) {
+  out->p = nullptr;
+  out->kept = false;
+  if (bytes == 0) bytes = 16;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lk(kept_mu);
+    Kept& k = kept[std::make_tuple(dev, st, slot)];
+    if (!k.busy) {
+      if (k.cap < bytes) {
+        // a larger block: the old one goes back to the pool in stream order
+        if (k.p) hipFreeAsync(k.p, st);
+        k.p = nullptr;
+        k.cap = 0;
+        const size_t cap = bytes + bytes / 4;
+        void* p = nullptr;
+        const hipError_t e = pool_malloc_async(&p, cap, st);
+        if (e != hipSuccess) return e;
+        k.p = p;
+        k.cap = cap;
+      }
+      k.busy = true;
+      out->p = k.p;
+      out->kept = true;
+      return hipSuccess;
+    }
+  }
+  return pool_malloc_async(&out->p, bytes, st);
+}
+
+void scratch_release(int slot, const ScratchLease& l, hipStream_t st) {
+  if (!l.p) return;
+  if (!l.kept) {
+    hipFreeAsync(l.p, st);
+    return;
+  }
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(kept_mu);
+  kept[std::make_tuple(dev, st, slot)].busy = false;
 }
 
 }  // namespace miann

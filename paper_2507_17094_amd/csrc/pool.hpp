@@ -20,4 +20,17 @@ inline hipError_t pool_malloc_async(T** p, size_t bytes, hipStream_t st) {
   return hipMallocFromPoolAsync((void**)p, bytes, pool, st);
 }
 
+// Scratch that stays with a stream. The hot paths (search scratch, dense entry buffers) lease one block per
+// (device, stream, slot); a released block is kept for the next lease on the same stream, whose work the stream
+// orders after the previous user's, so back-to-back calls skip the stream-ordered allocator and the markers it
+// queues. A lease whose block is held by another host thread on the same stream gets a block of its own from the
+// pool instead. A kept block grows to the largest size asked for and is held until the process ends.
+enum ScratchSlot { kSlotSearch = 0, kSlotDenseQueries = 1, kSlotDenseWork = 2, kNumSlots = 3 };
+struct ScratchLease {
+  void* p = nullptr;
+  bool kept = false;  // the stream's kept block (else a block of its own)
+};
+hipError_t scratch_lease(int slot, size_t bytes, hipStream_t st, ScratchLease* out);
+void scratch_release(int slot, const ScratchLease& l, hipStream_t st);
+
 }  // namespace miann
