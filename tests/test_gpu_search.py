@@ -199,6 +199,31 @@ def test_phase_events_pipelined(small):
         hip.hipEventDestroy(e)
 
 
+def test_concurrent_calls_on_one_stream(small):
+    """Host threads searching on the same stream at once: a call that finds the stream's kept scratch
+    held by another thread takes its own block, so every call returns the single-call result."""
+    import threading
+    X, Q, ox, gx = small
+    opts = miann.SearchOptions(dgs=True, entry="ghost_dense", search_width=2)
+    qd = dev(Q)
+    ref = gx.search(qd, K, 64, 40, opts)
+    torch.cuda.synchronize()
+    out = [None] * 4
+
+    def work(i):
+        out[i] = [gx.search(qd, K, 64, 40, opts) for _ in range(3)]
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    for calls in out:
+        for ids, dists in calls:
+            assert torch.equal(ids, ref[0]) and torch.equal(dists, ref[1])
+
+
 def test_per_query_budget_and_seed_entry(small):
     X, Q, ox, gx = small
     rng = np.random.default_rng(3)
