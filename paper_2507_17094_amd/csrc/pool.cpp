@@ -54,7 +54,9 @@ hipError_t scratch_lease(int slot, size_t bytes, hipStream_t st, ScratchLease* o
         if (k.p) hipFreeAsync(k.p, st);
         k.p = nullptr;
         k.cap = 0;
-        const size_t cap = bytes + bytes / 4;
+        // power-of-two sizes: a stream whose requests grow reallocates a few times, not at every new maximum
+        size_t cap = 65536;
+        while (cap < bytes) cap <<= 1;
         void* p = nullptr;
         const hipError_t e = pool_malloc_async(&p, cap, st);
         if (e != hipSuccess) return e;

@@ -24,7 +24,7 @@ inline hipError_t pool_malloc_async(T** p, size_t bytes, hipStream_t st) {
 // (device, stream, slot); a released block is kept for the next lease on the same stream, whose work the stream
 // orders after the previous user's, so back-to-back calls skip the stream-ordered allocator and the markers it
 // queues. A lease whose block is held by another host thread on the same stream gets a block of its own from the
-// pool instead. A kept block grows to the largest size asked for and is held until the process ends.
+// pool instead. A kept block grows in powers of two to cover the largest size asked for and is held until the process ends.
 enum ScratchSlot { kSlotSearch = 0, kSlotDenseQueries = 1, kSlotDenseWork = 2, kNumSlots = 3 };
 struct ScratchLease {
   void* p = nullptr;
