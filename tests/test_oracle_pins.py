@@ -508,3 +508,188 @@ def test_degenerate_inputs():
     assert np.all(ctr[:, 2] == 0) and np.all(ds[:, 0] >= 0)
     with pytest.raises(ValueError):
         oracle.search(ix, X[:3], k=9, l=8, T=5)
+
+
+# ---------------------------------------------------------------------------
+# Eq. 2 against its exact value. The oracle's distance is the float32
+# difference of each coordinate, squared and summed in double, rounded once to
+# float. Relative to the exact sum of (q_i - x_i)^2 that differs by at most
+#   2^-23 + 2^-48   (each difference rounded to float, then squared)
+# + d * 2^-53       (the double sum of non-negative terms)
+# + 2^-24           (the final rounding to float),
+# which the bound below rounds up to 3 * 2^-24 + d * 2^-52.
+# ---------------------------------------------------------------------------
+def _exact_sq_l2(q, x):
+    from fractions import Fraction
+    return sum((Fraction(float(a)) - Fraction(float(b))) ** 2 for a, b in zip(q, x))
+
+
+@pytest.mark.parametrize("d,scale", [(7, 1.0), (96, 0.25), (128, 30.0), (256, 1e-3), (300, 1e4)])
+def test_distance_within_rounding_bound_of_exact_eq2(d, scale):
+    rng = np.random.default_rng(d)
+    X = (rng.standard_normal((40, d)) * scale).astype(np.float32)
+    q = (rng.standard_normal(d) * scale).astype(np.float32)
+    X[0] = q                      # distance 0 exactly
+    X[1] = q + np.float32(scale)  # every coordinate differs by about the same amount
+    bound = 3 * 2.0 ** -24 + d * 2.0 ** -52
+    for v in range(40):
+        exact = _exact_sq_l2(q, X[v])
+        got = oracle.dist(X, q, v)
+        if exact == 0:
+            assert got == 0.0
+            continue
+        rel = abs(float((got - exact) / exact))
+        assert rel <= bound, (v, rel, bound)
+
+
+def test_distance_correctly_rounded_when_differences_are_exact():
+    """Coordinates on a grid of 2^-6 in [-8, 8]: every float difference and its
+    square are exact, so the oracle must return the exact sum rounded once to the
+    nearest float."""
+    rng = np.random.default_rng(17)
+    d = 129
+    X = (rng.integers(-512, 513, (60, d)) / 64.0).astype(np.float32)
+    q = (rng.integers(-512, 513, d) / 64.0).astype(np.float32)
+    for v in range(60):
+        exact = _exact_sq_l2(q, X[v])
+        assert exact.denominator <= 1 << 12
+        assert oracle.dist(X, q, v) == float(np.float32(float(exact)))
+
+
+# ---------------------------------------------------------------------------
+# Direction-guided selection and its cool-down (Sec. 3.3.2 (b)): entries that a
+# DGS expansion only partly expanded are expanded again, in full, once the
+# cool-down starts; the cool-down is the last ceil(c T) iterations, and starts
+# early when no fresh entry is left.
+# ---------------------------------------------------------------------------
+def _kept_edge_reach(X, G, S, q, starts, n_keep):
+    """Nodes reachable from `starts` when every node follows only its n_keep slots of
+    smallest (sign mismatch, slot) toward query q (numpy, independent of oracle.c)."""
+    d = X.shape[1]
+    seen = set(int(s) for s in starts)
+    todo = list(seen)
+    while todo:
+        u = todo.pop()
+        qbits = (q > X[u])
+        mm = []
+        for j in range(G.shape[1]):
+            vbits = np.array([(int(S[u, j, i // 32]) >> (i % 32)) & 1 for i in range(d)], bool)
+            mm.append((int((qbits != vbits).sum()), j))
+        for _, j in sorted(mm)[:n_keep]:
+            v = int(G[u, j])
+            if v not in seen:
+                seen.add(v)
+                todo.append(v)
+    return seen
+
+
+def test_dgs_exhaustive_search_reaches_brute_force_through_the_cooldown():
+    """l >= N and a budget large enough for every node to be expanded in full after
+    the direction-filtered phase: on a connected graph the result is brute force.
+    The nodes reachable through the kept slots alone miss part of the true top-10
+    for some queries, so a cool-down that did not re-expand partly expanded entries
+    could not reach it."""
+    rng = np.random.default_rng(8)
+    N, d = 160, 12
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    Q = rng.standard_normal((25, d)).astype(np.float32)
+    ix = oracle.build_index(X, deg=8, dgs=True)
+    G, S = ix.shards[0]["graph"], ix.shards[0]["sign"]
+    n_cc = connected_components(csr_matrix((np.ones(G.size), (np.repeat(np.arange(N), 8), G.ravel().astype(np.int64))),
+                                           shape=(N, N)), directed=True, connection="strong")[0]
+    assert n_cc == 1
+    T = 4 * N
+    ids, ds, ctr = oracle.search(ix, Q, k=10, l=N, T=T, n_init=2, dgs_on=True, discard=0.5, cooldown=0.3)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    truth = f32_order(D, 10)
+    assert np.array_equal(ids, truth)
+    assert np.all(ctr[:, 3] > 0)
+    short = 0
+    for i in range(len(Q)):
+        reach = _kept_edge_reach(X, G, S, Q[i], init_ids(6, 0, i, 2, N), 4)
+        short += not set(truth[i].tolist()) <= reach
+    assert short > 0
+
+
+def _line_index(pos, G):
+    X = np.asarray(pos, np.float32).reshape(-1, 1)
+    return X, oracle.build_index(X, deg=G.shape[1], dgs=True, graph=np.asarray(G, np.uint32))
+
+
+def test_dgs_cooldown_length_is_ceil_of_c_times_T():
+    """A chain 0 - 1 - ... - 11 on a line, query far to the right, seed 0. Each DGS
+    expansion keeps the one slot that points right, so the search walks one node per
+    iteration. T = 9, c = 0.3: the cool-down is ceil(2.7) = 3 iterations, so exactly 6
+    expansions run under the filter (floor would give 7)."""
+    n = 12
+    G = [[1, 2]] + [[i - 1, i + 1] for i in range(1, n - 1)] + [[n - 2, n - 3]]
+    X, ix = _line_index(range(n), np.array(G))
+    q = np.array([[20.0]], np.float32)
+    ids, ds, ctr = oracle.search(ix, q, k=3, l=n, T=9, entry="seeds", seeds=np.array([[0]]), dgs_on=True,
+                                 discard=0.5, cooldown=0.3)
+    assert ids[0].tolist() == [9, 8, 7]
+    assert ctr[0, 3] == 6      # slots skipped: one per DGS-phase expansion
+    assert ctr[0, 1] == 9 and ctr[0, 2] == 9 and ctr[0, 0] == 10
+
+
+def test_dgs_forced_cooldown_reexpands_partial_entries():
+    """Nodes on a line: A = 0, B = 1, C = 2, D = 10; query 11; seed A.
+    A -> (B, D): both point toward the query, the slot order keeps B and skips D.
+    B -> (A, C) keeps C. C -> (B, A) keeps B, already visited: no fresh entry is left
+    after three DGS iterations, so the cool-down starts at once without spending an
+    iteration. It expands C, B and A in full (they were partial); A's skipped slot
+    finally reaches D, which is expanded in the last of the T = 7 iterations."""
+    G = np.array([[1, 3], [0, 2], [1, 0], [2, 0]])
+    X, ix = _line_index([0.0, 1.0, 2.0, 10.0], G)
+    q = np.array([[11.0]], np.float32)
+    ids, ds, ctr = oracle.search(ix, q, k=3, l=4, T=7, entry="seeds", seeds=np.array([[0]]), dgs_on=True,
+                                 discard=0.5, cooldown=0.3)
+    assert ids[0].tolist() == [3, 2, 1]
+    assert ds[0].tolist() == [1.0, 81.0, 100.0]
+    assert ctr[0, 0] == 4 and ctr[0, 1] == 7 and ctr[0, 2] == 7 and ctr[0, 3] == 3
+    # one iteration less: D is found but not expanded
+    _, _, c6 = oracle.search(ix, q, k=3, l=4, T=6, entry="seeds", seeds=np.array([[0]]), dgs_on=True,
+                             discard=0.5, cooldown=0.3)
+    assert c6[0, 1] == 6 and c6[0, 0] == 4
+
+
+# ---------------------------------------------------------------------------
+# Ghost staging hands over M[g], the node a ghost copies (Sec. 3.2.2).
+# ---------------------------------------------------------------------------
+def _ghost_expect(X, q, gmap, t):
+    Xg = np.ascontiguousarray(X[gmap])
+    _, Dg = oracle.brute_force_numpy(Xg, q[None], 1)
+    top = f32_order(Dg, t)[0]
+    nodes = gmap[top].astype(np.int64)
+    _, D = oracle.brute_force_numpy(X, q[None], 1)
+    dn = D[0, nodes].astype(np.float32)
+    order = np.lexsort((nodes, dn))
+    return top, nodes[order], dn[order]
+
+
+@pytest.mark.parametrize("entry", ["ghost_dense", "ghost_graph"])
+def test_ghost_seeds_are_the_mapped_nodes_of_the_nearest_ghosts(entry):
+    """R = 60 ghosts out of N = 500, so the ghost index and the node it copies differ.
+    With T = 0 the result is exactly the handed-over seeds: the nodes M[g] of the t
+    ghosts nearest to the query (exact for the dense entry; for the graph entry an
+    exhaustive ghost search on a connected ghost graph), ordered by (dist, id)."""
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((500, 10)).astype(np.float32)
+    Q = rng.standard_normal((20, 10)).astype(np.float32)
+    ix = oracle.build_index(X, deg=8, dgs=False, ghost_R=60, deg_g=8)
+    gmap = ix.shards[0]["g_map"]
+    assert len(gmap) == 60 and np.any(gmap != np.arange(60))
+    t = 12
+    kw = dict(l_g=60, T_g=200) if entry == "ghost_graph" else {}
+    if entry == "ghost_graph":
+        Gg = ix.shards[0]["g_graph"]
+        assert connected_components(csr_matrix((np.ones(Gg.size), (np.repeat(np.arange(60), 8),
+                                                                    Gg.ravel().astype(np.int64))), shape=(60, 60)),
+                                    directed=True, connection="strong")[0] == 1
+    ids, ds, ctr, gh = oracle.search(ix, Q, k=t, l=t, T=0, entry=entry, t_seeds=t, want_ghost=True, **kw)
+    for i in range(len(Q)):
+        top, nodes, dn = _ghost_expect(X, Q[i], gmap, t)
+        assert gh[i].tolist() == top.tolist()
+        assert ids[i].tolist() == nodes.tolist()
+        assert np.array_equal(ds[i], dn)
+        assert not np.array_equal(ids[i], np.sort(top))  # ghost indices are not node ids here
