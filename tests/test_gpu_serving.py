@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import dev, say, to_device_index
+from gpu_util import compare, dev, oracle_kwargs, say, to_device_index
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -29,6 +29,12 @@ def direct(gx, Q, k, itopk, T, opts):
                            qkeys=torch.arange(len(Q), dtype=torch.int64).cuda())
     torch.cuda.synchronize()
     return ids.cpu().numpy().view(np.uint32), dists.cpu().numpy()
+
+
+def oracle_of(ox, Q, k, itopk, T, opts):
+    """The CPU oracle's result for one request: query keys are the rows' indices in the request."""
+    o = oracle.search(ox, Q, qkeys=np.arange(len(Q), dtype=np.uint64), **oracle_kwargs(k, itopk, T, opts))
+    return o
 
 
 def test_alone_equals_in_mix(served):
@@ -69,6 +75,8 @@ def test_alone_equals_in_mix(served):
         lats.append(lat)
         ri, rd = direct(gx, Qj, k, 64, 60, opts)
         assert np.array_equal(ij, ri) and np.array_equal(dj, rd), j
+        # and the CPU oracle's result for the request on its own
+        compare((ij, dj, None), oracle_of(ox, Qj, k, 64, 60, opts), check_counters=False, label=f"served {j}")
     st = srv.stats()
     say(f"  batches {st['batches']} for {st['requests_done']} requests; p50 {np.percentile(lats, 50):.2f} ms "
         f"p99 {np.percentile(lats, 99):.2f} ms")
@@ -93,4 +101,34 @@ def test_admission_limits_queue_requests(served):
         srv.submit(synth.mixture_small(65, 64, 16, 0.3, 1), 10, 32, 30, opts)  # larger than one batch
     with pytest.raises(miann.MiannError):
         srv.submit(Qs[0], 40, 32, 30, opts)  # k > itopk
+    srv.close()
+
+
+def test_u8_degree64_dense_entry_mix():
+    """The serving form of the benchmark: uint8 rows, degree-64 graph, dense ghost entry with the direction
+    filter, requests of 1..1,024 queries with k in {10, 100} on four server streams (each stream with its own
+    kept scratch). Every served result equals the direct search of the same request and the CPU oracle's,
+    bit for bit (exact int32 distances)."""
+    say("serving u8 degree 64 dense entry, k in {10, 100}")
+    X = synth.to_u8(synth.mixture_small(3000, 128, 8, 0.3, 111))
+    ox = oracle.build_index(X, deg=64, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
+    setting = {10: (64, 32), 100: (128, 48)}
+    rng = np.random.default_rng(17)
+    reqs = []
+    for j in range(24):
+        n = int(min(1024, np.floor(np.exp(rng.uniform(0, np.log(1025))))))
+        reqs.append((synth.to_u8(synth.mixture_small(max(1, n), 128, 8, 0.3, 400 + j)), int(rng.choice([10, 100]))))
+    srv = miann.Server(gx, num_streams=4, max_batch_queries=4096)
+    tickets = [srv.submit(Qj, k, *setting[k], opts) for Qj, k in reqs]
+    for j, (Qj, k) in enumerate(reqs):
+        ij, dj, _ = srv.wait(tickets[j], len(Qj), k)
+        ri, rd = direct(gx, Qj, k, *setting[k], opts)
+        assert np.array_equal(ij, ri) and np.array_equal(dj, rd), j
+        frac = compare((ij, dj, None), oracle_of(ox, Qj, k, *setting[k], opts), min_frac=1.0, check_counters=False,
+                       label=f"u8 served {j} k={k} n={len(Qj)}")
+        assert frac == 1.0
+    st = srv.stats()
+    assert st["requests_done"] == len(reqs)
     srv.close()
