@@ -67,7 +67,7 @@ class Params(C.Structure):
                 ("dgs_on", C.c_int32), ("discard_pm", C.c_int32), ("cooldown_pm", C.c_int32),
                 ("random_discard", C.c_int32), ("ppe_on", C.c_int32), ("forward_f", C.c_int32),
                 ("rerank_mult", C.c_int32), ("visited_policy", C.c_int32), ("stop_on_no_change", C.c_int32),
-                ("ghost_every_stage", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("ghost_every_stage", C.c_int32), ("dgs_threshold_pm", C.c_int32), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -362,7 +362,8 @@ def build_index(X: np.ndarray, deg: int, S: int = 1, seed: int = 5, store: str |
 
 DEFAULTS = dict(k=10, l=64, r=1, T=64, n_init=None, entry="random", l_g=32, T_g=8, t_seeds=None,
                 dgs_on=False, discard=0.5, cooldown=0.3, random_discard=False, ppe_on=True, forward_f=1,
-                rerank_mult=4, visited="exact", stop_on_no_change=False, ghost_every_stage=False, seed=6)
+                rerank_mult=4, visited="exact", stop_on_no_change=False, ghost_every_stage=False, seed=6,
+                dgs_threshold=0.0)
 
 
 def make_params(ix: OracleIndex, **kw) -> Params:
@@ -382,6 +383,7 @@ def make_params(ix: OracleIndex, **kw) -> Params:
     p.visited_policy = VISITED[o["visited"]]
     p.stop_on_no_change = int(bool(o["stop_on_no_change"]))
     p.ghost_every_stage = int(bool(o["ghost_every_stage"]))
+    p.dgs_threshold_pm = int(round(o["dgs_threshold"] * 1000))
     p.seed = o["seed"] & (2**64 - 1)
     return p
 

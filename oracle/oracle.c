@@ -533,6 +533,7 @@ typedef struct {
   int l, r, T, n_init, k;
   int dgs_on, n_keep, cooldown_pm, random_discard;
   int visited_policy, stop_on_no_change;
+  int dgs_thr; /* < 0: keep the n_keep best-ranked slots; >= 0: keep every slot whose mismatch is <= dgs_thr */
 } beam_cfg;
 
 typedef struct {
@@ -635,6 +636,7 @@ static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint6
       for (int i = 0; i < l; i++) if (p[i].id != NONE_ID) vis_test_insert(V, p[i].id);
     }
     int keep = dgs_phase ? cfg->n_keep : deg;
+    const int thr_mode = dgs_phase && cfg->dgs_thr >= 0;
     for (int a = 0; a < npar; a++) p[par[a]].flag = (dgs_phase && keep < deg) ? FLAG_PARTIAL : FLAG_DONE;
     nc = 0;
     for (int a = 0; a < npar; a++) {
@@ -642,7 +644,28 @@ static void beam_search(const graph_view* g, const void* q, uint64_t qkey, uint6
       const uint32_t* nb = g->graph + (size_t)u * deg;
       int order[1024];
       for (int j = 0; j < deg; j++) order[j] = j;
-      if (dgs_phase) {
+      if (thr_mode) {
+        /* similarity-threshold pruning (Sec. 6.3): keep each slot whose mismatch is at most the threshold,
+         * in slot order; the parent is partly expanded only if some slot was skipped */
+        uint32_t qs[64];
+        for (int w = 0; w < g->W; w++) qs[w] = 0;
+        for (int i = 0; i < g->st->d; i++) {
+          int gt;
+          if (g->st->dtype == DT_U8) gt = ((const uint8_t*)q)[i] > ((const uint8_t*)g->st->codes)[(size_t)u * g->st->d + i];
+          else gt = ((const float*)q)[i] > elem(g->st, u, i);
+          if (gt) qs[i / 32] |= 1u << (i % 32);
+        }
+        int nk = 0;
+        for (int j = 0; j < deg; j++) {
+          int mm = 0;
+          const uint32_t* sj = g->sign + ((size_t)u * deg + j) * g->W;
+          for (int w = 0; w < g->W; w++) mm += popc32(qs[w] ^ sj[w]);
+          if (mm <= cfg->dgs_thr) order[nk++] = j;
+        }
+        keep = nk;
+        p[par[a]].flag = nk < deg ? FLAG_PARTIAL : FLAG_DONE;
+        ctr[3] += deg - nk;
+      } else if (dgs_phase) {
         /* rank slots by (mismatch, slot); mismatch = popcount(qsign XOR S[u][j]) */
         uint64_t rk[1024];
         if (cfg->random_discard) {
@@ -749,7 +772,7 @@ typedef struct {
   int32_t dgs_on, discard_pm, cooldown_pm, random_discard;
   int32_t ppe_on, forward_f, rerank_mult;
   int32_t visited_policy, stop_on_no_change;
-  int32_t ghost_every_stage, reserved;
+  int32_t ghost_every_stage, dgs_threshold_pm; /* 0: top-n selection; 1..1000: similarity threshold */
   uint64_t seed;
 } orc_params;
 
@@ -806,6 +829,8 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
   cfg.random_discard = P->random_discard;
   cfg.visited_policy = P->visited_policy;
   cfg.stop_on_no_change = P->stop_on_no_change;
+  /* threshold mode: keep a slot when mismatch * 1000 <= theta_pm * d, i.e. mismatch <= floor(theta_pm d / 1000) */
+  cfg.dgs_thr = P->dgs_threshold_pm > 0 ? (int)(((int64_t)P->dgs_threshold_pm * ix->d) / 1000) : -1;
 
   for (int t = 0; t < S; t++) {
     int s = (s0 + t) % S;
@@ -959,6 +984,7 @@ int orc_search(const orc_index* ix, const orc_params* P, const void* queries, in
   if (P->k < 1 || P->l < P->k || P->l > 1024 || P->r < 1 || P->r > 64 || P->T < 0) return 1;
   if (ix->S < 1 || ix->S > ORC_MAXS) return 1;
   if (P->forward_f > 64 || P->t_seeds > 1024 || P->n_init > 1024 || ix->deg > 1024) return 1;
+  if (P->dgs_threshold_pm < 0 || P->dgs_threshold_pm > 1000 || (P->dgs_threshold_pm > 0 && P->random_discard)) return 1;
   if (n_given < 0 || n_given > ORC_MAX_GIVEN) return 1;
   search_ctx C = {ix, P, queries, qkeys, given_seeds, n_given, given_T, out_id, out_d, ctr, out_ghost};
   int64_t nmax = 1, gmax = 1;

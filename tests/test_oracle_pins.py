@@ -693,3 +693,51 @@ def test_ghost_seeds_are_the_mapped_nodes_of_the_nearest_ghosts(entry):
         assert ids[i].tolist() == nodes.tolist()
         assert np.array_equal(ds[i], dn)
         assert not np.array_equal(ids[i], np.sort(top))  # ghost indices are not node ids here
+
+
+# ---------------------------------------------------------------------------
+# Similarity-threshold pruning (Sec. 6.3): instead of the fixed top-n of the
+# direction ranking, a filtered expansion keeps every slot whose sign mismatch
+# is at most floor(theta d); the parent is partly expanded only if a slot was
+# skipped.
+# ---------------------------------------------------------------------------
+def test_threshold_one_keeps_every_slot_and_equals_plain_search():
+    X = small(600, 16, C=5)
+    Q = small(30, 16, C=5, seed=2)
+    ix = oracle.build_index(X, deg=10, dgs=True)
+    plain = oracle.search(ix, Q, k=10, l=32, T=50)
+    o = oracle.search(ix, Q, k=10, l=32, T=50, dgs_on=True, dgs_threshold=1.0)
+    assert np.array_equal(plain[0], o[0]) and np.array_equal(plain[1], o[1])
+    assert np.array_equal(plain[2][:, :3], o[2][:, :3]) and np.all(o[2][:, 3] == 0)
+
+
+def test_threshold_on_a_line_keeps_all_aligned_slots():
+    """The chain of the cool-down pin with node 0 -> (1, 2), both toward the query. With d = 1 and
+    theta = 0.999 the threshold is floor(0.999) = 0 mismatches: node 0 keeps both slots (top-n with
+    n = 1 would keep one), node i keeps i + 1 and skips i - 1. T = 9, c = 0.3: 6 filtered iterations
+    expand 0, 2, 3, 4, 5, 6 (five of them skip one slot), the cool-down expands 7, 8, 9."""
+    n = 12
+    G = [[1, 2]] + [[i - 1, i + 1] for i in range(1, n - 1)] + [[n - 2, n - 3]]
+    X, ix = _line_index(range(n), np.array(G))
+    q = np.array([[20.0]], np.float32)
+    ids, ds, ctr = oracle.search(ix, q, k=3, l=n, T=9, entry="seeds", seeds=np.array([[0]]), dgs_on=True,
+                                 dgs_threshold=0.999, cooldown=0.3)
+    assert ids[0].tolist() == [10, 9, 8]
+    assert ctr[0, 3] == 5 and ctr[0, 1] == 9 and ctr[0, 0] == 11
+
+
+def test_threshold_skipping_every_slot_leaves_the_parent_partial():
+    """In 2-D, a parent whose two neighbours both point away from the query on both axes keeps neither
+    (theta = 0.5: at most one mismatch of two); it stays partial and the cool-down expands it in full."""
+    X = np.array([[0.0, 0.0], [-1.0, -1.0], [-2.0, -1.5], [5.0, 5.0]], np.float32)
+    G = np.array([[1, 2], [0, 2], [0, 1], [0, 1]])
+    X, ix = np.asarray(X), oracle.build_index(X, deg=2, dgs=True, graph=G)
+    q = np.array([[4.0, 4.0]], np.float32)
+    ids, ds, ctr = oracle.search(ix, q, k=3, l=4, T=3, entry="seeds", seeds=np.array([[0]]), dgs_on=True,
+                                 dgs_threshold=0.5, cooldown=0.3)
+    # it 0 (filtered): node 0 skips both slots; no fresh entry is left, so the cool-down starts and
+    # it 1 expands node 0 in full (1 and 2 found); it 2 expands node 1 (nothing new)
+    assert ids[0].tolist() == [0, 1, 2]
+    assert ctr[0, 3] == 2 and ctr[0, 1] == 3 and ctr[0, 0] == 3 and ctr[0, 2] == 3
+    with pytest.raises(ValueError):
+        oracle.search(ix, q, k=3, l=4, T=3, dgs_on=True, dgs_threshold=0.5, random_discard=True)
