@@ -58,7 +58,7 @@ class Index(C.Structure):
                 ("orig", C.c_void_p * MAXS), ("graph", C.c_void_p * MAXS), ("sign", C.c_void_p * MAXS),
                 ("gmap", C.c_void_p * MAXS), ("next", C.c_void_p * MAXS), ("R", C.c_int64 * MAXS),
                 ("g_codes", C.c_void_p * MAXS), ("g_scale", C.c_void_p * MAXS),
-                ("g_graph", C.c_void_p * MAXS), ("g_map", C.c_void_p * MAXS)]
+                ("g_graph", C.c_void_p * MAXS), ("g_map", C.c_void_p * MAXS), ("dead", C.c_void_p * MAXS)]
 
 
 class Params(C.Structure):
@@ -291,6 +291,7 @@ class OracleIndex:
             ix.g_scale[s] = _ptr(sh.get("g_scale"))
             ix.g_graph[s] = _ptr(sh.get("g_graph"))
             ix.g_map[s] = _ptr(sh.get("g_map"))
+            ix.dead[s] = _ptr(sh.get("dead"))
         return ix
 
 
@@ -349,15 +350,66 @@ def build_index(X: np.ndarray, deg: int, S: int = 1, seed: int = 5, store: str |
         for s in range(S):
             sh = ix.shards[s]
             R = ghost_R if ghost_R else int(np.floor(ghost_ratio * sh["n"] + 0.5))
-            gam = ghost_sample(sh["n"], R, seed, s)
-            Xg = np.ascontiguousarray(sh["orig_base"][gam])
-            sh["R"] = R
-            sh["g_map"] = gam
-            sh["g_graph"] = build_graph(Xg, deg_g)
-            sh["g_codes"] = np.ascontiguousarray(sh["codes"][gam])
-            if "scale" in sh:
-                sh["g_scale"] = np.ascontiguousarray(sh["scale"][gam])
+            _ghost_shard(sh, R, seed, s, deg_g)
     return ix
+
+
+def _ghost_shard(sh: dict, R: int, seed: int, s: int, deg_g: int) -> None:
+    """Ghost shard of one shard (Sec. 3.2.2): R sampled nodes, their copies and their own graph."""
+    gam = ghost_sample(sh["n"], R, seed, s)
+    Xg = np.ascontiguousarray(sh["orig_base"][gam])
+    sh["R"] = R
+    sh["g_map"] = gam
+    sh["g_graph"] = build_graph(Xg, deg_g)
+    sh["g_codes"] = np.ascontiguousarray(sh["codes"][gam])
+    if "scale" in sh:
+        sh["g_scale"] = np.ascontiguousarray(sh["scale"][gam])
+
+
+def delete(ix: OracleIndex, global_ids) -> None:
+    """Deletion flags (Sec. 6.2): the nodes stay in the graphs and are traversed, but no result returns them."""
+    gl = set(int(g) for g in np.asarray(global_ids).ravel())
+    for sh in ix.shards:
+        dead = sh.get("dead")
+        if dead is None:
+            dead = np.zeros(sh["n"], np.uint8)
+        dead = dead | np.array([int(g) in gl for g in sh["gmap"]], np.uint8)
+        sh["dead"] = np.ascontiguousarray(dead)
+
+
+def append(ix: OracleIndex, s: int, Xnew: np.ndarray, ghost_seed: int = 5, K0: int | None = None) -> None:
+    """Insertion into an existing shard (Sec. 6.2): the new rows get the next global ids and the next local ids
+    of shard s; the shard's graph and direction table are rebuilt over all its rows, its store re-made, its
+    ghost shard re-sampled with the same count, and the inter-shard maps into and out of the shard refreshed
+    (I(u) of Sec. 3.1.2, exact)."""
+    sh = ix.shards[s]
+    Xnew = np.ascontiguousarray(Xnew)
+    n_old = sh["n"]
+    Xs = np.ascontiguousarray(np.concatenate([sh["orig_base"], Xnew]))
+    sh["orig_base"] = Xs
+    sh["n"] = len(Xs)
+    sh["gmap"] = np.ascontiguousarray(np.concatenate([sh["gmap"], np.arange(ix.n_total, ix.n_total + len(Xnew),
+                                                                            dtype=np.uint32)]))
+    ix.n_total += len(Xnew)
+    sh["graph"] = build_graph(Xs, ix.deg, K0)
+    if "sign" in sh:
+        sh["sign"] = sign_table(Xs, sh["graph"])
+    if ix.dtype in ("f16", "fp8"):
+        sh["codes"], sh["scale"] = quantize(Xs, ix.dtype)
+        sh["orig"] = Xs
+    else:
+        sh["codes"] = Xs
+    if "dead" in sh:
+        sh["dead"] = np.ascontiguousarray(np.concatenate([sh["dead"], np.zeros(len(Xnew), np.uint8)]))
+    S = ix.S
+    if S > 1:
+        nxt = ix.shards[(s + 1) % S]["orig_base"]
+        sh["next"] = np.ascontiguousarray(knn(nxt, Xs, 1)[0][:, 0])
+        prev = ix.shards[(s - 1) % S]
+        prev["next"] = np.ascontiguousarray(knn(Xs, prev["orig_base"], 1)[0][:, 0])
+    if sh.get("R"):
+        _ghost_shard(sh, sh["R"], ghost_seed, s, ix.deg_g)
+    del n_old
 
 
 DEFAULTS = dict(k=10, l=64, r=1, T=64, n_init=None, entry="random", l_g=32, T_g=8, t_seeds=None,

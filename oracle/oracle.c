@@ -757,6 +757,7 @@ typedef struct {
   const float* g_scale[ORC_MAXS];
   const uint32_t* g_graph[ORC_MAXS];
   const uint32_t* g_map[ORC_MAXS];  /* ghost id -> local id in its shard */
+  const uint8_t* dead[ORC_MAXS];    /* nonzero: the node is deleted (still traversed, never returned), or NULL */
 } orc_index;
 
 #define ENTRY_RANDOM 0
@@ -907,6 +908,15 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
         handoff[nhand++] = ix->next[s][sc->p[i].id];
       }
 
+    /* deleted nodes (Sec. 6.2, a deletion flag) served the traversal and the hand-off above; the stage
+     * result is taken from the entries of p that are not deleted, in p order */
+    entry live[1024];
+    int nlive = 0;
+    for (int i = 0; i < l; i++) {
+      if (sc->p[i].id == NONE_ID) break;
+      if (ix->dead[s] && ix->dead[s][sc->p[i].id]) continue;
+      live[nlive++] = sc->p[i];
+    }
     /* stage result: first k (after an FP32 rerank of the first min(m k, l) for low precision) */
     res loc[1024];
     int nloc = 0;
@@ -914,19 +924,17 @@ static void search_row(void* vctx, int64_t row, void* vscratch) {
       orc_store o = {DT_F32, ix->d, ix->n[s], ix->orig[s], NULL};
       int m = P->rerank_mult * k;
       if (m > l) m = l;
-      for (int i = 0; i < m; i++) {
-        if (sc->p[i].id == NONE_ID) break;
-        loc[nloc].d = dist_qv(&o, q, sc->p[i].id);
-        loc[nloc].id = sc->p[i].id;
+      for (int i = 0; i < m && i < nlive; i++) {
+        loc[nloc].d = dist_qv(&o, q, live[i].id);
+        loc[nloc].id = live[i].id;
         nloc++;
         ctr[6]++;
       }
       qsort(loc, (size_t)nloc, sizeof(res), res_cmp);
     } else {
-      for (int i = 0; i < l; i++) {
-        if (sc->p[i].id == NONE_ID) break;
-        loc[nloc].d = sc->p[i].d;
-        loc[nloc].id = sc->p[i].id;
+      for (int i = 0; i < nlive; i++) {
+        loc[nloc].d = live[i].d;
+        loc[nloc].id = live[i].id;
         nloc++;
       }
     }

@@ -741,3 +741,79 @@ def test_threshold_skipping_every_slot_leaves_the_parent_partial():
     assert ctr[0, 3] == 2 and ctr[0, 1] == 3 and ctr[0, 0] == 3 and ctr[0, 2] == 3
     with pytest.raises(ValueError):
         oracle.search(ix, q, k=3, l=4, T=3, dgs_on=True, dgs_threshold=0.5, random_discard=True)
+
+
+# ---------------------------------------------------------------------------
+# Dynamic updates (Sec. 6.2): deletion flags and insertion into a shard.
+# ---------------------------------------------------------------------------
+def test_deleted_nodes_are_never_returned_exhaustive_search_is_brute_force_over_live():
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((250, 10)).astype(np.float32)
+    Q = rng.standard_normal((20, 10)).astype(np.float32)
+    ix = oracle.build_index(X, deg=10, dgs=True)
+    base = oracle.search(ix, Q, k=10, l=250, T=300)
+    dead = rng.choice(250, 60, replace=False)
+    oracle.delete(ix, dead)
+    ids, ds, ctr = oracle.search(ix, Q, k=10, l=250, T=300)
+    _, D = oracle.brute_force_numpy(X, Q, 10)
+    D[:, dead] = np.inf
+    assert np.array_equal(ids, f32_order(D, 10))
+    assert not np.isin(ids, dead).any()
+    # the traversal itself is unchanged: the same nodes are evaluated and expanded
+    assert np.array_equal(base[2], ctr)
+    # no flag set: identical to an index without flags
+    ix.shards[0]["dead"][:] = 0
+    again = oracle.search(ix, Q, k=10, l=250, T=300)
+    assert np.array_equal(again[0], base[0]) and np.array_equal(again[1], base[1])
+
+
+def test_deleted_node_still_bridges_and_low_precision_reranks_live_entries():
+    """A line 0 - 1 - 2 - 3 with the query beside node 3 and the search seeded at node 0: node 1, deleted,
+    is the only way on, and the search still reaches 2 and 3 through it; the result skips 1."""
+    G = np.array([[1, 1], [0, 2], [1, 3], [2, 2]])
+    X, ix = _line_index([0.0, 1.0, 2.0, 3.0], G)
+    oracle.delete(ix, [1])
+    ids, ds, ctr = oracle.search(ix, np.array([[3.2]], np.float32), k=3, l=4, T=10, entry="seeds",
+                                 seeds=np.array([[0]]))
+    assert ids[0].tolist() == [3, 2, 0]
+    Xf = small(300, 32, C=3)
+    Q = small(10, 32, C=3, seed=2)
+    for store in ("f16", "fp8"):
+        lp = oracle.build_index(Xf, deg=10, dgs=False, store=store)
+        full = oracle.search(lp, Q, k=5, l=40, T=60)
+        oracle.delete(lp, full[0][:, 0])  # every query's best result
+        ids, ds, ctr = oracle.search(lp, Q, k=5, l=40, T=60)
+        assert not np.isin(ids, full[0][:, 0]).any()
+        assert np.all(ctr[:, 6] == 20)  # the rerank takes the first 4k live entries
+
+
+def test_append_to_one_shard_equals_building_from_all_rows():
+    X = small(500, 16, C=4)
+    ixa = oracle.build_index(X[:420], deg=8, dgs=True, ghost_R=40, deg_g=8)
+    oracle.append(ixa, 0, X[420:], ghost_seed=5)
+    ixb = oracle.build_index(X, deg=8, dgs=True, ghost_R=40, deg_g=8)
+    a, b = ixa.shards[0], ixb.shards[0]
+    for key in ("graph", "sign", "gmap", "g_map", "g_graph"):
+        assert np.array_equal(a[key], b[key]), key
+    Q = small(30, 16, C=4, seed=2)
+    for kw in (dict(dgs_on=True), dict(entry="ghost_graph"), dict(entry="ghost_dense", dgs_on=True)):
+        ra = oracle.search(ixa, Q, k=10, l=32, T=40, **kw)
+        rb = oracle.search(ixb, Q, k=10, l=32, T=40, **kw)
+        assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1])
+
+
+def test_append_keeps_inter_shard_maps_exact():
+    X = small(600, 12, C=3)
+    ix = oracle.build_index(X, deg=8, S=3, dgs=False)
+    new = small(50, 12, C=3, seed=7)
+    oracle.append(ix, 1, new)
+    assert ix.shards[1]["n"] == 250 and ix.n_total == 650
+    assert np.array_equal(ix.shards[1]["gmap"][-50:], np.arange(600, 650))
+    for s in range(3):
+        A = ix.shards[s]["orig_base"]
+        B = ix.shards[(s + 1) % 3]["orig_base"]
+        _, D = oracle.brute_force_numpy(B, A, 1)
+        assert np.array_equal(ix.shards[s]["next"], f32_order(D, 1)[:, 0])
+    # the appended rows are found by their new global ids
+    ids, _, _ = oracle.search(ix, new[:5], k=1, l=64, T=80, n_init=32)
+    assert ids[:, 0].tolist() == list(range(600, 605))
