@@ -412,6 +412,23 @@ def append(ix: OracleIndex, s: int, Xnew: np.ndarray, ghost_seed: int = 5, K0: i
     del n_old
 
 
+def next_map_by_search(ix: OracleIndex, s: int, **kw) -> np.ndarray:
+    """The shard-to-shard lookup table built by search (Sec. 4, implementation of path extension): every node
+    of shard s is a query of a search on shard (s+1) mod S alone (that shard's graph, direction table, store
+    and ghost shard; no deletion flags), keyed by its local id, and the top-1 local id is the entry I_s(u).
+    kw are the search parameters of `search` (k is 1; path extension does not apply to one shard)."""
+    nx = ix.shards[(s + 1) % ix.S]
+    view = OracleIndex(dtype=ix.dtype, d=ix.d, deg=ix.deg, S=1, n_total=nx["n"], deg_g=ix.deg_g)
+    sh = {k: v for k, v in nx.items() if k not in ("next", "dead")}
+    sh["gmap"] = np.arange(nx["n"], dtype=np.uint32)
+    view.shards.append(sh)
+    src = ix.shards[s]["orig_base"]
+    kw = dict(kw)
+    kw["k"] = 1
+    ids, _, _ = search(view, src, qkeys=np.arange(len(src), dtype=np.uint64), **kw)
+    return np.ascontiguousarray(ids[:, 0])
+
+
 DEFAULTS = dict(k=10, l=64, r=1, T=64, n_init=None, entry="random", l_g=32, T_g=8, t_seeds=None,
                 dgs_on=False, discard=0.5, cooldown=0.3, random_discard=False, ppe_on=True, forward_f=1,
                 rerank_mult=4, visited="exact", stop_on_no_change=False, ghost_every_stage=False, seed=6,

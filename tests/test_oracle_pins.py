@@ -817,3 +817,50 @@ def test_append_keeps_inter_shard_maps_exact():
     # the appended rows are found by their new global ids
     ids, _, _ = oracle.search(ix, new[:5], k=1, l=64, T=80, n_init=32)
     assert ids[:, 0].tolist() == list(range(600, 605))
+
+
+# ---------------------------------------------------------------------------
+# The lookup table built by search (Sec. 4): every node of a shard searches the adjacent shard, top-1 kept
+# ---------------------------------------------------------------------------
+def test_search_built_lookup_table_exhaustive_equals_exact_nearest():
+    """An exhaustive search (queue longer than the shard, T beyond it) on a connected graph reaches the whole
+    shard, so its top-1 is the brute-force nearest node: the search-built table equals I(u) of Sec. 3.1.2."""
+    X = small(500, 12, C=1, sigma=1.0, seed=21)
+    ix = oracle.build_index(X, deg=12, S=2, dgs=True)
+    for s in range(2):
+        nx = ix.shards[(s + 1) % 2]
+        A = csr_matrix((np.ones(nx["graph"].size), nx["graph"].ravel(),
+                        np.arange(0, nx["graph"].size + 1, nx["graph"].shape[1])), shape=(nx["n"], nx["n"]))
+        assert connected_components(A, directed=True, connection="strong")[0] == 1
+        lut = oracle.next_map_by_search(ix, s, l=nx["n"], T=2 * nx["n"], n_init=8)
+        _, D = oracle.brute_force_numpy(nx["orig_base"], ix.shards[s]["orig_base"], 1)
+        assert np.array_equal(lut, f32_order(D, 1)[:, 0])
+        assert np.array_equal(lut, ix.shards[s]["next"])
+
+
+def test_search_built_lookup_table_is_the_per_node_search():
+    """Entry u is the top-1 local id of one search of node u on the next shard alone, keyed by u: the same
+    value as a 1-shard index of that shard searched with the node as its only query."""
+    X = small(600, 16, C=3, seed=22)
+    ix = oracle.build_index(X, deg=8, S=3, dgs=True, ghost_R=30, deg_g=8)
+    kw = dict(l=16, T=6, entry="ghost_graph", dgs_on=True)
+    lut = oracle.next_map_by_search(ix, 1, **kw)
+    nx = ix.shards[2]
+    assert lut.max() < nx["n"]
+    one = oracle.OracleIndex(dtype=ix.dtype, d=ix.d, deg=ix.deg, S=1, n_total=nx["n"], deg_g=ix.deg_g)
+    sh = dict(nx)
+    sh.pop("next")
+    sh["gmap"] = np.arange(nx["n"], dtype=np.uint32)
+    one.shards.append(sh)
+    src = ix.shards[1]["orig_base"]
+    for u in (0, 17, 150, len(src) - 1):
+        ids, _, _ = oracle.search(one, src[u:u + 1], qkeys=np.array([u], np.uint64), k=1, **kw)
+        assert lut[u] == ids[0, 0]
+    # a short search does not always find the nearest node; where it does not, its pick is farther
+    _, D = oracle.brute_force_numpy(nx["orig_base"], src, nx["n"])
+    exact = f32_order(D, 1)[:, 0]
+    miss = lut != exact
+    assert 0 < miss.mean() < 0.5
+    d32 = D.astype(np.float32)
+    rows = np.arange(len(src))
+    assert np.all(d32[rows[miss], lut[miss]] >= d32[rows[miss], exact[miss]])
