@@ -191,7 +191,10 @@ typedef struct {
   int32_t n_seeds;          /* entries per query in seeds_dev (MIANN_ENTRY_SEEDS) */
   int32_t ghost_every_stage;/* with path extension and a ghost entry: stages t >= 1 also start from their
                                shard's ghost-entry seeds, besides I(z) (an extension; 0 = stage 0 only) */
-  int32_t reserved;
+  int32_t dgs_threshold_permille; /* theta * 1000 in 1..1000: the direction filter keeps every slot whose sign
+                               mismatch is at most floor(theta * d) instead of the n_keep best (the
+                               similarity-threshold variant of Sec. 6.3); a parent with a skipped slot is
+                               re-expanded in the cool-down. 0 = top-n selection */
   uint64_t seed;            /* random-stream seed */
   const uint64_t* qkeys;    /* device [nq] query keys (index within a request), NULL = row index */
   const uint32_t* seeds;    /* device [nq][n_seeds] local ids in each query's start shard */

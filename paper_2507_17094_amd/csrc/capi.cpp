@@ -435,6 +435,9 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   if (sp.dgs && !ix->dgs) return fail(MIANN_ESTATE, "miann_search: the index has no direction table");
   if (sp.discard_permille < 0 || sp.discard_permille > 1000 || sp.cooldown_permille < 0 || sp.cooldown_permille > 1000)
     return fail(MIANN_EINVAL, "miann_search: discard/cooldown permille out of [0, 1000]");
+  if (sp.dgs_threshold_permille < 0 || sp.dgs_threshold_permille > 1000 ||
+      (sp.dgs_threshold_permille > 0 && sp.random_discard))
+    return fail(MIANN_EINVAL, "miann_search: dgs_threshold_permille out of [0, 1000] or combined with random_discard");
   const int f = sp.forward_f;
   if (ix->S > 1 && sp.ppe && (f < 1 || f > 16 || f > itopk))
     return fail(MIANN_EINVAL, "miann_search: forward_f %d out of [1, min(16, itopk)]", f);
@@ -479,6 +482,7 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   a.entry = sp.entry;
   a.dgs = sp.dgs;
   a.n_keep = ix->deg - (sp.discard_permille * ix->deg) / 1000;
+  a.dgs_thr = sp.dgs_threshold_permille > 0 ? (int)(((int64_t)sp.dgs_threshold_permille * ix->d) / 1000) : -1;
   a.cooldown_pm = sp.cooldown_permille;
   a.random_discard = sp.random_discard;
   a.stop_on_no_change = sp.stop_on_no_change;

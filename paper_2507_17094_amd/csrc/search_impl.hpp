@@ -474,8 +474,10 @@ struct Searcher {
       }
       if (hfill > ((hmask + 1) >> 1)) hash_rebuild(l);
       const int keep = dgs_phase ? a.n_keep : g.deg;
+      // similarity-threshold selection (Sec. 6.3): the parents' flags follow from their kept counts below
+      const bool thr_mode = dgs_phase && a.dgs_thr >= 0;
       const uint32_t newflag = (dgs_phase && keep < g.deg) ? kPartial : kDone;
-      if (lane < npar) pk[ppos[lane]] = (pk[ppos[lane]] & ~3ull) | newflag;
+      if (!thr_mode && lane < npar) pk[ppos[lane]] = (pk[ppos[lane]] & ~3ull) | newflag;
       // lane -> (parent, slot)
       const int pa = lane / g.degp, slot = lane % g.degp;
       const bool act = pa < npar && slot < g.deg;
@@ -494,12 +496,12 @@ struct Searcher {
         if (!a.random_discard) parent_signs(g, npar);
         wsync();
         uint32_t rk = 0xFFFFFFFFu;
+        int mm = 0;
         if (act) {
           if (a.random_discard) {
             const uint64_t h1 = sm_at(stream, qkey + 1);
             rk = ((uint32_t)(sm_mix(h1 ^ (((uint64_t)u << 8) | (uint64_t)slot)) >> 40) << 8) | (uint32_t)slot;
           } else {
-            int mm = 0;
 #pragma unroll
             for (int w = 0; w < kSW; w++)
               if (w < W) mm += __popc(qsign[pa * W + w] ^ sw[w]);
@@ -507,13 +509,26 @@ struct Searcher {
             rk = ((uint32_t)mm << 8) | (uint32_t)slot;
           }
         }
-        // the kept slots: the keep smallest (mismatch, slot) keys of each parent's segment, first in it
-        rk = 2 * keep == g.degp ? bitonic_lower_half_u32_seg(rk, g.degp) : bitonic_sort_u32_seg(rk, g.degp);
-        const bool kept = act && slot < keep && rk != 0xFFFFFFFFu;
-        const int src = pa * g.degp + (int)(rk & 0xFFu);
-        const uint32_t nb_sel = shfl_u32(nb, kept ? src : lane);
-        nb = kept ? nb_sel : kNone;
-        ctr_add(3, (g.deg - keep) * npar);
+        if (thr_mode) {
+          // keep every slot whose mismatch is at most the threshold; a parent with a skipped slot is partial
+          const bool kept = act && mm <= a.dgs_thr;
+          const uint64_t km = ballot(kept);
+          if (lane < npar) {
+            const uint64_t seg = g.deg >= 64 ? ~0ull : ((1ull << g.deg) - 1ull);
+            const int nk = __popcll((km >> (lane * g.degp)) & seg);
+            pk[ppos[lane]] = (pk[ppos[lane]] & ~3ull) | (nk < g.deg ? kPartial : kDone);
+          }
+          nb = kept ? nb : kNone;
+          ctr_add(3, npar * g.deg - __popcll(km));
+        } else {
+          // the kept slots: the keep smallest (mismatch, slot) keys of each parent's segment, first in it
+          rk = 2 * keep == g.degp ? bitonic_lower_half_u32_seg(rk, g.degp) : bitonic_sort_u32_seg(rk, g.degp);
+          const bool kept = act && slot < keep && rk != 0xFFFFFFFFu;
+          const int src = pa * g.degp + (int)(rk & 0xFFu);
+          const uint32_t nb_sel = shfl_u32(nb, kept ? src : lane);
+          nb = kept ? nb_sel : kNone;
+          ctr_add(3, (g.deg - keep) * npar);
+        }
       }
       const int changed = add_ids(g, nb != kNone, nb, l);
       n_exp += npar;

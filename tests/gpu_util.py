@@ -64,7 +64,8 @@ def oracle_kwargs(k, itopk, T, o: miann.SearchOptions) -> dict:
     return dict(k=k, l=itopk, r=o.search_width, T=T, n_init=o.n_init or None, entry=o.entry, l_g=o.ghost_itopk,
                 T_g=o.ghost_iters, t_seeds=o.t_seeds or None, dgs_on=o.dgs, discard=o.discard, cooldown=o.cooldown,
                 random_discard=o.random_discard, ppe_on=o.ppe, forward_f=o.forward_f, rerank_mult=o.rerank_mult,
-                stop_on_no_change=o.stop_on_no_change, ghost_every_stage=o.ghost_every_stage, seed=o.seed)
+                stop_on_no_change=o.stop_on_no_change, ghost_every_stage=o.ghost_every_stage, seed=o.seed,
+                dgs_threshold=o.dgs_threshold)
 
 
 def run_both(ox, gx, Q: np.ndarray, k, itopk, T, opts: miann.SearchOptions, qkeys=None, seeds=None, Tq=None):

@@ -50,6 +50,8 @@ CASES = [
     ("itopk_k", 10, 40, dict()),
     ("T0", 64, 0, dict(n_init=100)),
     ("discard_07", 64, 80, dict(dgs=True, discard=0.7, cooldown=0.1)),
+    ("dgs_threshold_040", 64, 80, dict(dgs=True, dgs_threshold=0.4)),
+    ("dgs_threshold_035_r2", 64, 60, dict(dgs=True, dgs_threshold=0.35, search_width=2)),
 ]
 
 

@@ -41,6 +41,7 @@ WIDE_CASES = [
     ("dgs_c05_discard07", 10, 128, 60, dict(dgs=True, entry="ghost_dense", discard=0.7, cooldown=0.5)),
     ("k100_itopk512", 100, 512, 64, dict(dgs=True, entry="ghost_dense")),
     ("k100_itopk256_plain", 100, 256, 48, dict()),
+    ("dgs_threshold", 10, 64, 40, dict(dgs=True, dgs_threshold=0.42, entry="ghost_dense")),
 ]
 
 
