@@ -154,6 +154,28 @@ miann_status miann_index_info(const miann_index* idx, int32_t* num_shards, int64
                               int32_t* degree, int32_t* store_dtype);
 void miann_index_free(miann_index* idx);
 
+/* Dynamic updates (Sec. 6.2). */
+/* Deletion flags: the m nodes with these global ids (device [m], unknown ids
+ * ignored) stay in their graphs and are still traversed and handed over
+ * between shards, but no search returns them: each stage's result is taken
+ * from the entries of its priority queue that are not deleted, in queue
+ * order (for low-precision stores, the rerank takes the first min(m k,
+ * itopk) live entries). Flags accumulate over calls. Synchronises `stream`. */
+miann_status miann_index_delete(miann_index* idx, const uint32_t* global_ids_dev, int64_t m, void* stream);
+/* Insertion into one shard: the n new rows (device [n][d], the index's input
+ * type) get the next global ids and the next local ids of `shard`; the shard's
+ * graph is rebuilt over all its rows by the same exact K0-NN and pruning as
+ * miann_build_graph (K0 of the original build, else 2 * degree), its
+ * direction table and store are extended, the inter-shard maps into and out
+ * of the shard are recomputed (exact 1-NN, Sec. 3.1.2), and, when the index
+ * has ghost shards, every shard's ghosts are re-sampled with the same counts
+ * from `ghost_seed` (pass the seed of the earlier miann_build_ghost to keep
+ * the other shards' samples) and the dense arrays rebuilt. The old arrays of
+ * the shard are freed. Not safe while searches on the index are in flight.
+ * Synchronises `stream`. */
+miann_status miann_index_append(miann_index* idx, int32_t shard, const void* vectors_dev, int64_t n, uint64_t ghost_seed,
+                                void* stream);
+
 /* Writes an index to a file at `path` (host file I/O; synchronises the
  * device): per shard the originals, graph, global ids, inter-shard map, ghost
  * ids and ghost graph, with the index's dimensions and types. EINVAL if the
@@ -227,6 +249,18 @@ void miann_search_params_default(miann_search_params* sp);
 miann_status miann_search(const miann_index* idx, const void* queries_dev, int64_t nq, int32_t k, int32_t itopk,
                           int32_t max_iters, const miann_search_params* sp, uint32_t* ids_dev, void* dists_dev,
                           int64_t* counters_dev, void* stream);
+
+/* The shard-to-shard lookup table built by search, as the paper builds it
+ * (Sec. 4): every node u of shard s is a query of a search on shard (s+1) mod
+ * S alone (its graph, direction table, store and ghost shard; deletion flags
+ * do not apply), keyed by its local id u, with k = 1, `itopk`, `max_iters` and
+ * the parameters `sp` (entry MIANN_ENTRY_RANDOM or MIANN_ENTRY_GHOST_GRAPH;
+ * qkeys, seeds, max_iters_per_query, phase_ms and phase_events must be NULL);
+ * the top-1 local id replaces I_s(u). The exact 1-NN map of miann_build_graph
+ * is the same table built by an exhaustive scan. EINVAL for S < 2,
+ * EUNSUPPORTED for the dense or seeded entries. Synchronises `stream`. */
+miann_status miann_build_next_map(miann_index* idx, int32_t itopk, int32_t max_iters, const miann_search_params* sp,
+                                  void* stream);
 
 /* Exact k nearest neighbours of each query over all shards (Sec. 2.1 Eq. 1),
  * by MFMA distance tiles with fused selection and direct-form rescoring.

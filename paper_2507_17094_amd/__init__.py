@@ -116,6 +116,9 @@ def load():
     L.miann_search_params_default.restype = None
     L.miann_search.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.miann_exact_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    L.miann_index_delete.argtypes = [vp, vp, i64, vp]
+    L.miann_index_append.argtypes = [vp, i32, vp, i64, u64, vp]
+    L.miann_build_next_map.argtypes = [vp, i32, i32, C.POINTER(SearchParams), vp]
     L.miann_last_error.restype = C.c_char_p
     L.miann_version.restype = C.c_char_p
     L.miann_nearest_ghost.argtypes = [vp, i32, vp, i64, vp, vp]
@@ -139,7 +142,8 @@ def load():
     for f in ("miann_server_create", "miann_server_submit", "miann_server_wait", "miann_server_get_stats"):
         getattr(L, f).restype = C.c_int
     for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
-              "miann_index_info", "miann_search", "miann_exact_knn", "miann_nearest_ghost", "miann_predictor_create",
+              "miann_index_info", "miann_search", "miann_exact_knn", "miann_index_delete",
+              "miann_index_append", "miann_build_next_map", "miann_nearest_ghost", "miann_predictor_create",
               "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step",
               "miann_predictor_train", "miann_predictor_predict"):
         getattr(L, f).restype = C.c_int
@@ -170,6 +174,20 @@ def _ptr(t):
 def _require_cuda(t, name):
     if t is not None and not t.is_cuda:
         raise MiannError(1, f"{name} must be a device tensor")
+
+
+def _require(t, name, dtypes, shape):
+    """Checks a device tensor's dtype (one of `dtypes`), shape (None = any size in that axis) and layout."""
+    if t is None:
+        return None
+    _require_cuda(t, name)
+    if t.dtype not in dtypes:
+        raise MiannError(1, f"{name}: dtype {t.dtype} not in {list(dtypes)}")
+    if t.dim() != len(shape) or any(w is not None and w != n for w, n in zip(shape, t.shape)):
+        raise MiannError(1, f"{name}: shape {tuple(t.shape)} does not match {shape}")
+    if not t.is_contiguous():
+        raise MiannError(1, f"{name} must be contiguous")
+    return t
 
 
 @dataclass
@@ -269,6 +287,8 @@ class Index:
         torch = _torch()
         _require_cuda(base, "base")
         base = base.contiguous()
+        if base.dtype not in (torch.float32, torch.uint8) or base.dim() != 2:
+            raise MiannError(1, f"base: need a 2-D float32 or uint8 tensor, got {base.dtype} {tuple(base.shape)}")
         in_dt = U8 if base.dtype == torch.uint8 else F32
         st = DTYPE_CODES[store] if store else in_dt
         bp = BuildParams(degree, knn_k0, num_shards, st, int(bool(dgs_table)), 0, seed & (2**64 - 1))
@@ -307,6 +327,28 @@ class Index:
         _check(load().miann_build_ghost(self._h, float(ratio), int(num_ghost), ghost_degree, seed & (2**64 - 1),
                                         _stream_ptr(stream)))
 
+    def build_next_map(self, itopk: int, max_iters: int, opts: SearchOptions | None = None, stream=None) -> None:
+        """Replaces every shard's inter-shard map by the lookup table built by search (top-1 of a search of each
+        node on the next shard)."""
+        p = (opts or SearchOptions()).cstruct()
+        _check(load().miann_build_next_map(self._h, itopk, max_iters, C.byref(p), _stream_ptr(stream)))
+
+    # -- dynamic updates (Sec. 6.2) ------------------------------------------
+    def delete(self, global_ids, stream=None) -> None:
+        """Deletion flags for these global ids (device int32/uint32 tensor): traversed, never returned."""
+        torch = _torch()
+        _require(global_ids, "global_ids", (torch.int32, torch.uint32), (None,))
+        _check(load().miann_index_delete(self._h, global_ids.data_ptr(), global_ids.shape[0], _stream_ptr(stream)))
+
+    def append(self, shard: int, vectors, ghost_seed: int = 5, stream=None) -> None:
+        """Inserts rows into one shard (the next global ids) and rebuilds that shard's graph, direction table,
+        inter-shard maps and the ghost shards (re-sampled from ghost_seed)."""
+        torch = _torch()
+        info = self.info()
+        _require(vectors, "vectors", (torch.uint8,) if self.in_dtype == U8 else (torch.float32,), (None, info["d"]))
+        _check(load().miann_index_append(self._h, shard, vectors.data_ptr(), vectors.shape[0],
+                                         ghost_seed & (2**64 - 1), _stream_ptr(stream)))
+
     # -- search -----------------------------------------------------------
     def search(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None,
                qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None,
@@ -317,16 +359,26 @@ class Index:
         phase_events: optional 4 raw hipEvent_t handles (ints or None), recorded before the ghost entry,
         before stage 0, after the last stage and after the merge; the call does not wait for them."""
         torch = _torch()
-        for n_, t_ in (("queries", queries), ("qkeys", qkeys), ("seeds", seeds), ("max_iters_per_query", max_iters_per_query)):
-            _require_cuda(t_, n_)
+        d = self.info()["d"]
+        qdt = torch.uint8 if self.in_dtype == U8 else torch.float32
+        _require_cuda(queries, "queries")
+        if queries.dtype != qdt or queries.dim() != 2 or queries.shape[1] != d:
+            raise MiannError(1, f"queries: need [nq, {d}] {qdt}, got {queries.dtype} {tuple(queries.shape)}")
+        queries = queries.contiguous()
         nq = queries.shape[0]
+        _require(qkeys, "qkeys", (torch.int64, torch.uint64), (nq,))
+        if seeds is not None:
+            _require(seeds, "seeds", (torch.int32, torch.uint32), (nq, None))
+        _require(max_iters_per_query, "max_iters_per_query", (torch.int32,), (nq,))
         opts = opts or SearchOptions()
+        ddt = torch.int32 if self.in_dtype == U8 else torch.float32
         if out is None:
             ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
-            dists = torch.empty((nq, k), dtype=torch.int32 if self.in_dtype == U8 else torch.float32,
-                                device=queries.device)
+            dists = torch.empty((nq, k), dtype=ddt, device=queries.device)
         else:
             ids, dists = out
+            _require(ids, "out ids", (torch.int32, torch.uint32), (nq, k))
+            _require(dists, "out dists", (ddt,), (nq, k))
         ctr = torch.empty((nq, NCTR), dtype=torch.int64, device=queries.device) if counters else None
         p = opts.cstruct(qkeys, seeds, max_iters_per_query)
         tbuf = None
@@ -466,20 +518,35 @@ class Server:
         h = C.c_void_p()
         _check(load().miann_server_create(index.handle, C.byref(cfg), C.byref(h)))
         self._h, self._index = h, index
+        self._d = index.info()["d"]
+        self._shapes = {}  # ticket -> (nq, k) of its request
 
     def submit(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None) -> int:
         """queries: numpy array [nq][d] (float32, or uint8 for u8 indices). Returns a ticket."""
         import numpy as np
-        q = np.ascontiguousarray(queries)
+        qdt = np.uint8 if self._index.in_dtype == U8 else np.float32
+        q = np.asarray(queries)
+        if q.dtype != qdt or q.ndim != 2 or q.shape[1] != self._d:
+            raise MiannError(1, f"queries: need [nq, {self._d}] {np.dtype(qdt)}, got {q.dtype} {q.shape}")
+        q = np.ascontiguousarray(q)
         p = (opts or SearchOptions()).cstruct()
         t = C.c_uint64()
         _check(load().miann_server_submit(self._h, q.ctypes.data, q.shape[0], k, itopk, max_iters, C.byref(p),
                                           C.byref(t)))
+        self._shapes[t.value] = (q.shape[0], k)
         return t.value
 
-    def wait(self, ticket: int, nq: int, k: int):
-        """Returns (ids uint32 [nq,k], dists [nq,k], latency_ms)."""
+    def wait(self, ticket: int, nq: int | None = None, k: int | None = None):
+        """Returns (ids uint32 [nq,k], dists [nq,k], latency_ms); the sizes are the request's own (nq and k, if
+        given, must match them)."""
         import numpy as np
+        if ticket not in self._shapes:
+            raise MiannError(1, f"unknown or already waited ticket {ticket}")
+        rq, rk = self._shapes[ticket]
+        if (nq is not None and nq != rq) or (k is not None and k != rk):
+            raise MiannError(1, f"ticket {ticket} is a request of {rq} queries with k = {rk}")
+        nq, k = rq, rk
+        del self._shapes[ticket]
         ids = np.empty((nq, k), np.uint32)
         dists = np.empty((nq, k), np.int32 if self._index.in_dtype == U8 else np.float32)
         lat = C.c_double()

@@ -222,4 +222,55 @@ hipError_t count_out_of_range(const uint32_t* ids, int64_t n, uint32_t limit, in
   return e;
 }
 
+// Unpadded copy: dst [n][d] from src rows of d_pad elements of `esize` bytes.
+__global__ void unpad_rows_kernel(const uint8_t* __restrict__ src, int64_t n, int row_src, int row_dst,
+                                  uint8_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * row_dst) return;
+  const int64_t r = i / row_dst, c = i % row_dst;
+  dst[i] = src[r * row_src + c];
+}
+
+hipError_t unpad_rows(const void* src, int64_t n, int d_pad, int esize, void* dst, int d, hipStream_t st) {
+  const int64_t total = n * (int64_t)d * esize;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(unpad_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, (const uint8_t*)src,
+                     n, d_pad * esize, d * esize, (uint8_t*)dst);
+  return hipGetLastError();
+}
+
+// Deletion flags (Sec. 6.2): dead[u] |= 1 when gmap[u] is one of the m sorted global ids.
+__global__ void mark_dead_kernel(const uint32_t* __restrict__ gmap, int64_t n, const uint32_t* __restrict__ ids,
+                                 int64_t m, uint8_t* __restrict__ dead) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= n) return;
+  const uint32_t g = gmap[u];
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (ids[mid] < g) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < m && ids[lo] == g) dead[u] = 1;
+}
+
+hipError_t mark_dead(const uint32_t* gmap, int64_t n, const uint32_t* sorted_ids, int64_t m, uint8_t* dead,
+                     hipStream_t st) {
+  if (n == 0 || m == 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_dead_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gmap, n, sorted_ids, m,
+                     dead);
+  return hipGetLastError();
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, int64_t n, uint8_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 }  // namespace miann

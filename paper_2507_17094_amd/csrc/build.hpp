@@ -18,5 +18,11 @@ hipError_t iota_u32(uint32_t* p, int64_t n, uint32_t base, hipStream_t st);
 hipError_t count_out_of_range(const uint32_t* ids, int64_t n, uint32_t limit, int allow_none, int64_t* host_bad,
                               hipStream_t st);
 hipError_t u8_to_f32(const uint8_t* src, int64_t total, float* dst, hipStream_t st);
+// dead[u] = 1 for every u whose gmap[u] is in sorted_ids[0..m) (other flags unchanged).
+hipError_t mark_dead(const uint32_t* gmap, int64_t n, const uint32_t* sorted_ids, int64_t m, uint8_t* dead,
+                     hipStream_t st);
+hipError_t fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
+// dst [n][d] (row length d) from src rows of d_pad elements, `esize` bytes each.
+hipError_t unpad_rows(const void* src, int64_t n, int d_pad, int esize, void* dst, int d, hipStream_t st);
 
 }  // namespace miann

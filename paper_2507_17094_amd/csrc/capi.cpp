@@ -64,6 +64,7 @@ struct Shard {
   uint32_t* g_graph = nullptr;// [R][deg_g]
   uint32_t* g_map = nullptr;  // [R]
   float* g_f32 = nullptr;     // [R][d_pad_f32] traversal values in f32 (MFMA dense entry)
+  uint8_t* dead = nullptr;    // [n] deletion flags, or null when nothing was deleted
 };
 
 }  // namespace
@@ -89,6 +90,8 @@ struct miann_index {
   int d_pad_in = 0;   // originals row length
   int d_pad_f32 = 0;  // f32 row length (rerank originals / MFMA copies)
   int64_t n_total = 0;
+  int knn_k0 = 0;           // K0 of the graph build (0 = 2 * degree), reused when a shard is rebuilt
+  uint64_t ghost_seed = 0;  // seed of the last ghost sample, reused when a shard is rebuilt
   std::vector<Shard> sh;
   DenseGhosts dg;  // all shards' ghosts, bf16-split, for the dense entry
   std::vector<void*> allocs;
@@ -103,6 +106,14 @@ struct miann_index {
     (ghost ? ghost_allocs : allocs).push_back(v);
     *p = (T*)v;
     return hipSuccess;
+  }
+  // Frees one array of `allocs` (the caller has synchronised the streams that used it).
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it == allocs.end()) return;
+    allocs.erase(it);
+    hipFree(p);
   }
   void free_ghost() {
     for (void* p : ghost_allocs) hipFree(p);
@@ -127,6 +138,7 @@ struct miann_index {
       o.store = x.store; o.scale = x.scale; o.orig = lp ? (const float*)x.orig : nullptr;
       o.graph = x.graph; o.sign = x.sign; o.gmap = x.gmap; o.next = x.next;
       o.g_store = x.g_store; o.g_scale = x.g_scale; o.g_graph = x.g_graph; o.g_map = x.g_map;
+      o.dead = x.dead;
       o.n = (uint32_t)x.n; o.R = (uint32_t)x.R;
     }
     hipError_t e = hipSuccess;
@@ -393,9 +405,12 @@ void miann_search_params_default(miann_search_params* sp) {
   sp->seed = 6;
 }
 
-miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
-                          int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
-                          int64_t* counters, void* stream) {
+}  // extern "C"
+
+// The search of miann_search (also run by the library on views of an index).
+miann_status miann_search_impl(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
+                               int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
+                               int64_t* counters, void* stream) {
   if (!ix) return fail(MIANN_EINVAL, "miann_search: null index");
   miann_search_params sp;
   if (spp) sp = *spp; else miann_search_params_default(&sp);
@@ -598,6 +613,14 @@ miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq
   return rc;
 }
 
+extern "C" {
+
+miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
+                          int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
+                          int64_t* counters, void* stream) {
+  return miann_search_impl(ix, queries, nq, k, itopk, max_iters, spp, ids, dists, counters, stream);
+}
+
 }  // extern "C"
 
 namespace {
@@ -627,6 +650,8 @@ miann_status gemm_rows(miann_index* ix, const Shard& h, Temps& tmp, const float*
   *out = f;
   return MIANN_OK;
 }
+
+miann_status build_ghosts(miann_index* ix, const std::vector<int64_t>& R, int deg_g, uint64_t seed, hipStream_t st);
 
 // Exact K0-NN of `n` rows (f32 copy `xf`, raw `xr`) among themselves, pruned to `deg`.
 miann_status knn_graph(miann_index* ix, const float* xf, const void* xr, int64_t n, int deg, int K0, uint32_t* graph,
@@ -660,6 +685,7 @@ miann_status miann_build_graph(const void* base, int64_t n, int32_t d, int32_t i
   miann_index* ix = new miann_index();
   init_dims(ix, d, in_dtype, bp->store_dtype, bp->degree, 0, bp->dgs_table);
   ix->S = S;
+  ix->knn_k0 = K0;
   ix->n_total = n;
   ix->sh.resize(S);
   {
@@ -732,10 +758,20 @@ miann_status miann_build_ghost(miann_index* ix, double ratio, int64_t num_ghost,
       return fail(MIANN_EINVAL, "miann_build_ghost: shard %d: %lld ghosts invalid (need 2 * ghost_degree < R <= n)", s,
                     (long long)R[s]);
   }
-  hipStream_t st = (hipStream_t)stream;
+  return build_ghosts(ix, R, deg_g, seed, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The ghost shards of every shard with R[s] ghosts (Sec. 3.2.2): a SplitMix64-keyed sample without replacement,
+// its own exact-k-NN graph and the ghost store, then the dense entry's arrays.
+miann_status build_ghosts(miann_index* ix, const std::vector<int64_t>& R, int deg_g, uint64_t seed, hipStream_t st) {
   hipStreamSynchronize(st);
   ix->free_ghost();
   ix->deg_g = deg_g;
+  ix->ghost_seed = seed;
   miann_status rc = MIANN_OK;
   for (int s = 0; s < ix->S && rc == MIANN_OK; s++) {
     Shard& h = ix->sh[s];
@@ -779,6 +815,10 @@ miann_status miann_build_ghost(miann_index* ix, double ratio, int64_t num_ghost,
   if (rc == MIANN_OK && e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_ghost: %s", hipGetErrorString(e));
   return rc;
 }
+
+}  // namespace
+
+extern "C" {
 
 miann_status miann_exact_knn(const miann_index* cix, const void* queries, int64_t nq, int32_t k, uint32_t* ids,
                              void* dists, void* stream) {
@@ -844,6 +884,192 @@ miann_status miann_nearest_ghost(const miann_index* ix, int32_t shard, const voi
   HIP_TRY(dense_entry(ix->store_dtype, vectors, n, ix->d, nullptr, 1, 0, 0, h.g_f32, h.g_store, h.g_scale, nullptr,
                       h.R, ix->d_pad, ix->d_pad_f32, 1, keys, st));
   HIP_TRY(keys_to_ids(keys, n, 1, 0, ghost_idx, 1, st));
+  return MIANN_OK;
+}
+
+
+miann_status miann_index_delete(miann_index* ix, const uint32_t* global_ids, int64_t m, void* stream) {
+  if (!ix) return fail(MIANN_EINVAL, "miann_index_delete: null index");
+  if (m < 0 || (m > 0 && !global_ids)) return fail(MIANN_EINVAL, "miann_index_delete: need m >= 0 and ids");
+  if (m == 0) return MIANN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Temps tmp(st);
+  uint32_t* ids = nullptr;
+  HIP_TRY(tmp.get(&ids, (size_t)m * 4));
+  HIP_TRY(hipMemcpyAsync(ids, global_ids, (size_t)m * 4, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(sort_u32(ids, m, st));
+  bool fresh = false;
+  for (int s = 0; s < ix->S; s++) {
+    Shard& h = ix->sh[s];
+    if (!h.dead) {
+      HIP_TRY(ix->alloc(&h.dead, (size_t)h.n));
+      HIP_TRY(fill_u8(h.dead, h.n, 0, st));
+      fresh = true;
+    }
+    HIP_TRY(mark_dead(h.gmap, h.n, ids, m, h.dead, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (fresh) HIP_TRY(ix->refresh(st));
+  return MIANN_OK;
+}
+
+miann_status miann_index_append(miann_index* ix, int32_t shard, const void* vectors, int64_t n_new, uint64_t ghost_seed,
+                                void* stream) {
+  if (!ix) return fail(MIANN_EINVAL, "miann_index_append: null index");
+  if (shard < 0 || shard >= ix->S) return fail(MIANN_EINVAL, "miann_index_append: shard %d out of range", shard);
+  if (n_new < 0 || (n_new > 0 && !vectors)) return fail(MIANN_EINVAL, "miann_index_append: need n >= 0 and rows");
+  if (n_new == 0) return MIANN_OK;
+  if (ix->n_total + n_new >= (1ll << 30))
+    return fail(MIANN_EINVAL, "miann_index_append: %lld nodes would exceed 2^30 - 1", (long long)(ix->n_total + n_new));
+  const int K0 = ix->knn_k0 ? ix->knn_k0 : 2 * ix->deg;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  Shard& h = ix->sh[shard];
+  const int64_t n0 = h.n, n = n0 + n_new;
+  if (K0 >= n) return fail(MIANN_EINVAL, "miann_index_append: shard too small for K0 = %d", K0);
+  const int ein = esize_of(ix->in_dtype);
+  const bool lp = lowp(ix->store_dtype);
+  const size_t row_in = (size_t)ix->d_pad_in * ein, row_st = (size_t)ix->d_pad * esize_of(ix->store_dtype);
+  Shard nh = h;  // the rebuilt shard; the old arrays are released once it is complete
+  nh.n = n;
+  hipError_t e = ix->alloc(&nh.orig, (size_t)n * row_in);
+  if (e == hipSuccess) e = hipMemcpyAsync(nh.orig, h.orig, (size_t)n0 * row_in, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = pad_rows(vectors, n_new, ix->d, ein, (char*)nh.orig + n0 * row_in, ix->d_pad_in, nullptr, st);
+  if (e == hipSuccess && lp) {
+    // per-vector quantisation: the old rows' codes stay valid
+    e = ix->alloc(&nh.store, (size_t)n * row_st);
+    if (e == hipSuccess) e = ix->alloc(&nh.scale, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(nh.store, h.store, (size_t)n0 * row_st, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(nh.scale, h.scale, (size_t)n0 * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = quantize((const float*)vectors, n_new, ix->d, ix->store_dtype, (char*)nh.store + n0 * row_st, ix->d_pad,
+                   nh.scale + n0, nullptr, st);
+  } else if (e == hipSuccess) {
+    nh.store = nh.orig;
+  }
+  // the new rows take the next global ids
+  if (e == hipSuccess) e = ix->alloc(&nh.gmap, (size_t)n * 4);
+  if (e == hipSuccess) e = hipMemcpyAsync(nh.gmap, h.gmap, (size_t)n0 * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = iota_u32(nh.gmap + n0, n_new, (uint32_t)ix->n_total, st);
+  if (e == hipSuccess && h.dead) {
+    e = ix->alloc(&nh.dead, (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(nh.dead, h.dead, (size_t)n0, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = fill_u8(nh.dead + n0, n_new, 0, st);
+  }
+  if (e == hipSuccess) e = ix->alloc(&nh.graph, (size_t)n * ix->deg * 4);
+  if (e == hipSuccess && ix->dgs) e = ix->alloc(&nh.sign, (size_t)n * ix->W * ix->deg * 4);
+  if (e != hipSuccess) return fail(MIANN_EDEVICE, "miann_index_append: %s", hipGetErrorString(e));
+  miann_status rc = MIANN_OK;
+  {
+    Temps tmp(st);
+    const float* xf = nullptr;
+    // the shard's graph and direction table over all its rows (Sec. 6.2: an insertion rebuilds the affected shard)
+    if ((rc = gemm_rows(ix, nh, tmp, &xf))) return rc;
+    if ((rc = knn_graph(ix, xf, nh.orig, n, ix->deg, K0, nh.graph, st))) return rc;
+    if (ix->dgs) HIP_TRY(sign_table(nh.orig, ix->in_dtype, n, ix->d, ix->d_pad_in, nh.graph, ix->deg, nh.sign, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  // swap in the rebuilt shard, then release the arrays it replaced
+  Shard old = h;
+  h = nh;
+  ix->n_total += n_new;
+  ix->release(old.orig);
+  if (lp) { ix->release(old.store); ix->release(old.scale); }
+  ix->release(old.gmap);
+  ix->release(old.dead);
+  ix->release(old.graph);
+  ix->release(old.sign);
+  // inter-shard maps into and out of the shard (Sec. 3.1.2), exact 1-NN as at build time
+  if (ix->S > 1) {
+    Temps tmp(st);
+    std::vector<const float*> xf(ix->S, nullptr);
+    for (int t : {(shard + ix->S - 1) % ix->S, shard, (shard + 1) % ix->S})
+      if (!xf[t] && (rc = gemm_rows(ix, ix->sh[t], tmp, &xf[t]))) return rc;
+    for (int s : {(shard + ix->S - 1) % ix->S, shard}) {
+      Shard& a = ix->sh[s];
+      const Shard& b = ix->sh[(s + 1) % ix->S];
+      uint64_t* keys = nullptr;
+      uint32_t* next = nullptr;
+      HIP_TRY(tmp.get(&keys, (size_t)a.n * 8));
+      HIP_TRY(ix->alloc(&next, (size_t)a.n * 4));
+      HIP_TRY(knn_exact(xf[s], a.n, xf[(s + 1) % ix->S], b.n, ix->d_pad_in, ix->d, ix->in_dtype, a.orig, ix->d_pad_in,
+                        b.orig, nullptr, ix->d_pad_in, 1, 0, nullptr, keys, st));
+      HIP_TRY(keys_to_ids(keys, a.n, 1, 0, next, 1, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      ix->release(a.next);
+      a.next = next;
+    }
+  }
+  // ghost shards: the same counts, sampled with ghost_seed (the seed of the earlier sample keeps the other
+  // shards' samples unchanged)
+  if (h.R > 0) {
+    std::vector<int64_t> R(ix->S);
+    for (int s = 0; s < ix->S; s++) R[s] = ix->sh[s].R;
+    if (R[shard] > n) R[shard] = n;
+    return build_ghosts(ix, R, ix->deg_g, ghost_seed, st);
+  }
+  hipError_t e2 = ix->refresh(st);
+  if (e2 != hipSuccess) return fail(MIANN_EDEVICE, "miann_index_append: %s", hipGetErrorString(e2));
+  return MIANN_OK;
+}
+
+miann_status miann_build_next_map(miann_index* ix, int32_t itopk, int32_t max_iters, const miann_search_params* spp,
+                                  void* stream) {
+  if (!ix) return fail(MIANN_EINVAL, "miann_build_next_map: null index");
+  if (ix->S < 2) return fail(MIANN_EINVAL, "miann_build_next_map: needs S >= 2 shards");
+  miann_search_params sp;
+  if (spp) sp = *spp; else miann_search_params_default(&sp);
+  if (sp.entry != MIANN_ENTRY_RANDOM && sp.entry != MIANN_ENTRY_GHOST_GRAPH)
+    return fail(MIANN_EUNSUPPORTED, "miann_build_next_map: entry must be random or the ghost graph");
+  if (sp.qkeys || sp.seeds || sp.max_iters_per_query || sp.phase_ms || sp.phase_events)
+    return fail(MIANN_EINVAL, "miann_build_next_map: qkeys, seeds, per-query budgets and timing must be NULL");
+  sp.ppe = 0;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  const int ein = esize_of(ix->in_dtype);
+  std::vector<uint32_t*> nexts(ix->S, nullptr);
+  miann_status rc = MIANN_OK;
+  for (int s = 0; s < ix->S && rc == MIANN_OK; s++) {
+    const Shard& h = ix->sh[s];
+    // shard (s+1) mod S alone, results in its local ids, no deletion flags
+    miann_index v;
+    v.S = 1;
+    v.d = ix->d; v.deg = ix->deg; v.deg_g = ix->deg_g; v.W = ix->W;
+    v.store_dtype = ix->store_dtype; v.in_dtype = ix->in_dtype; v.dgs = ix->dgs;
+    v.d_pad = ix->d_pad; v.d_pad_in = ix->d_pad_in; v.d_pad_f32 = ix->d_pad_f32;
+    Shard nx = ix->sh[(s + 1) % ix->S];
+    nx.gmap = nullptr;
+    nx.next = nullptr;
+    nx.dead = nullptr;
+    v.n_total = nx.n;
+    v.sh.push_back(nx);
+    hipError_t e = v.refresh(st);
+    Temps tmp(st);
+    void* q = nullptr;
+    void* dist = nullptr;
+    if (e == hipSuccess) e = tmp.get(&q, (size_t)h.n * ix->d * ein);
+    if (e == hipSuccess) e = tmp.get(&dist, (size_t)h.n * 4);
+    if (e == hipSuccess) e = unpad_rows(h.orig, h.n, ix->d_pad_in, ein, q, ix->d, st);
+    if (e == hipSuccess) e = ix->alloc(&nexts[s], (size_t)h.n * 4);
+    if (e != hipSuccess) { rc = fail(MIANN_EDEVICE, "miann_build_next_map: %s", hipGetErrorString(e)); break; }
+    // every node of shard s is a query keyed by its local id; the top-1 is its entry in the table
+    rc = miann_search_impl(&v, q, h.n, 1, itopk, max_iters, &sp, nexts[s], dist, nullptr, st);
+    if (rc == MIANN_OK) {
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_next_map: %s", hipGetErrorString(e));
+    }
+    v.sh.clear();  // the view borrows the shard's arrays
+  }
+  if (rc != MIANN_OK) {
+    hipStreamSynchronize(st);
+    for (uint32_t* p : nexts) ix->release(p);
+    return rc;
+  }
+  for (int s = 0; s < ix->S; s++) {
+    ix->release(ix->sh[s].next);
+    ix->sh[s].next = nexts[s];
+  }
+  HIP_TRY(ix->refresh(st));
   return MIANN_OK;
 }
 

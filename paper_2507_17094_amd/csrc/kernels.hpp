@@ -25,6 +25,7 @@ struct ShardDev {
   const float* g_scale;     // [R]
   const uint32_t* g_graph;  // [R][deg_g]
   const uint32_t* g_map;    // [R] ghost -> local id
+  const uint8_t* dead;      // [n] deletion flags (traversed, never returned), or nullptr
   uint32_t n, R;
 };
 

@@ -709,6 +709,24 @@ void stage_kernel(StageArgs a) {
     a.hand_out[(size_t)q * a.f + S.lane] = key != kDummy ? sh.next[key_id(key)] : kNone;
   }
   wsync();
+  if (sh.dead) {
+    // deletion flags (Sec. 6.2): deleted nodes served the traversal and the hand-off above; the stage result
+    // is taken from the live entries of p, in p order
+    int nl = 0;
+    for (int i0 = 0; i0 < a.l; i0 += 64) {
+      const int i = i0 + S.lane;
+      const uint64_t key = i < a.l ? S.pk[i] : kDummy;
+      const bool live = key != kDummy && !as_global(sh.dead)[key_id(key)];
+      const uint64_t m = ballot(live);
+      if (live) S.pk_alt[nl + lanes_below(m)] = key;
+      nl += __popcll(m);
+    }
+    for (int i = nl + S.lane; i < a.l; i += 64) S.pk_alt[i] = kDummy;
+    wsync();
+    uint64_t* tp = S.pk;
+    S.pk = S.pk_alt;
+    S.pk_alt = tp;
+  }
   if (a.lowp) {
     int m = a.rerank_m * a.k;
     if (m > a.l) m = a.l;
