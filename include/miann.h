@@ -250,6 +250,27 @@ miann_status miann_search(const miann_index* idx, const void* queries_dev, int64
                           int32_t max_iters, const miann_search_params* sp, uint32_t* ids_dev, void* dists_dev,
                           int64_t* counters_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as miann_search, with the same arguments, results and errors, whose
+ * temporary buffers (path-extension hand-off, per-stage results, the dense
+ * entry's query split, minima, bounds and candidate masks) all come from one
+ * static device array of MIANN_NOALLOC_SCRATCH_MB MiB per GPU, held from the
+ * library's load until the process ends. The call allocates nothing: no
+ * hipMalloc, hipFree or pool allocation. A batch whose buffers do not fit
+ * (about 1 KB per query and stage result, plus the dense entry's per-query
+ * rows; the dense entry processes its queries in chunks that fit what is
+ * left) fails with EINVAL before anything is launched; phase_ms must be NULL
+ * (phase_events may be used). Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams, or two host threads) race and
+ * must be serialised by the caller. */
+#define MIANN_NOALLOC_SCRATCH_MB 64
+miann_status miann_search_noalloc(const miann_index* idx, const void* queries_dev, int64_t nq, int32_t k,
+                                  int32_t itopk, int32_t max_iters, const miann_search_params* sp, uint32_t* ids_dev,
+                                  void* dists_dev, int64_t* counters_dev, void* stream);
+/* Bytes of the array miann_search_noalloc carves its buffers from. */
+size_t miann_noalloc_scratch_bytes(void);
+
 /* The shard-to-shard lookup table built by search, as the paper builds it
  * (Sec. 4): every node u of shard s is a query of a search on shard (s+1) mod
  * S alone (its graph, direction table, store and ghost shard; deletion flags

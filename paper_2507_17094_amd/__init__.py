@@ -25,7 +25,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNS
 
 EXPORTS = [
     "miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard", "miann_index_info",
-    "miann_index_free", "miann_search_params_default", "miann_search", "miann_exact_knn", "miann_last_error",
+    "miann_index_free", "miann_search_params_default", "miann_search", "miann_search_noalloc",
+    "miann_noalloc_scratch_bytes", "miann_exact_knn", "miann_last_error",
     "miann_version", "miann_nearest_ghost", "miann_predictor_create", "miann_predictor_free",
     "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step", "miann_predictor_train",
     "miann_predictor_predict", "miann_server_config_default", "miann_server_create", "miann_server_submit",
@@ -115,6 +116,9 @@ def load():
     L.miann_search_params_default.argtypes = [C.POINTER(SearchParams)]
     L.miann_search_params_default.restype = None
     L.miann_search.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
+    L.miann_search_noalloc.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
+    L.miann_noalloc_scratch_bytes.argtypes = []
+    L.miann_noalloc_scratch_bytes.restype = C.c_size_t
     L.miann_exact_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     L.miann_index_delete.argtypes = [vp, vp, i64, vp]
     L.miann_index_append.argtypes = [vp, i32, vp, i64, u64, vp]
@@ -142,7 +146,7 @@ def load():
     for f in ("miann_server_create", "miann_server_submit", "miann_server_wait", "miann_server_get_stats"):
         getattr(L, f).restype = C.c_int
     for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
-              "miann_index_info", "miann_search", "miann_exact_knn", "miann_index_delete",
+              "miann_index_info", "miann_search", "miann_search_noalloc", "miann_exact_knn", "miann_index_delete",
               "miann_index_append", "miann_build_next_map", "miann_nearest_ghost", "miann_predictor_create",
               "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step",
               "miann_predictor_train", "miann_predictor_predict"):
@@ -352,12 +356,14 @@ class Index:
     # -- search -----------------------------------------------------------
     def search(self, queries, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None,
                qkeys=None, seeds=None, max_iters_per_query=None, counters: bool = False, out=None, stream=None,
-               phase_ms=None, phase_events=None):
+               phase_ms=None, phase_events=None, noalloc: bool = False):
         """Returns (ids [nq,k] int32 view of uint32, dists [nq,k] float32|int32[, counters [nq,8] int64]).
         phase_ms: optional list that receives per-launch milliseconds [dense, stage 0..S-1, merge]
         (the call then synchronises the stream).
         phase_events: optional 4 raw hipEvent_t handles (ints or None), recorded before the ghost entry,
-        before stage 0, after the last stage and after the merge; the call does not wait for them."""
+        before stage 0, after the last stage and after the merge; the call does not wait for them.
+        noalloc: call miann_search_noalloc (temporary buffers from the library's static device array; pass
+        `out` as well to keep the whole call free of allocations)."""
         torch = _torch()
         d = self.info()["d"]
         qdt = torch.uint8 if self.in_dtype == U8 else torch.float32
@@ -391,8 +397,9 @@ class Index:
                 raise ValueError("phase_events needs 4 event handles")
             evbuf = (C.c_void_p * 4)(*[e or None for e in phase_events])
             p.phase_events = C.cast(evbuf, C.c_void_p)
-        _check(load().miann_search(self._h, queries.data_ptr(), nq, k, itopk, max_iters, C.byref(p), ids.data_ptr(),
-                                   dists.data_ptr(), _ptr(ctr), _stream_ptr(stream)))
+        fn = load().miann_search_noalloc if noalloc else load().miann_search
+        _check(fn(self._h, queries.data_ptr(), nq, k, itopk, max_iters, C.byref(p), ids.data_ptr(), dists.data_ptr(),
+                  _ptr(ctr), _stream_ptr(stream)))
         if tbuf is not None:
             phase_ms[:] = list(tbuf)
         return (ids, dists, ctr) if counters else (ids, dists)

@@ -407,10 +407,11 @@ void miann_search_params_default(miann_search_params* sp) {
 
 }  // extern "C"
 
-// The search of miann_search (also run by the library on views of an index).
+// The search of miann_search. With `ext` (device memory of ext_bytes, 256-byte aligned) every temporary
+// buffer is carved from it and nothing is allocated; the call fails with EINVAL if it does not fit.
 miann_status miann_search_impl(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
                                int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
-                               int64_t* counters, void* stream) {
+                               int64_t* counters, void* stream, void* ext, size_t ext_bytes) {
   if (!ix) return fail(MIANN_EINVAL, "miann_search: null index");
   miann_search_params sp;
   if (spp) sp = *spp; else miann_search_params_default(&sp);
@@ -536,13 +537,27 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
     off_dense = total;
     total += (size_t)nq * ix->S * t_seeds * 8;
   }
+  total = (total + 255) & ~(size_t)255;
+  // a caller's buffer: the search's part first, the dense entry's after it
+  const int start_only = ix->S > 1 && sp.ppe && !sp.ghost_every_stage;
+  if (ext) {
+    if (sp.phase_ms) return fail(MIANN_EINVAL, "miann_search: phase_ms creates events; use phase_events");
+    size_t need = total;
+    if (sp.entry == MIANN_ENTRY_GHOST_DENSE)
+      need += dense_entry_min_scratch(ix->store_dtype, nq, ix->d_pad, ix->d_pad_f32, ix->S, start_only, ix->dg);
+    if (need > ext_bytes)
+      return fail(MIANN_EINVAL, "miann_search: %lld queries need %zu bytes of scratch, more than the %zu available",
+                  (long long)nq, need, ext_bytes);
+  }
   ScratchLease lease;
-  if (total) HIP_TRY(scratch_lease(kSlotSearch, total, st, &lease));
+  if (ext) lease.p = ext;
+  else if (total) HIP_TRY(scratch_lease(kSlotSearch, total, st, &lease));
   struct LeaseGuard {
     const ScratchLease& l;
     hipStream_t st;
-    ~LeaseGuard() { scratch_release(kSlotSearch, l, st); }
-  } lease_guard{lease, st};
+    bool own;
+    ~LeaseGuard() { if (own) scratch_release(kSlotSearch, l, st); }
+  } lease_guard{lease, st, ext == nullptr};
   scratch = lease.p;
   char* sb = (char*)scratch;
   miann_status rc = MIANN_OK;
@@ -569,9 +584,9 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
     a.dense = (const uint64_t*)(sb + off_dense);
     mark(0, 0);
     // dense seeds are needed for the start shard only, unless every stage takes a ghost entry
-    const int start_only = ix->S > 1 && sp.ppe && !sp.ghost_every_stage;
     hipError_t e = dense_entry_split(ix->store_dtype, queries, nq, ix->d, ix->d_pad, ix->d_pad_f32, sp.qkeys, ix->S,
-                                     start_only, ix->dg, t_seeds, (uint64_t*)(sb + off_dense), st);
+                                     start_only, ix->dg, t_seeds, (uint64_t*)(sb + off_dense), st,
+                                     ext ? sb + total : nullptr, ext ? ext_bytes - total : 0);
     if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_search: dense entry: %s", hipGetErrorString(e));
     mark(0, 1);
   }
@@ -618,7 +633,7 @@ extern "C" {
 miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
                           int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
                           int64_t* counters, void* stream) {
-  return miann_search_impl(ix, queries, nq, k, itopk, max_iters, spp, ids, dists, counters, stream);
+  return miann_search_impl(ix, queries, nq, k, itopk, max_iters, spp, ids, dists, counters, stream, nullptr, 0);
 }
 
 }  // extern "C"
@@ -1053,7 +1068,7 @@ miann_status miann_build_next_map(miann_index* ix, int32_t itopk, int32_t max_it
     if (e == hipSuccess) e = ix->alloc(&nexts[s], (size_t)h.n * 4);
     if (e != hipSuccess) { rc = fail(MIANN_EDEVICE, "miann_build_next_map: %s", hipGetErrorString(e)); break; }
     // every node of shard s is a query keyed by its local id; the top-1 is its entry in the table
-    rc = miann_search_impl(&v, q, h.n, 1, itopk, max_iters, &sp, nexts[s], dist, nullptr, st);
+    rc = miann_search_impl(&v, q, h.n, 1, itopk, max_iters, &sp, nexts[s], dist, nullptr, st, nullptr, 0);
     if (rc == MIANN_OK) {
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_next_map: %s", hipGetErrorString(e));

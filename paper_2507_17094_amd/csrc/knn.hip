@@ -1336,18 +1336,51 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   }
 }
 
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+// Bytes of the per-query buffers (split query rows, norms, raw rows, start-shard list, counter).
+size_t dense_query_bytes(int store_dt, int64_t nq, int d_pad, int dk) {
+  const size_t raw = store_dt == DT_U8 ? 1 : 4;
+  return 2 * al256((size_t)nq * dk * 2) + al256((size_t)nq * 4) + al256((size_t)nq * d_pad * raw) +
+         al256((size_t)nq * 4) + 256;
+}
+// Scratch bytes per row of a chunk in the pass over shards [s0, s1): 8-column minima, bounds and candidate masks.
+size_t dense_row_bytes(const DenseGhosts& G, int s0, int s1) {
+  int64_t ntmax = 0;
+  for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
+  const int64_t ncols = G.off[s1] - G.off[s0];
+  return (size_t)(ncols / DG) * 4 + (size_t)(s1 - s0) * (4 + (size_t)(2 * ntmax) * 4);
+}
+}  // namespace
+
+size_t dense_entry_min_scratch(int store_dt, int64_t nq, int d_pad, int dk, int S, int start_only,
+                               const DenseGhosts& G) {
+  size_t per_row = 0;
+  const int npass = start_only ? S : 1;
+  for (int ps = 0; ps < npass; ps++) {
+    const int s0 = start_only ? ps : 0, s1 = start_only ? ps + 1 : S;
+    per_row = std::max(per_row, dense_row_bytes(G, s0, s1));
+  }
+  return dense_query_bytes(store_dt, nq, d_pad, dk) + (size_t)dense_block_rows(dk) * per_row + 4096;
+}
+
 hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int d, int d_pad, int dk,
                              const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G, int t, uint64_t* out,
-                             hipStream_t st) {
+                             hipStream_t st, void* ext, size_t ext_bytes) {
   if (nq == 0) return hipSuccess;
   const int qdt = store_dt == DT_U8 ? DT_U8 : DT_F32;
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  auto al = al256;
   const size_t sz_qb = al((size_t)nq * dk * 2), sz_qn = al((size_t)nq * 4);
   const size_t sz_qraw = al((size_t)nq * d_pad * (qdt == DT_U8 ? 1 : 4));
   const size_t sz_list = al((size_t)nq * 4), sz_cnt = 256;
   const size_t total = 2 * sz_qb + sz_qn + sz_qraw + sz_list + sz_cnt;
+  // a caller's buffer holds the query buffers first and the chunk work area after them
+  if (ext && ext_bytes < dense_entry_min_scratch(store_dt, nq, d_pad, dk, S, start_only, G))
+    return hipErrorInvalidValue;
   ScratchLease lq;
-  hipError_t e = scratch_lease(kSlotDenseQueries, total, st, &lq);
+  hipError_t e = hipSuccess;
+  if (ext) lq.p = ext;
+  else e = scratch_lease(kSlotDenseQueries, total, st, &lq);
   if (e != hipSuccess) return e;
   char* buf = (char*)lq.p;
   char* p = buf;
@@ -1380,14 +1413,17 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     int64_t ntmax = 0;
     for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
     const int64_t nht = 2 * ntmax;
-    const size_t per_row = (size_t)(ncols / DG) * 4 + (size_t)nseg * (4 + (size_t)nht * 4);
+    const size_t per_row = dense_row_bytes(G, s0, s1);
     const int brows = dense_block_rows(dk);
-    int64_t chunk = ((int64_t)1 << 29) / (int64_t)per_row;  // at most 512 MB of scratch
+    // at most 512 MB of scratch, or what the caller's buffer leaves after the query buffers
+    const size_t work_cap = ext ? ext_bytes - total - 4096 : ((size_t)1 << 29);
+    int64_t chunk = (int64_t)(work_cap / per_row);
     chunk = chunk < brows ? brows : chunk / brows * brows;
     if (chunk > (nq + brows - 1) / brows * brows) chunk = (nq + brows - 1) / brows * brows;
     char* wb = nullptr;
     ScratchLease lw;
-    e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
+    if (ext) lw.p = buf + total;
+    else e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
     wb = (char*)lw.p;
     if (e != hipSuccess) break;
     uint32_t* cmask = (uint32_t*)wb;
@@ -1430,9 +1466,9 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       }
       e = hipGetLastError();
     }
-    scratch_release(kSlotDenseWork, lw, st);
+    if (!ext) scratch_release(kSlotDenseWork, lw, st);
   }
-  scratch_release(kSlotDenseQueries, lq, st);
+  if (!ext) scratch_release(kSlotDenseQueries, lq, st);
   return e;
 }
 

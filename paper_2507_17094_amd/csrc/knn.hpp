@@ -44,9 +44,14 @@ hipError_t split_rows(const float* x, int64_t n, int64_t n_pad, int dk, uint16_t
 // Dense entry of every query on every shard (start_only = 0) or on its start shard (q_key mod S) only:
 // the exact top-t ghosts of the shard by (dist, id), as keys (dist bits << 32 | local node id) in
 // out[(q * S + s) * t + i].
+// Scratch comes from the stream's kept blocks, or from `ext` (ext_bytes >= dense_entry_min_scratch, else
+// hipErrorInvalidValue) when the caller must not allocate: rows are then processed in chunks that fit it.
 hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int d, int d_pad, int dk,
                              const uint64_t* qkeys, int S, int start_only, const DenseGhosts& G, int t, uint64_t* out,
-                             hipStream_t st);
+                             hipStream_t st, void* ext = nullptr, size_t ext_bytes = 0);
+// Smallest caller buffer dense_entry_split accepts for these sizes (one chunk of block rows).
+size_t dense_entry_min_scratch(int store_dt, int64_t nq, int d_pad, int dk, int S, int start_only,
+                               const DenseGhosts& G);
 
 // Exact k-NN of A rows against B rows by MFMA tiles + direct-form rescoring.
 //   A_f32 [na][dpf], B_f32 [nb][dpf]: f32 copies for the GEMM-form selection.
