@@ -240,7 +240,8 @@ void miann_search_params_default(miann_search_params* sp);
  *   queries_dev : device [nq][d], F32 for float indices, U8 for u8 indices.
  *   k, itopk    : 1 <= k <= itopk <= 512; low-precision stores need itopk >= rerank_mult * k
  *                 unless rerank_mult * k is capped by itopk.
- *   max_iters   : T >= 0 iterations per stage.
+ *   max_iters   : T >= 0 iterations per stage. T = 0 is valid: each stage returns its entry candidates
+ *                 (seeds, hand-off or random starts) ordered, without expanding any.
  *   ids_dev     : device [nq][k] global ids, 0xFFFFFFFF where fewer than k were found.
  *   dists_dev   : device [nq][k] float (or int32 for u8), +inf / INT32_MAX padding.
  *   counters_dev: device [nq][MIANN_NCTR] int64, or NULL.
@@ -343,6 +344,17 @@ miann_status miann_predictor_predict(const miann_predictor* p, const float* x_de
                                      uint32_t* seeds_dev, int32_t* iters_dev, float* conf_dev,
                                      uint32_t* top_entry_dev, void* stream);
 
+/* Training labels of the predictor on a one-shard float index, all on the
+ * device: iters_dev [n] = the last iteration in which the top-k of the search
+ * (k, itopk, max_iters, sp: normally the ghost entry) changed, budget_dev [n]
+ * = log(1 + iters), and entry_dev [n] = the ghost index nearest to the exact
+ * nearest node of the query (exact 1-NN, then the nearest ghost). queries_dev
+ * [n][d] float32. EINVAL for S != 1, ESTATE without ghosts. Enqueues on
+ * `stream`. */
+miann_status miann_predictor_labels(const miann_index* idx, const float* queries_dev, int64_t n, int32_t k,
+                                    int32_t itopk, int32_t max_iters, const miann_search_params* sp, int32_t* entry_dev,
+                                    float* budget_dev, int32_t* iters_dev, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching over a resident index                       */
 /* ------------------------------------------------------------------------ */
@@ -363,7 +375,8 @@ typedef struct {
   int32_t reserved;
   int64_t max_batch_queries;    /* queries coalesced into one launch, default 8192 */
   int64_t max_inflight_queries; /* admission limit on queries on the device, default 65536 */
-  int64_t memory_budget_bytes;  /* admission limit on device bytes of in-flight batches, default 1 GiB */
+  int64_t memory_budget_bytes;  /* admission limit on device bytes of in-flight batches (staging buffers plus
+                                   each batch's search temporaries), default 1 GiB */
 } miann_server_config;
 
 typedef struct {
@@ -388,6 +401,14 @@ miann_status miann_server_wait(miann_server* srv, uint64_t ticket, uint32_t* ids
 miann_status miann_server_get_stats(miann_server* srv, miann_server_stats* out);
 /* Completes every queued request, then frees the server. */
 void miann_server_destroy(miann_server* srv);
+
+/* A search keeps its temporary buffers with the stream it ran on, so that
+ * back-to-back calls on one stream allocate nothing (each block grows in
+ * powers of two to the largest batch seen on that stream). This returns the
+ * blocks kept for `stream` on the current device to the library's pool, in
+ * stream order; call it before destroying a stream that searched, or to trim
+ * memory. miann_server_destroy does it for its own streams. */
+miann_status miann_release_scratch(void* stream);
 
 /* Thread-local text of the last error (empty string if none). */
 const char* miann_last_error(void);

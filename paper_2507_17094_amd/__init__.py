@@ -123,6 +123,8 @@ def load():
     L.miann_index_delete.argtypes = [vp, vp, i64, vp]
     L.miann_index_append.argtypes = [vp, i32, vp, i64, u64, vp]
     L.miann_build_next_map.argtypes = [vp, i32, i32, C.POINTER(SearchParams), vp]
+    L.miann_release_scratch.argtypes = [vp]
+    L.miann_predictor_labels.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.miann_last_error.restype = C.c_char_p
     L.miann_version.restype = C.c_char_p
     L.miann_nearest_ghost.argtypes = [vp, i32, vp, i64, vp, vp]
@@ -147,7 +149,7 @@ def load():
         getattr(L, f).restype = C.c_int
     for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
               "miann_index_info", "miann_search", "miann_search_noalloc", "miann_exact_knn", "miann_index_delete",
-              "miann_index_append", "miann_build_next_map", "miann_nearest_ghost", "miann_predictor_create",
+              "miann_index_append", "miann_build_next_map", "miann_release_scratch", "miann_predictor_labels", "miann_nearest_ghost", "miann_predictor_create",
               "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step",
               "miann_predictor_train", "miann_predictor_predict"):
         getattr(L, f).restype = C.c_int

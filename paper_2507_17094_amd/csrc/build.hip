@@ -239,6 +239,23 @@ hipError_t unpad_rows(const void* src, int64_t n, int d_pad, int esize, void* ds
   return hipGetLastError();
 }
 
+// Predictor labels from per-query counters [n][8]: iters = the last iteration in which the top-k changed
+// (counter 7), budget = log(1 + iters) (the regression target).
+__global__ void budget_labels_kernel(const int64_t* __restrict__ ctr, int64_t n, int32_t* __restrict__ iters,
+                                     float* __restrict__ budget) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t it = ctr[i * 8 + 7];
+  iters[i] = (int32_t)it;
+  budget[i] = log1pf((float)it);
+}
+
+hipError_t budget_labels(const int64_t* ctr, int64_t n, int32_t* iters, float* budget, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(budget_labels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, n, iters, budget);
+  return hipGetLastError();
+}
+
 // Deletion flags (Sec. 6.2): dead[u] |= 1 when gmap[u] is one of the m sorted global ids.
 __global__ void mark_dead_kernel(const uint32_t* __restrict__ gmap, int64_t n, const uint32_t* __restrict__ ids,
                                  int64_t m, uint8_t* __restrict__ dead) {

@@ -22,6 +22,8 @@ hipError_t u8_to_f32(const uint8_t* src, int64_t total, float* dst, hipStream_t 
 hipError_t mark_dead(const uint32_t* gmap, int64_t n, const uint32_t* sorted_ids, int64_t m, uint8_t* dead,
                      hipStream_t st);
 hipError_t fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
+// iters[i] = counter 7 of query i ([n][8] counters), budget[i] = log(1 + iters[i]).
+hipError_t budget_labels(const int64_t* ctr, int64_t n, int32_t* iters, float* budget, hipStream_t st);
 // dst [n][d] (row length d) from src rows of d_pad elements, `esize` bytes each.
 hipError_t unpad_rows(const void* src, int64_t n, int d_pad, int esize, void* dst, int d, hipStream_t st);
 

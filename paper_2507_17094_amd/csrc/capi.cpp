@@ -510,8 +510,12 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
   a.lowp = lp;
   a.hash_log2 = hlog;
   a.lp_pow2 = std::max(64, pow2_ceil(lp_max));
-  a.waves_per_block = 1;
-  if (const char* w = getenv("MIANN_WAVES_PER_BLOCK")) a.waves_per_block = std::max(1, std::min(4, atoi(w)));
+  // queries (waves) per workgroup: 1, or MIANN_WAVES_PER_BLOCK (1..4) read once when the library first searches
+  static const int wpb_env = [] {
+    const char* w = getenv("MIANN_WAVES_PER_BLOCK");
+    return w ? std::max(1, std::min(4, atoi(w))) : 1;
+  }();
+  a.waves_per_block = wpb_env;
   a.per_wave_lds = stage_lds_bytes(a);
   if ((int64_t)a.per_wave_lds * a.waves_per_block > 160 * 1024)
     return fail(MIANN_EUNSUPPORTED, "miann_search: %d bytes of LDS per query exceed the CU", a.per_wave_lds);
@@ -628,7 +632,42 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
   return rc;
 }
 
+// Device bytes of a search's temporary buffers (hand-off, per-stage results, dense seeds, and the dense entry's
+// query split and work area), as the stream-kept blocks hold them (each rounded up to a power of two): what a
+// batch of nq queries with these parameters keeps on its stream. Used by the server's admission control.
+size_t miann_search_scratch_bytes(const miann_index* ix, int64_t nq, int32_t k, int32_t itopk,
+                                  const miann_search_params* spp) {
+  if (!ix || nq <= 0) return 0;
+  miann_search_params sp;
+  if (spp) sp = *spp; else miann_search_params_default(&sp);
+  auto p2 = [](size_t b) {
+    size_t c = 65536;
+    while (c < b) c <<= 1;
+    return b ? c : 0;
+  };
+  const int t = sp.t_seeds ? sp.t_seeds : std::min(sp.ghost_itopk, itopk);
+  size_t search = 0;
+  if (ix->S > 1) search += (size_t)2 * nq * std::max(1, sp.forward_f) * 4 + (size_t)nq * ix->S * k * 8 + 512;
+  size_t dense = 0;
+  if (sp.entry == MIANN_ENTRY_GHOST_DENSE && ix->dg.cols) {
+    search += (size_t)nq * ix->S * t * 8;
+    const int start_only = ix->S > 1 && sp.ppe && !sp.ghost_every_stage;
+    const size_t qpart = (size_t)nq * ((size_t)ix->d_pad_f32 * 4 + (size_t)ix->d_pad * 4 + 8) + 2048;
+    const size_t one = dense_entry_min_scratch(ix->store_dtype, 1, ix->d_pad, ix->d_pad_f32, ix->S, start_only, ix->dg);
+    // the work area: every row of the batch, up to the 512 MB chunk limit
+    const size_t work = std::min((size_t)nq * one, (size_t)1 << 29);
+    dense = p2(qpart) + p2(work);
+  }
+  return p2(search) + dense;
+}
+
 extern "C" {
+
+miann_status miann_release_scratch(void* stream) {
+  const hipError_t e = scratch_drop_stream((hipStream_t)stream);
+  if (e != hipSuccess) return fail(MIANN_EDEVICE, "miann_release_scratch: %s", hipGetErrorString(e));
+  return MIANN_OK;
+}
 
 miann_status miann_search(const miann_index* ix, const void* queries, int64_t nq, int32_t k, int32_t itopk,
                           int32_t max_iters, const miann_search_params* spp, uint32_t* ids, void* dists,
@@ -902,6 +941,51 @@ miann_status miann_nearest_ghost(const miann_index* ix, int32_t shard, const voi
   return MIANN_OK;
 }
 
+
+miann_status miann_predictor_labels(const miann_index* cix, const float* queries, int64_t n, int32_t k, int32_t itopk,
+                                    int32_t max_iters, const miann_search_params* sp, int32_t* entry, float* budget,
+                                    int32_t* iters, void* stream) {
+  miann_index* ix = const_cast<miann_index*>(cix);
+  if (!ix) return fail(MIANN_EINVAL, "miann_predictor_labels: null index");
+  if (ix->S != 1) return fail(MIANN_EINVAL, "miann_predictor_labels: the learned entry is defined for one shard");
+  if (ix->in_dtype != MIANN_F32) return fail(MIANN_EUNSUPPORTED, "miann_predictor_labels: float queries only");
+  if (ix->sh[0].R == 0) return fail(MIANN_ESTATE, "miann_predictor_labels: no ghost shard");
+  if (n < 0) return fail(MIANN_EINVAL, "miann_predictor_labels: n < 0");
+  if (n == 0) return MIANN_OK;
+  if (!queries || !entry || !budget || !iters) return fail(MIANN_EINVAL, "miann_predictor_labels: null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const Shard& h = ix->sh[0];
+  Temps tmp(st);
+  // budget: the search's trace (counter 7, the last iteration in which its top-k changed)
+  int64_t* ctr = nullptr;
+  uint32_t* ids = nullptr;
+  float* ds = nullptr;
+  HIP_TRY(tmp.get(&ctr, (size_t)n * kNumCtr * 8));
+  HIP_TRY(tmp.get(&ids, (size_t)n * k * 4));
+  HIP_TRY(tmp.get(&ds, (size_t)n * k * 4));
+  miann_status rc = miann_search(ix, queries, n, k, itopk, max_iters, sp, ids, ds, ctr, stream);
+  if (rc) return rc;
+  HIP_TRY(budget_labels(ctr, n, iters, budget, st));
+  // entry: the ghost nearest to the query's exact nearest node (local ids of the one shard)
+  const int dpi = ix->d_pad_in;
+  float* qf = nullptr;
+  uint64_t* keys = nullptr;
+  uint32_t* nn = nullptr;
+  float* rows = nullptr;
+  float* vec = nullptr;
+  HIP_TRY(tmp.get(&qf, (size_t)n * dpi * 4));
+  HIP_TRY(queries_to_f32(queries, MIANN_F32, n, ix->d, dpi, qf, st));
+  HIP_TRY(tmp.get(&keys, (size_t)n * 8));
+  HIP_TRY(knn_exact(qf, n, (const float*)h.orig, h.n, dpi, ix->d, ix->in_dtype, qf, dpi, h.orig, nullptr, dpi, 1, 0,
+                    nullptr, keys, st));
+  HIP_TRY(tmp.get(&nn, (size_t)n * 4));
+  HIP_TRY(keys_to_ids(keys, n, 1, 0, nn, 1, st));
+  HIP_TRY(tmp.get(&rows, (size_t)n * dpi * 4));
+  HIP_TRY(gather_rows(h.orig, nn, n, dpi * 4, rows, st));
+  HIP_TRY(tmp.get(&vec, (size_t)n * ix->d * 4));
+  HIP_TRY(unpad_rows(rows, n, dpi, 4, vec, ix->d, st));
+  return miann_nearest_ghost(ix, 0, vec, n, (uint32_t*)entry, stream);
+}
 
 miann_status miann_index_delete(miann_index* ix, const uint32_t* global_ids, int64_t m, void* stream) {
   if (!ix) return fail(MIANN_EINVAL, "miann_index_delete: null index");

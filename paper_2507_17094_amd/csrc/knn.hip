@@ -1045,12 +1045,11 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
     break;
 #define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
-    static bool set = false;                                                                                         \
-    if (!set) {                                                                                                      \
+    static std::once_flag set;                                                                                       \
+    std::call_once(set, [] {                                                                                         \
       (void)hipFuncSetAttribute((const void*)dense_tiles_kernel<MODE, 32 * KC>,                                      \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
-      set = true;                                                                                                    \
-    }                                                                                                                \
+    });                                                                                                              \
     hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
                        chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, bnd,  \
                        cmask);                                                                                       \

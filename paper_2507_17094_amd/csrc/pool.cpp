@@ -45,6 +45,7 @@ hipError_t scratch_lease(int slot, size_t bytes, hipStream_t st, ScratchLease* o
   if (bytes == 0) bytes = 16;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (st == hipStreamPerThread) return pool_malloc_async(&out->p, bytes, st);
   {
     std::lock_guard<std::mutex> lk(kept_mu);
     Kept& k = kept[std::make_tuple(dev, st, slot)];
@@ -82,6 +83,25 @@ void scratch_release(int slot, const ScratchLease& l, hipStream_t st) {
   hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(kept_mu);
   kept[std::make_tuple(dev, st, slot)].busy = false;
+}
+
+hipError_t scratch_drop_stream(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  hipError_t rc = hipSuccess;
+  std::lock_guard<std::mutex> lk(kept_mu);
+  for (auto it = kept.begin(); it != kept.end();) {
+    if (std::get<0>(it->first) == dev && std::get<1>(it->first) == st && !it->second.busy) {
+      if (it->second.p) {
+        const hipError_t e = hipFreeAsync(it->second.p, st);
+        if (e != hipSuccess) rc = e;
+      }
+      it = kept.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return rc;
 }
 
 }  // namespace miann

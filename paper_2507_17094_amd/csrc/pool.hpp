@@ -24,7 +24,9 @@ inline hipError_t pool_malloc_async(T** p, size_t bytes, hipStream_t st) {
 // (device, stream, slot); a released block is kept for the next lease on the same stream, whose work the stream
 // orders after the previous user's, so back-to-back calls skip the stream-ordered allocator and the markers it
 // queues. A lease whose block is held by another host thread on the same stream gets a block of its own from the
-// pool instead. A kept block grows in powers of two to cover the largest size asked for and is held until the process ends.
+// pool instead. A kept block grows in powers of two to cover the largest size asked for and is held until
+// scratch_drop_stream (miann_release_scratch) or the end of the process. hipStreamPerThread names a different
+// stream in every thread, so its leases are never kept.
 enum ScratchSlot { kSlotSearch = 0, kSlotDenseQueries = 1, kSlotDenseWork = 2, kNumSlots = 3 };
 struct ScratchLease {
   void* p = nullptr;
@@ -32,5 +34,8 @@ struct ScratchLease {
 };
 hipError_t scratch_lease(int slot, size_t bytes, hipStream_t st, ScratchLease* out);
 void scratch_release(int slot, const ScratchLease& l, hipStream_t st);
+// Returns the stream's kept blocks to the pool (stream-ordered frees on `st`, so work already queued on it keeps
+// its buffers); blocks leased at the moment stay kept. Call before destroying a stream that searched.
+hipError_t scratch_drop_stream(hipStream_t st);
 
 }  // namespace miann

@@ -128,7 +128,11 @@ miann_status miann_predictor_create(int32_t d_in, int32_t hidden, int32_t n_entr
   const int64_t sz[6] = {(int64_t)d_in * hidden, hidden, (int64_t)hidden * hidden, hidden,
                          (int64_t)hidden * P->n_out, P->n_out};
   const int64_t fan_in[6] = {d_in, d_in, hidden, hidden, hidden, hidden};
-  hipError_t e = hipSuccess;
+  // a non-blocking stream of its own: creating a predictor waits for its own copies only, not for the work
+  // other streams (a server, say) have queued
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  std::vector<std::vector<float>> host(6);
   for (int i = 0; i < 6 && e == hipSuccess; i++) {
     P->sz[i] = sz[i];
     e = P->alloc(&P->w[i], sz[i] * 4);
@@ -138,7 +142,8 @@ miann_status miann_predictor_create(int32_t d_in, int32_t hidden, int32_t n_entr
     if (e == hipSuccess && i % 2 == 0) e = P->alloc(&P->wb[i / 2], sz[i] * 2);
     if (e != hipSuccess) break;
     // weights U(-a, a), a = sqrt(6 / fan_in) from SplitMix64; biases zero
-    std::vector<float> h(sz[i], 0.f);
+    std::vector<float>& h = host[i];
+    h.assign(sz[i], 0.f);
     if (i % 2 == 0) {
       const double a = std::sqrt(6.0 / (double)fan_in[i]);
       for (int64_t j = 0; j < sz[i]; j++) {
@@ -146,14 +151,17 @@ miann_status miann_predictor_create(int32_t d_in, int32_t hidden, int32_t n_entr
         h[j] = (float)(a * (2.0 * u - 1.0));
       }
     }
-    e = hipMemcpy(P->w[i], h.data(), sz[i] * 4, hipMemcpyHostToDevice);
-    std::vector<float> z(sz[i], 0.f);
-    if (e == hipSuccess) e = hipMemcpy(P->m[i], z.data(), sz[i] * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(P->v[i], z.data(), sz[i] * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(P->g[i], z.data(), sz[i] * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess && i % 2 == 0) e = to_bf16(P->w[i], sz[i], P->wb[i / 2], nullptr);
+    e = hipMemcpyAsync(P->w[i], h.data(), sz[i] * 4, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipMemsetAsync(P->m[i], 0, sz[i] * 4, cs);
+    if (e == hipSuccess) e = hipMemsetAsync(P->v[i], 0, sz[i] * 4, cs);
+    if (e == hipSuccess) e = hipMemsetAsync(P->g[i], 0, sz[i] * 4, cs);
+    if (e == hipSuccess && i % 2 == 0) e = to_bf16(P->w[i], sz[i], P->wb[i / 2], cs);
   }
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (cs) {
+    const hipError_t e2 = hipStreamSynchronize(cs);  // the host copies must outlive the transfers
+    if (e == hipSuccess) e = e2;
+    hipStreamDestroy(cs);
+  }
   if (e != hipSuccess) {
     delete P;
     return miann_fail(MIANN_EDEVICE, "miann_predictor_create: %s", hipGetErrorString(e));

@@ -21,6 +21,8 @@
 // first T - ceil(c T) iterations the direction filter of Sec. 3.3.2 keeps only
 // the neighbours whose stored sign bits agree most with the query's.
 #pragma once
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -768,12 +770,12 @@ static hipError_t launch_occ(const StageArgs& a, hipStream_t st) {
   const int wpb = a.waves_per_block;
   const int64_t blocks = (a.nq + wpb - 1) / wpb;
   const size_t lds = (size_t)a.per_wave_lds * wpb;
-  static bool attr_set = false;
-  if (!attr_set) {
+  // once per kernel instance, also when host threads search concurrently
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
     (void)hipFuncSetAttribute((const void*)stage_kernel<DT, CPL, OCC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
-    attr_set = true;
-  }
+  });
   hipLaunchKernelGGL((stage_kernel<DT, CPL, OCC>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
   return hipGetLastError();
 }

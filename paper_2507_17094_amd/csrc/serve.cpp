@@ -30,6 +30,8 @@
 
 miann_status miann_fail(miann_status st, const char* fmt, ...);
 int miann_index_input_esize(const miann_index* idx, int32_t* d_out);
+size_t miann_search_scratch_bytes(const miann_index* ix, int64_t nq, int32_t k, int32_t itopk,
+                                  const miann_search_params* sp);
 
 namespace {
 
@@ -92,9 +94,12 @@ struct miann_server {
   std::thread th;
   clk::time_point t0;
 
-  size_t batch_bytes(int64_t nq, int32_t k) const {
-    return (size_t)nq * ((size_t)d * esize + 8 + (size_t)k * 8) + 4096;
+  // device bytes of a batch: its staging buffers plus the search's temporaries on the slot's stream
+  size_t batch_bytes(int64_t nq, int32_t k, int32_t itopk, const miann_search_params* sp) const {
+    return (size_t)nq * ((size_t)d * esize + 8 + (size_t)k * 8) + 4096 +
+           miann_search_scratch_bytes(idx, nq, k, itopk, sp);
   }
+  size_t batch_bytes(int64_t nq, const Request& r) const { return batch_bytes(nq, r.k, r.itopk, &r.sp); }
 
   void loop();
   bool reserve(Slot& s, int64_t nq, int32_t k);
@@ -159,7 +164,7 @@ bool miann_server::launch(Slot& s, std::vector<std::shared_ptr<Request>>& batch)
   s.reqs = batch;
   s.nq = nq;
   s.k = k;
-  s.bytes = batch_bytes(nq, k);
+  s.bytes = batch_bytes(nq, *batch[0]);
   return true;
 }
 
@@ -216,7 +221,7 @@ void miann_server::loop() {
           const auto& r = *it;
           if (same_shape(*r, *head) && nq + r->nq <= cfg.max_batch_queries &&
               inflight_q + nq + r->nq <= cfg.max_inflight_queries &&
-              inflight_b + batch_bytes(nq + r->nq, head->k) <= (size_t)cfg.memory_budget_bytes) {
+              inflight_b + batch_bytes(nq + r->nq, *head) <= (size_t)cfg.memory_budget_bytes) {
             nq += r->nq;
             batch.push_back(r);
             it = pending.erase(it);
@@ -226,7 +231,7 @@ void miann_server::loop() {
         }
         if (batch.empty()) break;  // the oldest request must wait for capacity
         inflight_q += nq;
-        inflight_b += batch_bytes(nq, head->k);
+        inflight_b += batch_bytes(nq, *head);
         stats.peak_inflight_queries = std::max<int64_t>(stats.peak_inflight_queries, inflight_q);
         stats.peak_inflight_bytes = std::max<int64_t>(stats.peak_inflight_bytes, (int64_t)inflight_b);
         stats.batches++;
@@ -245,7 +250,7 @@ void miann_server::loop() {
           nq += r->nq;
         }
         inflight_q -= nq;
-        inflight_b -= batch_bytes(nq, t.second[0]->k);
+        inflight_b -= batch_bytes(nq, *t.second[0]);
         cv_done.notify_all();
       }
     }
@@ -261,7 +266,11 @@ namespace {
 
 void miann_server_destroy_slots(miann_server* s) {
   for (auto& sl : s->slots) {
-    if (sl.st) hipStreamSynchronize(sl.st);
+    if (sl.st) {
+      hipStreamSynchronize(sl.st);
+      miann_release_scratch(sl.st);  // the searches' kept blocks of this stream go back to the pool
+      hipStreamSynchronize(sl.st);
+    }
     if (sl.d_buf) hipFree(sl.d_buf);
     if (sl.h_in) hipHostFree(sl.h_in);
     if (sl.h_out) hipHostFree(sl.h_out);
@@ -306,7 +315,8 @@ miann_status miann_server_create(const miann_index* idx, const miann_server_conf
   }
   // full batches up front, as far as the memory budget covers them
   s->prealloc_nq = std::max<int64_t>(1, std::min<int64_t>(c.max_batch_queries, c.memory_budget_bytes /
-                                                              (int64_t)s->batch_bytes(1, kPreallocK)));
+                                                              (int64_t)s->batch_bytes(1, kPreallocK, kPreallocK,
+                                                                                      nullptr)));
   for (auto& sl : s->slots) {
     if (!s->reserve(sl, s->prealloc_nq, kPreallocK)) {
       miann_server_destroy_slots(s);
@@ -324,12 +334,12 @@ miann_status miann_server_submit(miann_server* s, const void* queries, int64_t n
                                  int32_t max_iters, const miann_search_params* sp, uint64_t* ticket) {
   if (!s || !ticket || (nq > 0 && !queries)) return miann_fail(MIANN_EINVAL, "miann_server_submit: null argument");
   if (nq < 1) return miann_fail(MIANN_EINVAL, "miann_server_submit: nq = %lld < 1", (long long)nq);
-  if (nq > s->cfg.max_batch_queries || nq > s->cfg.max_inflight_queries ||
-      s->batch_bytes(nq, k) > (size_t)s->cfg.memory_budget_bytes)
-    return miann_fail(MIANN_EINVAL, "miann_server_submit: a request of %lld queries exceeds the server limits",
-                      (long long)nq);
   auto r = std::make_shared<Request>();
   if (sp) r->sp = *sp; else miann_search_params_default(&r->sp);
+  if (nq > s->cfg.max_batch_queries || nq > s->cfg.max_inflight_queries ||
+      s->batch_bytes(nq, k, itopk, &r->sp) > (size_t)s->cfg.memory_budget_bytes)
+    return miann_fail(MIANN_EINVAL, "miann_server_submit: a request of %lld queries exceeds the server limits",
+                      (long long)nq);
   if (r->sp.qkeys || r->sp.seeds || r->sp.max_iters_per_query || r->sp.phase_ms || r->sp.phase_events)
     return miann_fail(MIANN_EINVAL, "miann_server_submit: per-query device arrays are not accepted by the server");
   // validate the shape with a zero-query search (no device work)

@@ -17,9 +17,10 @@ calls:
 """
 from __future__ import annotations
 
+import ctypes as C
 from dataclasses import dataclass
 
-from . import Index, Predictor, SearchOptions, nearest_ghost
+from . import Index, Predictor, SearchOptions
 
 
 @dataclass
@@ -30,32 +31,19 @@ class Labels:
 
 
 def make_labels(index: Index, queries, k: int, itopk: int, t_max: int, opts: SearchOptions) -> Labels:
-    """Entry and budget labels for `queries` (device float32 [n][d]) on a one-shard index."""
+    """Entry and budget labels for `queries` (device float32 [n][d]) on a one-shard index
+    (miann_predictor_labels: the search's trace, the exact nearest node and its nearest ghost, all on the device)."""
     import torch
-    assert index.info()["num_shards"] == 1, "the learned entry is defined for one shard"
-    _, _, ctr = index.search(queries, k, itopk, t_max, opts, counters=True)
-    last = ctr[:, 7].to(torch.int32)
-    nn_ids, _ = index.exact_knn(queries, 1)
-    # vectors of the exact nearest neighbours (global id == local id for one shard)
-    nn_vec = _gather_rows(index, nn_ids[:, 0])
-    entry = nearest_ghost(index, nn_vec)
-    return Labels(entry=entry, budget=torch.log1p(last.float()), iters=last)
-
-
-def _gather_rows(index: Index, ids):
-    """Original vectors of `ids` from shard 0 (device gather through torch indexing of a view)."""
-    import torch
-    v = index.shard(0)
-    d, n = v.d, v.n
-    esz = 1 if index.in_dtype == 3 else 4
-    dp = (d * esz + 127) // 128 * 128 // esz  # originals rows are padded to 128 bytes
-    flat = torch.empty(n * dp * esz, dtype=torch.uint8, device="cuda")
-    from . import _hip_copy
-    _hip_copy(flat.data_ptr(), v.originals, n * dp * esz)
-    rows = flat.view(n, dp * esz)[ids.long()]
-    if esz == 4:
-        return rows.view(torch.float32)[:, :d].contiguous()
-    return rows[:, :d].contiguous()
+    from . import _check, _require, _stream_ptr, load
+    _require(queries, "queries", (torch.float32,), (None, index.info()["d"]))
+    n = queries.shape[0]
+    entry = torch.empty(n, dtype=torch.int32, device=queries.device)
+    budget = torch.empty(n, dtype=torch.float32, device=queries.device)
+    iters = torch.empty(n, dtype=torch.int32, device=queries.device)
+    p = opts.cstruct()
+    _check(load().miann_predictor_labels(index.handle, queries.data_ptr(), n, k, itopk, t_max, C.byref(p),
+                                         entry.data_ptr(), budget.data_ptr(), iters.data_ptr(), _stream_ptr()))
+    return Labels(entry=entry, budget=budget, iters=iters)
 
 
 def train(index: Index, queries, labels: Labels, hidden: int = 256, epochs: int = 10, batch: int = 4096,

@@ -38,6 +38,18 @@ def test_predictor_gain_over_ghost_staging():
     tr = torch.from_numpy(Qtr).cuda()
     te = torch.from_numpy(Qte).cuda()
     labels = learned.make_labels(gx, tr, k, itopk, T, opts)
+    # the labels against the oracle on a sample: the trace counter of the same search, and the ghost nearest to
+    # the exact nearest node (brute force over nodes, then over ghosts)
+    ox = oracle_from_device(gx, X)
+    m = 400
+    _, _, oc = oracle.search(ox, Qtr[:m], **oracle_kwargs(k, itopk, T, opts))
+    it = labels.iters.cpu().numpy()[:m]
+    assert np.mean(it == oc[:, 7]) >= 0.995  # (a near tie may change one query's path, as in the search parity)
+    assert np.allclose(labels.budget.cpu().numpy()[:m], np.log1p(it.astype(np.float64)), rtol=1e-6, atol=0)
+    nn, _ = oracle.knn(X, Qtr[:m], 1)
+    gids = ox.shards[0]["g_map"]
+    ge, _ = oracle.knn(X[gids], X[nn[:, 0]], 1)
+    assert np.mean(labels.entry.cpu().numpy()[:m] == ge[:, 0]) >= 0.999
     P, losses = learned.train(gx, tr, labels, hidden=128, epochs=12, batch=2048, lr=2e-3)
     say(f"  losses {[round(x, 3) for x in losses]}")
     assert losses[-1] < 0.5 * losses[0]
