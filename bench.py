@@ -32,7 +32,7 @@ HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
     "sharded1m": dict(N=1_000_000, d=96, C=1000, sigma=0.25, nq=10_000, k=10, deg=32, S=4, ghost_ratio=0.01,
-                      deg_g=32, itopks=(32, 48, 64), Ts=(8, 9, 10, 12, 16, 24)),
+                      deg_g=32, itopks=(32, 64, 128, 256), Ts=(8, 9, 10, 12, 16, 24)),
     "tiny": dict(N=10_000, d=128, C=32, sigma=0.3, nq=1_000, k=10, deg=32, S=1, ghost_ratio=0.01, deg_g=32,
                  itopks=(32, 64, 128), Ts=(16, 32, 64)),
 }
@@ -193,22 +193,117 @@ def record_traffic(args):
 
 
 def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_stage):
-    """Bytes the stage kernel must move per batch, from the per-query counters.
-    HBM-resident arrays: gathered vectors (n_dist rows), adjacency rows (n_exp),
-    direction-table rows and parent vectors of the expansions made under the
-    filter, the query per stage and the results per stage. Returned separately:
-    the ghost-graph vectors and rows of the graph-mode entry, which runs inside
-    the stage kernel on arrays small enough to stay in cache (about 1 MB per
-    shard), so they are not priced against HBM. The dense entry runs in its own
-    kernel and is not counted here."""
+    """Bytes the stage kernel must move per batch, from the per-query counters, by the per-query formula
+        B_q = sum over stages [n_dist row + n_exp deg 4 + n_exp,filter deg W 4] + S (d 4 + k 8)
+    (gathered vectors, adjacency rows, direction-table rows of the expansions made under the filter, the
+    query and the results per stage). Returned separately: the parent vectors the filter reads to form the
+    query's sign bits (not in the formula), and the ghost-graph vectors and rows of the graph-mode entry, which
+    runs inside the stage kernel on arrays small enough to stay in cache (about 1 MB per shard), so they are
+    not priced against HBM. The dense entry runs in its own kernels and is not counted here."""
     n_dist, n_exp, skipped = ctr[:, 0].sum(), ctr[:, 1].sum(), ctr[:, 3].sum()
     n_dist_g, n_exp_g = (ctr[:, 4].sum(), ctr[:, 5].sum()) if ghost_in_stage else (0, 0)
     n_exp_dgs = skipped / max(1, deg - n_keep) if deg > n_keep else 0
     nq = ctr.shape[0]
     vec = n_dist * row_bytes
-    hbm = vec + n_exp * deg * 4 + n_exp_dgs * (deg * W * 4 + row_bytes) + nq * S * (d * 4 + k * 8)
+    hbm = vec + n_exp * deg * 4 + n_exp_dgs * deg * W * 4 + nq * S * (d * 4 + k * 8)
+    parent = n_exp_dgs * row_bytes
     ghost = n_dist_g * row_bytes + n_exp_g * deg_g * 4
-    return float(hbm), float(vec), float(ghost)
+    return float(hbm), float(vec), float(parent), float(ghost)
+
+
+def profiled_launch_us(workload, itopk, T, opts):
+    """The stage kernel's average launch duration (us) from the committed rocprofv3 kernel-trace record of this
+    setting, while the kernel's sources are the ones it was taken on; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_timing.json")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    for rec in json.load(open(path)):
+        st = rec["setting"]
+        if (rec["sources_sha256"] == h.hexdigest() and rec["workload"] == workload and st["itopk"] == itopk and
+                st["T"] == T and st["entry"] == opts.entry and st["search_width"] == opts.search_width and
+                st["ghost_every_stage"] == bool(opts.ghost_every_stage) and st["t_seeds"] == opts.t_seeds):
+            return rec["stage_kernel_avg_us"]
+    return None
+
+
+def record_timing(args):
+    """Writes the stage kernel's average launch duration for the --fixed setting from a rocprofv3 --stats csv
+    (kernel_stats.csv) to the profiles record, with the sources it was taken on."""
+    import csv
+    import hashlib
+    f = args.fixed.split(",")
+    rows = list(csv.DictReader(open(args.record_timing)))
+    stage = [r for r in rows if r["Name"].startswith("void miann::stage_kernel")]
+    calls = sum(int(r["Calls"]) for r in stage)
+    avg = sum(float(r["TotalDurationNs"]) for r in stage) / calls / 1e3
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    rec = {"kernel": "stage_kernel", "sources": TRAFFIC_SOURCES, "sources_sha256": h.hexdigest(),
+           "workload": args.workload,
+           "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
+                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0},
+           "stage_kernel_avg_us": avg, "calls": calls,
+           "other_kernels_avg_us": {r["Name"][:80]: float(r["AverageNs"]) / 1e3 for r in rows[:12]}}
+    path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_timing.json")
+    recs = []
+    if os.path.exists(path):
+        recs = [r for r in json.load(open(path))
+                if r.get("sources_sha256") == rec["sources_sha256"] and r.get("setting") != rec["setting"]]
+    recs.append(rec)
+    with open(path, "w") as fh:
+        json.dump(recs, fh, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+def gather_probe(args):
+    """Random-row gather ceiling: the library's probe over a table much larger than the caches, rows of the
+    search's sizes, uniformly random ids; bytes of the gathered rows per second, timed with HIP events."""
+    import torch
+    import paper_2507_17094_amd as miann
+    table_bytes = 4 << 30
+    n = 1 << 24
+    tab = torch.empty(table_bytes, dtype=torch.uint8, device="cuda")
+    tab.fill_(1)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = []
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    for row in (384, 512, 1024):
+        n_rows = table_bytes // row
+        ids = torch.randint(0, n_rows, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+        L = miann.load()
+        st = torch.cuda.current_stream().cuda_stream
+
+        def go():
+            miann._check(L.miann_gather_probe(tab.data_ptr(), n_rows, row, ids.data_ptr(), n, out.data_ptr(), st))
+        for _ in range(2):
+            go()
+        evs = HipEvents(2)
+        torch.cuda.synchronize()
+        reps = 10
+        import ctypes
+        hip = evs.hip
+        hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        hip.hipEventRecord(evs.handles[0], st)
+        for _ in range(reps):
+            go()
+        hip.hipEventRecord(evs.handles[1], st)
+        torch.cuda.synchronize()
+        ms = evs.elapsed(0, 1) / reps
+        evs.close()
+        gbps = n * row / (ms * 1e-3) / 1e9
+        res.append({"row_bytes": row, "rows_per_launch": n, "launch_ms": ms, "gathered_GBps": gbps,
+                    "frac_of_8TBps": gbps / HBM_PEAK_GBPS})
+        log(f"  gather probe rows of {row} B: {ms:.3f} ms per launch, {gbps:,.0f} GB/s")
+        del ids
+    print(json.dumps({"gather_probe": res, "table_bytes": table_bytes}), flush=True)
 
 
 FORMS = {
@@ -533,9 +628,22 @@ def main():
                     help="only write the stage kernel's calibrated HBM traffic for the --fixed setting from four "
                          "rocprofv3 --pmc databases (FETCH_SIZE and WRITE_SIZE of the setting, then of "
                          "--copy-calibration 1024) to the profiles record")
+    ap.add_argument("--record-timing", metavar="KERNEL_STATS_CSV",
+                    help="only write the stage kernel's average launch duration for the --fixed setting from a "
+                         "rocprofv3 --stats csv to the profiles record")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="only measure the random-row gather ceiling (rows of 384, 512 and 1024 bytes)")
+    ap.add_argument("--lut", type=int, default=1,
+                    help="also compare the search-built shard-to-shard lookup table with the exact 1-NN map")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args)
+        return
+    if args.record_timing:
+        record_timing(args)
+        return
+    if args.gather_probe:
+        gather_probe(args)
         return
     if args.copy_calibration:
         import torch
@@ -578,7 +686,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.time()
     gx = miann.Index.build(Xd, degree=W["deg"], num_shards=W["S"], dgs_table=True, seed=5)
+    torch.cuda.synchronize()
     t_graph = time.time() - t0
+    build_steps = gx.build_times()
+    t_next_exact = build_steps["inter_shard_map_s"]
     t0 = time.time()
     gx.build_ghost(ratio=W["ghost_ratio"], ghost_degree=W["deg_g"], seed=5)
     t_ghost = time.time() - t0
@@ -619,17 +730,21 @@ def main():
         best = max(ok, key=lambda r: r["qps"]) if ok else max(rows, key=lambda r: r["recall"])
         return best, rows
 
-    tuned_opts = []
-    for r in (1, 2):
-        tuned_opts += [(f"gs-all+dgs r{r}", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=r,
-                                                                ghost_every_stage=True)),
-                       (f"gsdense-all+dgs r{r}", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=r,
-                                                                     ghost_every_stage=True))]
-    tuned_opts += [("gsdense-all+dgs r2 t8", miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=2,
-                                                                 ghost_every_stage=True, t_seeds=8)),
-                   ("gs-all+dgs r2 Tg4", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2,
-                                                             ghost_every_stage=True, ghost_iters=4)),
-                   ("gs+dgs r2", miann.SearchOptions(entry="ghost_graph", dgs=True, search_width=2))]
+    # forms of the tuned search. "stage 0" variants follow the paper (ghost staging seeds the first stage only,
+    # later stages start from I(z)); "every stage" variants are this build's extension: every stage also takes
+    # its own shard's ghost seeds next to I(z)
+    O = miann.SearchOptions
+    tuned_opts = [
+        ("gsdense+dgs r2 t8 (stage 0)", O(entry="ghost_dense", dgs=True, search_width=2, t_seeds=8)),
+        ("gs+dgs r2 (stage 0)", O(entry="ghost_graph", dgs=True, search_width=2)),
+        ("gsdense-all+dgs r2 t8", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
+                                    t_seeds=8)),
+        ("gsdense-all+dgs r1 t8", O(entry="ghost_dense", dgs=True, search_width=1, ghost_every_stage=True,
+                                    t_seeds=8)),
+        ("gs-all+dgs r2", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True)),
+        ("gs-all+dgs r2 Tg4", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True,
+                                ghost_iters=4)),
+    ]
     if args.fixed:
         f = args.fixed.split(",")
         fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])),
@@ -653,6 +768,49 @@ def main():
         del gp
 
     itopk, T, opts = best["itopk"], best["T"], best["opts"]
+    # the best paper-faithful form (ghost staging in stage 0 only) beside the chosen one
+    faithful = [r for r in tuned_rows if r["variant"].endswith("(stage 0)")]
+    ok_f = [r for r in faithful if r["recall"] >= 0.95]
+    best_faithful = (max(ok_f, key=lambda r: r["qps"]) if ok_f else
+                     max(faithful, key=lambda r: r["recall"]) if faithful else None)
+
+    lut = None
+    if args.lut and W["S"] > 1 and not args.fixed:
+        # the shard-to-shard lookup table built by search (each node searches the next shard, top-1 kept) against
+        # the exact 1-NN map the build made; the same tuned setting runs over both
+        import ctypes
+        exact_maps = []
+        for s_ in range(W["S"]):
+            v = gx.shard(s_)
+            exact_maps.append(d2h(v.next_map, v.n, np.uint32))
+        rows_l = []
+        for name, lo in (("random entry, itopk 32, T 12", O(n_init=64, dgs=True)),
+                         ("ghost-graph entry, itopk 32, T 8", O(entry="ghost_graph", dgs=True))):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            lit, lT = 32, (12 if lo.entry == "random" else 8)
+            gx.build_next_map(lit, lT, lo)
+            torch.cuda.synchronize()
+            t_lut = time.time() - t0
+            same = float(np.mean(np.concatenate([d2h(gx.shard(s_).next_map, gx.shard(s_).n, np.uint32) == exact_maps[s_]
+                                                 for s_ in range(W["S"])])))
+            ids_l, _ = run(gx, itopk, T, opts)
+            torch.cuda.synchronize()
+            rc_l = recall(gt, ids_l.cpu().numpy().view(np.uint32), k)
+            qps_l = nq / timed(gx, itopk, T, opts)
+            rows_l.append(dict(build=name, build_s=t_lut, entries_equal_exact=same, recall=rc_l, qps=qps_l))
+            log(f"  lookup table by search ({name}): {t_lut:.2f}s, {same:.4f} of entries equal the exact map; "
+                f"recall {rc_l:.4f} qps {qps_l:,.0f}")
+        # back to the exact map (the headline runs over it), timed as the exact build of the same table
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for s_ in range(W["S"]):
+            v = gx.shard(s_)
+            src = torch.from_numpy(exact_maps[s_].view(np.int32)).cuda()
+            miann._hip_copy(v.next_map, src.data_ptr(), v.n * 4)
+        torch.cuda.synchronize()
+        lut = {"exact_map_build_s": t_next_exact, "search_built": rows_l, "setting": best["variant"]}
+
     # counters and live per-launch timing of the chosen setting
     ids, dists, ctr = run(gx, itopk, T, opts, counters=True)
     ctr = ctr.cpu().numpy()
@@ -680,10 +838,18 @@ def main():
     v0 = gx.shard(0)
     row_bytes = v0.d_pad * 4
     n_keep = W["deg"] - (int(round(opts.discard * 1000)) * W["deg"]) // 1000 if opts.dgs else W["deg"]
-    bytes_total, vec_bytes, ghost_bytes = algorithmic_bytes(ctr, W["d"], W["deg"], W["deg_g"], v0.W, n_keep, S, k,
-                                                            row_bytes, opts.entry == "ghost_graph")
+    bytes_total, vec_bytes, parent_bytes, ghost_bytes = algorithmic_bytes(
+        ctr, W["d"], W["deg"], W["deg_g"], v0.W, n_keep, S, k, row_bytes, opts.entry == "ghost_graph")
     stage_total_ms = float(phases[1])
-    achieved = bytes_total / (stage_total_ms * 1e-3) / 1e9
+    launch_ms = stage_total_ms / S
+    achieved = bytes_total / S / (launch_ms * 1e-3) / 1e9
+    prof_us = profiled_launch_us(args.workload, itopk, T, opts)
+    probe = None
+    probe_path = os.path.join(ROOT, "profiles", "gather_probe.json")
+    if os.path.exists(probe_path):
+        for r in json.load(open(probe_path))["gather_probe"]:
+            if r["row_bytes"] == row_bytes:
+                probe = r["gathered_GBps"]
 
     out = {
         "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -700,20 +866,32 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload, itopk, T, opts),
                      "traffic_unit": "bytes per stage launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-                     "kernel": "stage_kernel", "stage_launch_ms": stage_total_ms / S,
-                     "dense_entry_ms": float(phases[0]), "merge_ms": float(phases[-1]),
+                     "kernel": "stage_kernel", "stage_launch_ms": launch_ms,
                      "bytes_per_launch": bytes_total / S,
-                     "gathered_vector_GBps": vec_bytes / (stage_total_ms * 1e-3) / 1e9,
+                     "rocprof_launch_us": prof_us,
+                     "frac_at_rocprof": (bytes_total / S / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBPS) if prof_us else None,
+                     "gathered_vector_GBps": vec_bytes / S / (launch_ms * 1e-3) / 1e9,
+                     "gathered_vector_frac": vec_bytes / S / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "gather_probe_GBps": probe,
+                     "frac_of_gather_probe": (achieved / probe) if probe else None,
+                     "filter_parent_row_bytes_per_launch": parent_bytes / S,
                      "cache_resident_ghost_bytes_per_launch": ghost_bytes / S,
-                     "with_ghost_GBps": (bytes_total + ghost_bytes) / (stage_total_ms * 1e-3) / 1e9},
+                     "dense_entry_ms": float(phases[0]), "merge_ms": float(phases[-1])},
         "counters_per_query": {"n_dist": float(ctr[:, 0].mean()), "n_exp": float(ctr[:, 1].mean()),
                                "iters": float(ctr[:, 2].mean()), "dgs_skipped": float(ctr[:, 3].mean()),
                                "n_dist_ghost": float(ctr[:, 4].mean()), "n_exp_ghost": float(ctr[:, 5].mean()),
                                "n_rerank": float(ctr[:, 6].mean()), "last_topk_iter": float(ctr[:, 7].mean())},
-        "build_s": {"graph": t_graph, "ghost": t_ghost, "ground_truth": t_gt},
+        "build_s": {"graph": t_graph, "ghost": t_ghost, "ground_truth": t_gt, "steps": build_steps},
         "plain": plain,
+        "paper_faithful_best": ({k_: best_faithful[k_] for k_ in ("variant", "itopk", "T", "recall", "qps")}
+                                if best_faithful else None),
+        "lookup_table": lut,
         "sweep": [{k_: r[k_] for k_ in ("form", "variant", "itopk", "T", "recall", "qps")} for r in tuned_rows],
     }
+    if opts.ghost_every_stage:
+        out["config"]["extension"] = ("ghost_every_stage: stages after the first also take their own shard's "
+                                      "ghost seeds next to the path-extension hand-off (the paper uses ghost "
+                                      "staging in the first stage only; see paper_faithful_best)")
     if args.cpu_baseline:
         import oracle
         ox = oracle_from_device(gx, X)

@@ -152,6 +152,11 @@ typedef struct {
 miann_status miann_index_shard(const miann_index* idx, int32_t shard, miann_shard_view* out);
 miann_status miann_index_info(const miann_index* idx, int32_t* num_shards, int64_t* n_total, int32_t* d,
                               int32_t* degree, int32_t* store_dtype);
+/* Host seconds of the index's build steps (Sec. 5.7's breakdown): [0] the
+ * graphs (exact K0-NN and pruning), [1] the direction tables, [2] the
+ * inter-shard map, [3] the ghost shards (last miann_build_ghost). Steps the
+ * index did not run read 0. */
+miann_status miann_index_build_times(const miann_index* idx, double* seconds4);
 void miann_index_free(miann_index* idx);
 
 /* Dynamic updates (Sec. 6.2). */
@@ -398,6 +403,26 @@ miann_status miann_server_submit(miann_server* srv, const void* queries_host, in
  * the latency from submission to completion in milliseconds. Each ticket can be waited for once. */
 miann_status miann_server_wait(miann_server* srv, uint64_t ticket, uint32_t* ids_host, void* dists_host,
                                double* latency_ms);
+/* Runs one search of nq (zero) queries with this shape on every stream of an
+ * idle server, so that each stream's staging buffers and kept search scratch
+ * reach the shape's size before requests arrive (the first use of a stream
+ * otherwise grows them while a request waits). Blocks until done. */
+miann_status miann_server_warm(miann_server* srv, int64_t nq, int32_t k, int32_t itopk, int32_t max_iters,
+                               const miann_search_params* sp);
+/* Open-loop replay of a request trace: a native thread submits request j
+ * (rows row_start[j] .. row_start[j] + nq[j] of queries_host, a pool of
+ * pool_rows rows; k[j], itopk[j], max_iters[j]; parameters sp) at
+ * arrival_s[j] seconds after the start, on the host's steady clock (sleeping
+ * until 200 us before, then spinning), while the calling thread waits for the
+ * requests in order; latency_ms[j] runs from the scheduled arrival (not the
+ * submission) to the completion of the request's batch, -1 for a failed
+ * request. *wall_s (nullable) receives the time from the start to the last
+ * completion. arrival_s must not decrease. Results are not copied out.
+ * Blocks until every request is done. */
+miann_status miann_server_replay(miann_server* srv, const void* queries_host, int64_t pool_rows,
+                                 const int64_t* row_start, const int64_t* nq, const int32_t* k, const int32_t* itopk,
+                                 const int32_t* max_iters, const double* arrival_s, int64_t n_req,
+                                 const miann_search_params* sp, double* latency_ms, double* wall_s);
 miann_status miann_server_get_stats(miann_server* srv, miann_server_stats* out);
 /* Completes every queued request, then frees the server. */
 void miann_server_destroy(miann_server* srv);
@@ -409,6 +434,16 @@ void miann_server_destroy(miann_server* srv);
  * stream order; call it before destroying a stream that searched, or to trim
  * memory. miann_server_destroy does it for its own streams. */
 miann_status miann_release_scratch(void* stream);
+
+/* Measurement probe (no part of the search): gathers the n rows ids_dev[i]
+ * of table_dev ([n_rows][row_bytes] in device memory, row_bytes in {128,
+ * 256, 384, 512, 768, 1024}) with the stage kernel's access pattern (8-lane
+ * teams, 16-byte chunks, two rows per team in flight), folds each row into
+ * out_dev[i]. Ids >= n_rows read row 0. Its bytes per second over a table much
+ * larger than the caches is the achievable HBM ceiling of random row gathers.
+ * Enqueues on `stream`. */
+miann_status miann_gather_probe(const void* table_dev, int64_t n_rows, int32_t row_bytes, const uint32_t* ids_dev,
+                                int64_t n, uint32_t* out_dev, void* stream);
 
 /* Thread-local text of the last error (empty string if none). */
 const char* miann_last_error(void);

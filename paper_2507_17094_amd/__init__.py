@@ -124,6 +124,8 @@ def load():
     L.miann_index_append.argtypes = [vp, i32, vp, i64, u64, vp]
     L.miann_build_next_map.argtypes = [vp, i32, i32, C.POINTER(SearchParams), vp]
     L.miann_release_scratch.argtypes = [vp]
+    L.miann_gather_probe.argtypes = [vp, i64, i32, vp, i64, vp, vp]
+    L.miann_index_build_times.argtypes = [vp, C.POINTER(C.c_double)]
     L.miann_predictor_labels.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.miann_last_error.restype = C.c_char_p
     L.miann_version.restype = C.c_char_p
@@ -143,13 +145,18 @@ def load():
     L.miann_server_submit.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(SearchParams), C.POINTER(u64)]
     L.miann_server_wait.argtypes = [vp, u64, vp, vp, C.POINTER(C.c_double)]
     L.miann_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.miann_server_warm.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
+    L.miann_server_replay.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, C.POINTER(SearchParams), vp,
+                                      C.POINTER(C.c_double)]
     L.miann_server_destroy.argtypes = [vp]
     L.miann_server_destroy.restype = None
-    for f in ("miann_server_create", "miann_server_submit", "miann_server_wait", "miann_server_get_stats"):
+    for f in ("miann_server_create", "miann_server_submit", "miann_server_wait", "miann_server_get_stats",
+              "miann_server_warm", "miann_server_replay"):
         getattr(L, f).restype = C.c_int
     for f in ("miann_build_graph", "miann_build_ghost", "miann_index_import", "miann_index_shard",
               "miann_index_info", "miann_search", "miann_search_noalloc", "miann_exact_knn", "miann_index_delete",
-              "miann_index_append", "miann_build_next_map", "miann_release_scratch", "miann_predictor_labels", "miann_nearest_ghost", "miann_predictor_create",
+              "miann_index_append", "miann_build_next_map", "miann_release_scratch", "miann_predictor_labels",
+              "miann_gather_probe", "miann_index_build_times", "miann_nearest_ghost", "miann_predictor_create",
               "miann_predictor_view_get", "miann_predictor_sync_weights", "miann_predictor_step",
               "miann_predictor_train", "miann_predictor_predict"):
         getattr(L, f).restype = C.c_int
@@ -267,6 +274,12 @@ class Index:
         S, n, d, deg, st = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().miann_index_info(self._h, C.byref(S), C.byref(n), C.byref(d), C.byref(deg), C.byref(st)))
         return dict(num_shards=S.value, n=n.value, d=d.value, degree=deg.value, store_dtype=st.value)
+
+    def build_times(self) -> dict:
+        """Host seconds of the build steps (graph, direction table, inter-shard map, ghost shards)."""
+        t = (C.c_double * 4)()
+        _check(load().miann_index_build_times(self._h, t))
+        return dict(graph_s=t[0], direction_table_s=t[1], inter_shard_map_s=t[2], ghost_s=t[3])
 
     def save(self, path: str) -> None:
         """Writes the index to a file (originals, graphs, maps and ghost shards)."""
@@ -561,6 +574,36 @@ class Server:
         lat = C.c_double()
         _check(load().miann_server_wait(self._h, ticket, ids.ctypes.data, dists.ctypes.data, C.byref(lat)))
         return ids, dists, lat.value
+
+    def warm(self, nq: int, k: int, itopk: int, max_iters: int, opts: SearchOptions | None = None) -> None:
+        """Sizes every stream's buffers for this shape with one search of nq zero queries per stream."""
+        p = (opts or SearchOptions()).cstruct()
+        _check(load().miann_server_warm(self._h, nq, k, itopk, max_iters, C.byref(p)))
+
+    def replay(self, pool, row_start, nq, ks, itopks, max_iters, arrival_s, opts: SearchOptions | None = None):
+        """Open-loop replay of a request trace (numpy arrays; request j = pool rows row_start[j] : row_start[j] +
+        nq[j] arriving at arrival_s[j] seconds). Returns (latency_ms from the scheduled arrival [n_req], wall s)."""
+        import numpy as np
+        qdt = np.uint8 if self._index.in_dtype == U8 else np.float32
+        pool = np.ascontiguousarray(pool)
+        if pool.dtype != qdt or pool.ndim != 2 or pool.shape[1] != self._d:
+            raise MiannError(1, f"pool: need [n, {self._d}] {np.dtype(qdt)}")
+        n = len(arrival_s)
+        rs = np.ascontiguousarray(row_start, np.int64)
+        nn = np.ascontiguousarray(nq, np.int64)
+        k = np.ascontiguousarray(ks, np.int32)
+        it = np.ascontiguousarray(itopks, np.int32)
+        T = np.ascontiguousarray(max_iters, np.int32)
+        arr = np.ascontiguousarray(arrival_s, np.float64)
+        if any(a.shape != (n,) for a in (rs, nn, k, it, T)):
+            raise MiannError(1, "replay: trace arrays of different lengths")
+        lat = np.empty(n, np.float64)
+        wall = C.c_double()
+        p = (opts or SearchOptions()).cstruct()
+        _check(load().miann_server_replay(self._h, pool.ctypes.data, len(pool), rs.ctypes.data, nn.ctypes.data,
+                                          k.ctypes.data, it.ctypes.data, T.ctypes.data, arr.ctypes.data, n,
+                                          C.byref(p), lat.ctypes.data, C.byref(wall)))
+        return lat, wall.value
 
     def stats(self) -> dict:
         st = ServerStats()

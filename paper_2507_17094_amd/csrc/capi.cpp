@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -92,6 +93,8 @@ struct miann_index {
   int64_t n_total = 0;
   int knn_k0 = 0;           // K0 of the graph build (0 = 2 * degree), reused when a shard is rebuilt
   uint64_t ghost_seed = 0;  // seed of the last ghost sample, reused when a shard is rebuilt
+  // host seconds of the build steps: [graph (k-NN and pruning), direction table, inter-shard map, ghost shards]
+  double build_s[4] = {0, 0, 0, 0};
   std::vector<Shard> sh;
   DenseGhosts dg;  // all shards' ghosts, bf16-split, for the dense entry
   std::vector<void*> allocs;
@@ -213,6 +216,14 @@ miann_status build_dense_ghosts(miann_index* ix, hipStream_t st) {
   }
   HIP_TRY(hipMemcpyAsync(G.off_dev, G.off.data(), (size_t)(ix->S + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G.R_dev, G.R.data(), (size_t)ix->S * 8, hipMemcpyHostToDevice, st));
+  // each shard's largest ghost norm (the dense entry's error bound scales with it)
+  std::vector<float> norms((size_t)G.cols), gmax((size_t)ix->S, 0.f);
+  HIP_TRY(hipMemcpyAsync(norms.data(), G.norm, (size_t)G.cols * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int s = 0; s < ix->S; s++)
+    for (int64_t j = 0; j < G.R[s]; j++) gmax[s] = std::max(gmax[s], norms[(size_t)(G.off[s] + j)]);
+  HIP_TRY(ix->alloc(&G.gmax_dev, (size_t)ix->S * 4, true));
+  HIP_TRY(hipMemcpyAsync(G.gmax_dev, gmax.data(), (size_t)ix->S * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return MIANN_OK;
 }
@@ -256,6 +267,12 @@ const char* miann_last_error(void) { return g_err.c_str(); }
 const char* miann_version(void) { return "miann 0.1 (gfx950)"; }
 
 void miann_index_free(miann_index* idx) { delete idx; }
+
+miann_status miann_index_build_times(const miann_index* idx, double* seconds4) {
+  if (!idx || !seconds4) return fail(MIANN_EINVAL, "miann_index_build_times: null argument");
+  for (int i = 0; i < 4; i++) seconds4[i] = idx->build_s[i];
+  return MIANN_OK;
+}
 
 miann_status miann_index_info(const miann_index* idx, int32_t* num_shards, int64_t* n_total, int32_t* d,
                               int32_t* degree, int32_t* store_dtype) {
@@ -663,6 +680,17 @@ size_t miann_search_scratch_bytes(const miann_index* ix, int64_t nq, int32_t k, 
 
 extern "C" {
 
+miann_status miann_gather_probe(const void* table, int64_t n_rows, int32_t row_bytes, const uint32_t* ids, int64_t n,
+                                uint32_t* out, void* stream) {
+  if (n < 0 || n_rows < 1 || n_rows > (1ll << 32)) return fail(MIANN_EINVAL, "miann_gather_probe: sizes out of range");
+  if (row_bytes % 128 || row_bytes < 128 || row_bytes > 1024 || row_bytes == 640 || row_bytes == 896)
+    return fail(MIANN_EINVAL, "miann_gather_probe: row_bytes %d not in {128, 256, 384, 512, 768, 1024}", row_bytes);
+  if (n > 0 && (!table || !ids || !out)) return fail(MIANN_EINVAL, "miann_gather_probe: null pointer");
+  const hipError_t e = launch_gather_probe(table, n_rows, row_bytes, ids, n, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(MIANN_EDEVICE, "miann_gather_probe: %s", hipGetErrorString(e));
+  return MIANN_OK;
+}
+
 miann_status miann_release_scratch(void* stream) {
   const hipError_t e = scratch_drop_stream((hipStream_t)stream);
   if (e != hipSuccess) return fail(MIANN_EDEVICE, "miann_release_scratch: %s", hipGetErrorString(e));
@@ -763,14 +791,23 @@ miann_status miann_build_graph(const void* base, int64_t n, int32_t d, int32_t i
       if ((rc = gemm_rows(ix, h, tmp, &xf[s]))) break;
       e = ix->alloc(&h.graph, (size_t)h.n * ix->deg * 4);
       if (e != hipSuccess) { rc = fail(MIANN_ENOMEM, "miann_build_graph: graph: %s", hipGetErrorString(e)); break; }
+      hipStreamSynchronize(st);
+      auto t0 = std::chrono::steady_clock::now();
       if ((rc = knn_graph(ix, xf[s], h.orig, h.n, ix->deg, K0, h.graph, st))) break;
+      hipStreamSynchronize(st);
+      auto t1 = std::chrono::steady_clock::now();
+      ix->build_s[0] += std::chrono::duration<double>(t1 - t0).count();
       if (ix->dgs) {
         e = ix->alloc(&h.sign, (size_t)h.n * ix->W * ix->deg * 4);
         if (e == hipSuccess) e = sign_table(h.orig, in_dtype, h.n, d, ix->d_pad_in, h.graph, ix->deg, h.sign, st);
         if (e != hipSuccess) { rc = fail(MIANN_EDEVICE, "miann_build_graph: sign table: %s", hipGetErrorString(e)); break; }
+        hipStreamSynchronize(st);
+        ix->build_s[1] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
       }
     }
     // inter-shard map I_s(u) = argmin over shard (s+1) mod S (Sec. 3.1.2)
+    hipStreamSynchronize(st);
+    const auto t_map = std::chrono::steady_clock::now();
     for (int s = 0; S > 1 && s < S && rc == MIANN_OK; s++) {
       Shard& h = ix->sh[s];
       const Shard& nx = ix->sh[(s + 1) % S];
@@ -785,6 +822,7 @@ miann_status miann_build_graph(const void* base, int64_t n, int32_t d, int32_t i
     }
     if (rc == MIANN_OK) {
       hipError_t e = hipStreamSynchronize(st);
+      ix->build_s[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_map).count();
       if (e == hipSuccess) e = ix->refresh(st);
       if (e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_graph: %s", hipGetErrorString(e));
     }
@@ -823,6 +861,7 @@ namespace {
 // its own exact-k-NN graph and the ghost store, then the dense entry's arrays.
 miann_status build_ghosts(miann_index* ix, const std::vector<int64_t>& R, int deg_g, uint64_t seed, hipStream_t st) {
   hipStreamSynchronize(st);
+  const auto t_ghost = std::chrono::steady_clock::now();
   ix->free_ghost();
   ix->deg_g = deg_g;
   ix->ghost_seed = seed;
@@ -865,6 +904,7 @@ miann_status build_ghosts(miann_index* ix, const std::vector<int64_t>& R, int de
     hipStreamSynchronize(st);
     ix->free_ghost();
   }
+  ix->build_s[3] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_ghost).count();
   hipError_t e = ix->refresh(st);
   if (rc == MIANN_OK && e != hipSuccess) rc = fail(MIANN_EDEVICE, "miann_build_ghost: %s", hipGetErrorString(e));
   return rc;

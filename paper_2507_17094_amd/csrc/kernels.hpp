@@ -59,6 +59,9 @@ struct StageArgs {
 // Bytes of LDS one wave needs for these arguments.
 int stage_lds_bytes(const StageArgs& a);
 hipError_t launch_stage(int dtype, int cpl, const StageArgs& a, hipStream_t st);
+// Random-row gather probe (rows of row_bytes in {128, 256, 384, 512, 768, 1024}).
+hipError_t launch_gather_probe(const void* table, int64_t n_rows, int row_bytes, const uint32_t* ids, int64_t n,
+                               uint32_t* out, hipStream_t st);
 hipError_t launch_merge(const uint64_t* stage_out, int64_t nq, int S, int k, int is_u8, uint32_t* ids, void* dists,
                         hipStream_t st);
 

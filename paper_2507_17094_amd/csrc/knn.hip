@@ -1073,19 +1073,28 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
 // Rows per block of the tile passes for rows of dk elements.
 static int dense_block_rows(int dk) { return dk <= 128 ? 128 : 64; }
 
-// One wave per (row, shard): a bound for pass 2 such that at least kp of the
-// shard's distances lie at or below it. Every lane keeps the two smallest of
-// its 8-column minima (distinct columns); the kp-th smallest of those 128
-// values is such a bound (kp <= 128), and nearly as tight as the kp-th
-// smallest of all the minima. For kp <= 32 the kp-th smallest of the 64 lane
-// minima alone is used: a little looser (about 30 instead of 25 candidates
-// for kp = 24 on the sharded1m mixture) for a sort of 64 32-bit keys instead
-// of 128 64-bit ones. +inf when the shard has fewer than kp groups.
+// One wave per (row, shard): the bound b of pass 2, which keeps every exact
+// top-t ghost of the shard. G_j = qn + gn_j - 2 q.x_j is the GEMM form of the
+// distance to ghost j (split-bf16 products, float32 accumulation), D_j the
+// exact distance (the search's definition), E >= |G_j - D_j|. Every lane keeps
+// the two smallest of its 8-column minima (each the G of a distinct ghost), so
+// the t-th smallest b_t of those values has t ghosts with G <= b_t, hence
+// D <= b_t + E for t ghosts and tau_D (the t-th smallest D) <= b_t + E; an
+// exact top-t ghost j then has G_j <= D_j + E <= tau_D + E <= b_t + 2E = b.
+// E = eps (qn + max_j gn_j): with |q.x| <= (qn + gn) / 2, eps covers the
+// dropped lo.lo term and the residual of the two-term bf16 split (about
+// 3.03 2^-16 |q||x|), the float32 accumulation of 3 dk products (6 dk 2^-24,
+// twice the usual bound in case the matrix cores truncate), the rounding of
+// the norms, of the GEMM form's additions and of the exact distance, with a
+// factor of 2 on the whole. +inf when the shard has fewer than t groups.
 __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int64_t ncols,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ Rs, int s0, int nseg,
                                                           int64_t col0, const int* __restrict__ nrows_dev,
                                                           int64_t nrows_max, int64_t row0, int64_t rows_chunk, int t,
+                                                          const uint32_t* __restrict__ list,
+                                                          const float* __restrict__ qn,
+                                                          const float* __restrict__ gmax, float eps,
                                                           float* __restrict__ bound) {
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t item = (int64_t)blockIdx.x * 4 + wave;
@@ -1095,7 +1104,7 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   if (rl >= rows_chunk || row0 + rl >= n_rows) return;
   const int s = s0 + sl;
   const int64_t R = Rs[s];
-  const int kp = (int)(t + 16 < R ? t + 16 : R);
+  const int kp = (int)(t < R ? t : R);
   const int64_t ng = (R + DG - 1) / DG;
   const float* m = M + rl * (ncols / DG) + (off[s] - col0) / DG;
   // float bits of non-negative values order like the values; 0xFFFFFFFF = none
@@ -1126,7 +1135,9 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
     const uint64_t x = (kp - 1) >= 64 ? w[1] : w[0];
     b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (kp - 1) & 63);
   }
-  if (lane == 0) bound[rl * nseg + sl] = b == 0xFFFFFFFFu ? INFINITY : __uint_as_float(b);
+  const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+  const float E = eps * (qn[qi] + gmax[s]);
+  if (lane == 0) bound[rl * nseg + sl] = b == 0xFFFFFFFFu ? INFINITY : __uint_as_float(b) + 2.f * E;
 }
 
 // Exact distance (the search's definition) of query row q to a stored row, by an 8-lane team; every lane of the
@@ -1337,6 +1348,10 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
 
 namespace {
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+// eps of the dense entry's error bound E = eps (qn + max gn) for rows of dk elements (see dense_bound_kernel).
+float dense_eps(int dk) {
+  return (float)(2.0 * (3.03 * std::ldexp(1.0, -16) + (6.0 * dk + 10.0) * std::ldexp(1.0, -24)));
+}
 // Bytes of the per-query buffers (split query rows, norms, raw rows, start-shard list, counter).
 size_t dense_query_bytes(int store_dt, int64_t nq, int d_pad, int dk) {
   const size_t raw = store_dt == DT_U8 ? 1 : 4;
@@ -1442,7 +1457,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                             ncols / DG, col0, Mg, bnd, cmask);
       hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, ncols, G.off_dev, G.R_dev, s0, nseg,
-                         col0, rc, nq, row0, chunk, t, bnd);
+                         col0, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, dense_eps(dk), bnd);
       launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                             ncols / DG, col0, Mg, bnd, cmask);
       switch (store_dt) {

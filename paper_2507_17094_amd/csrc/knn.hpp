@@ -33,6 +33,7 @@ struct DenseGhosts {
   uint16_t* hi = nullptr;       // [cols][dk] bf16
   uint16_t* lo = nullptr;       // [cols][dk] bf16, x - hi
   float* norm = nullptr;        // [cols]
+  float* gmax_dev = nullptr;    // [S] largest ghost norm of each shard (the dense entry's error bound)
   int64_t* off_dev = nullptr;   // [S + 1]
   int64_t* R_dev = nullptr;     // [S]
   DenseShardDev* shards_dev = nullptr;  // [S]

@@ -382,6 +382,104 @@ miann_status miann_server_wait(miann_server* s, uint64_t ticket, uint32_t* ids, 
   return MIANN_OK;
 }
 
+miann_status miann_server_warm(miann_server* s, int64_t nq, int32_t k, int32_t itopk, int32_t max_iters,
+                               const miann_search_params* sp) {
+  if (!s) return miann_fail(MIANN_EINVAL, "miann_server_warm: null server");
+  if (nq < 1 || nq > s->cfg.max_batch_queries) return miann_fail(MIANN_EINVAL, "miann_server_warm: nq out of range");
+  miann_search_params p;
+  if (sp) p = *sp; else miann_search_params_default(&p);
+  miann_status rc = miann_search(s->idx, nullptr, 0, k, itopk, max_iters, &p, nullptr, nullptr, nullptr, nullptr);
+  if (rc != MIANN_OK) return rc;
+  // every stream runs one search of nq zero queries while no batch is in flight, so that the buffers it keeps
+  // (slot staging, search scratch) reach this shape's size before requests arrive
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] {
+    for (auto& sl : s->slots)
+      if (sl.busy) return false;
+    return s->pending.empty();
+  });
+  for (auto& sl : s->slots) {
+    if (!s->reserve(sl, nq, k)) return miann_fail(MIANN_ENOMEM, "miann_server_warm: buffer allocation failed");
+    void* dq = sl.d_buf;
+    uint32_t* di = (uint32_t*)((char*)dq + (size_t)nq * s->d * s->esize + (size_t)nq * 8);
+    void* dd = (char*)di + (size_t)nq * k * 4;
+    hipError_t e = hipMemsetAsync(dq, 0, (size_t)nq * s->d * s->esize, sl.st);
+    if (e == hipSuccess) {
+      rc = miann_search(s->idx, dq, nq, k, itopk, max_iters, &p, di, dd, nullptr, sl.st);
+      if (rc != MIANN_OK) return rc;
+      e = hipStreamSynchronize(sl.st);
+    }
+    if (e != hipSuccess) return miann_fail(MIANN_EDEVICE, "miann_server_warm: %s", hipGetErrorString(e));
+  }
+  return MIANN_OK;
+}
+
+miann_status miann_server_replay(miann_server* s, const void* queries_host, int64_t pool_rows, const int64_t* row_start,
+                                 const int64_t* nq, const int32_t* k, const int32_t* itopk, const int32_t* max_iters,
+                                 const double* arrival_s, int64_t n_req, const miann_search_params* sp,
+                                 double* latency_ms, double* wall_s) {
+  if (!s || !queries_host || !row_start || !nq || !k || !itopk || !max_iters || !arrival_s || !latency_ms)
+    return miann_fail(MIANN_EINVAL, "miann_server_replay: null argument");
+  if (n_req < 0) return miann_fail(MIANN_EINVAL, "miann_server_replay: n_req < 0");
+  for (int64_t j = 0; j < n_req; j++)
+    if (row_start[j] < 0 || nq[j] < 1 || row_start[j] + nq[j] > pool_rows || (j > 0 && arrival_s[j] < arrival_s[j - 1]))
+      return miann_fail(MIANN_EINVAL, "miann_server_replay: request %lld outside the pool or out of order",
+                        (long long)j);
+  const size_t row_bytes = (size_t)s->d * s->esize;
+  std::vector<uint64_t> tickets((size_t)n_req, 0);
+  std::vector<std::atomic<int>> ready((size_t)n_req);
+  for (auto& r : ready) r.store(0);
+  std::atomic<int> failed{0};
+  std::string err;
+  const auto t0 = clk::now() + std::chrono::milliseconds(2);
+  auto at = [&](int64_t j) {
+    return t0 + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(arrival_s[j]));
+  };
+  // the arrivals: each request is submitted at its scheduled time (sleep until shortly before it, then spin)
+  std::thread sub([&] {
+    for (int64_t j = 0; j < n_req; j++) {
+      const auto when = at(j);
+      const auto early = when - std::chrono::microseconds(200);
+      if (clk::now() < early) std::this_thread::sleep_until(early);
+      while (clk::now() < when) {
+      }
+      uint64_t tk = 0;
+      const miann_status st = miann_server_submit(s, (const char*)queries_host + (size_t)row_start[j] * row_bytes,
+                                                  nq[j], k[j], itopk[j], max_iters[j], sp, &tk);
+      if (st != MIANN_OK) {
+        if (!failed.exchange(1)) err = miann_last_error();
+        ready[(size_t)j].store(2);
+        continue;
+      }
+      tickets[(size_t)j] = tk;
+      ready[(size_t)j].store(1);
+    }
+  });
+  // completions, in arrival order: latency from the scheduled arrival to the batch's completion
+  for (int64_t j = 0; j < n_req; j++) {
+    int rdy;
+    while ((rdy = ready[(size_t)j].load()) == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (rdy != 1) {
+      latency_ms[j] = -1.0;
+      continue;
+    }
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      auto it = s->all.find(tickets[(size_t)j]);
+      r = it->second;
+      s->cv_done.wait(lk, [&] { return r->done; });
+      s->all.erase(it);
+    }
+    latency_ms[j] = r->status == MIANN_OK ? std::chrono::duration<double, std::milli>(r->t_done - at(j)).count() : -1.0;
+    if (r->status != MIANN_OK && !failed.exchange(1)) err = r->err;
+  }
+  sub.join();
+  if (wall_s) *wall_s = std::chrono::duration<double>(clk::now() - t0).count();
+  if (failed.load()) return miann_fail(MIANN_EDEVICE, "miann_server_replay: %s", err.c_str());
+  return MIANN_OK;
+}
+
 miann_status miann_server_get_stats(miann_server* s, miann_server_stats* out) {
   if (!s || !out) return miann_fail(MIANN_EINVAL, "miann_server_get_stats: null argument");
   std::lock_guard<std::mutex> lk(s->mu);

@@ -89,10 +89,37 @@ def test_dense_entry_equidistant_ghosts():
     Q = np.concatenate([np.zeros((16, d), np.float32), 0.5 * X[:16]]).astype(np.float32)
     ox = oracle.build_index(X, deg=16, dgs=True, ghost_R=400, deg_g=8)
     gx = to_device_index(ox)
-    for kw in (dict(entry="ghost_dense"), dict(entry="ghost_dense", dgs=True, t_seeds=48)):
+    for kw in (dict(entry="ghost_dense"), dict(entry="ghost_dense", dgs=True, t_seeds=48),
+               dict(entry="ghost_dense", t_seeds=8), dict(entry="ghost_dense", dgs=True, t_seeds=20)):
         opts = miann.SearchOptions(**kw)
         g, o = run_both(ox, gx, Q, K, 48, 20, opts)
         compare(g, o, label=f"signs-{kw}", ndist_check=False)
+
+
+@pytest.mark.parametrize("t", [8, 20])
+def test_dense_entry_near_ties_inside_the_window(t):
+    """Near ties the GEMM form cannot separate: around each query, 30 ghosts at distances 1 + k 1e-6 (a spacing
+    far below the GEMM form's error bound, but resolved by the exact distance), the other ghosts at distance 2 or
+    more. With every node a ghost and T = 0, the result is the exact top-k of the t seeds, so the seeds must be
+    the exact top-t of the 30 (the window holds all of them and is rescored exactly)."""
+    rng = np.random.default_rng(62)
+    d, n_q = 64, 8
+    Q = (10.0 * rng.standard_normal((n_q, d)) / np.sqrt(d)).astype(np.float32)
+    rows = []
+    for q in Q:
+        u = rng.standard_normal((30, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        r = np.sqrt(1.0 + 1e-6 * rng.permutation(30))[:, None]
+        rows.append(q + u * r)
+        v = rng.standard_normal((30, d))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        rows.append(q + v * (2.0 + rng.random((30, 1))))
+    X = np.concatenate(rows).astype(np.float32)
+    ox = oracle.build_index(X, deg=16, dgs=False, ghost_R=len(X), deg_g=16)
+    gx = to_device_index(ox, dgs=False)
+    opts = miann.SearchOptions(entry="ghost_dense", t_seeds=t)
+    g, o = run_both(ox, gx, Q, t, 32, 0, opts)
+    compare(g, o, min_frac=1.0, label=f"near-ties-t{t}", ndist_check=False)
 
 
 @pytest.mark.parametrize("S", [2, 3])

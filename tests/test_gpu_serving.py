@@ -132,3 +132,33 @@ def test_u8_degree64_dense_entry_mix():
     st = srv.stats()
     assert st["requests_done"] == len(reqs)
     srv.close()
+
+
+def test_warm_and_replay_trace(served):
+    """The native load generator: requests arrive at their scheduled times from a thread of the library, every
+    one completes, latencies run from the scheduled arrival, and a request replayed this way returns what the
+    direct search returns (checked by submitting it again after the replay)."""
+    X, ox, gx = served
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
+    srv = miann.Server(gx, num_streams=4, max_batch_queries=2048)
+    srv.warm(512, 10, 64, 40, opts)
+    srv.warm(512, 32, 64, 40, opts)
+    rng = np.random.default_rng(23)
+    n_req = 200
+    sizes = np.minimum(256, np.floor(np.exp(rng.uniform(0, np.log(257), n_req)))).astype(np.int64)
+    pool = synth.mixture_small(int(sizes.sum()), 64, 16, 0.3, 131)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    ks = rng.choice([10, 32], n_req).astype(np.int32)
+    arrivals = np.cumsum(rng.exponential(0.002, n_req))
+    lat, wall = srv.replay(pool, off[:-1], sizes, ks, np.full(n_req, 64), np.full(n_req, 40), arrivals, opts)
+    say(f"  replay of {n_req} requests over {arrivals[-1]:.3f} s: wall {wall:.3f} s, p50 {np.percentile(lat, 50):.2f} ms"
+        f" p99 {np.percentile(lat, 99):.2f} ms")
+    assert np.all(lat > 0) and wall >= arrivals[-1]
+    st = srv.stats()
+    assert st["requests_done"] >= n_req
+    j = int(np.argmax(sizes))
+    t = srv.submit(pool[off[j]:off[j + 1]], int(ks[j]), 64, 40, opts)
+    ij, dj, _ = srv.wait(t)
+    ri, rd = direct(gx, pool[off[j]:off[j + 1]], int(ks[j]), 64, 40, opts)
+    assert np.array_equal(ij, ri) and np.array_equal(dj, rd)
+    srv.close()
