@@ -314,7 +314,7 @@ FORMS = {
     "learned1m": dict(N=1_000_000, d=96, C=4000, sigma=0.25, n_train=500_000, nq=100_000, deg=32, R=4096, deg_g=32,
                       hidden=256),
     # continuous-batching server on uint8 data (N reduced from 20M)
-    "serving1m": dict(N=1_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32, n_requests=6000),
+    "serving1m": dict(N=1_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32, pool=200_000),
 }
 
 
@@ -506,8 +506,8 @@ def form_learned(args):
 
 
 def form_serving(args):
-    """Poisson request stream into the continuous-batching server: QPS and p50 / p99 latency per rate."""
-    import threading
+    """Poisson request stream into the continuous-batching server, replayed open-loop by the library's own
+    thread: QPS and p50 / p99 latency (from each request's scheduled arrival) per offered load."""
     import torch
     import paper_2507_17094_amd as miann
     import synth
@@ -520,90 +520,86 @@ def form_serving(args):
     torch.cuda.synchronize()
     t_build = time.time() - t0
     rng = np.random.default_rng([synth.SEED_ARRIVALS, 1])
-    n_req = W["n_requests"]
-    sizes = np.minimum(1024, np.floor(np.exp(rng.uniform(0, np.log(1025), n_req)))).astype(int)
-    ks = rng.choice([10, 100], n_req)
-    pool = make_data(int(sizes.sum()), W["d"], W["C"], W["sigma"], synth.SEED_QUERIES, u8=True)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
+    pool = make_data(W["pool"], W["d"], W["C"], W["sigma"], synth.SEED_QUERIES, u8=True)
     opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
+    setting = {10: (64, 32), 100: (128, 64)}
     # recall of the settings used, on the first 20,000 queries of the pool in one batch
     Pd = torch.from_numpy(pool[:20000]).cuda()
     gt, _ = gx.exact_knn(Pd, 100)
     gt = gt.cpu().numpy().view(np.uint32)
-    setting = {10: (64, 32), 100: (128, 64)}
     rec = {}
     for k, (itopk, T) in setting.items():
         ids, _ = gx.search(Pd, k, itopk, T, opts)
         rec[k] = recall(gt[:, :k], ids.cpu().numpy().view(np.uint32), k)
     log(f"build {t_build:.1f}s recall {rec}")
-    # batch capacity on the request mix: the pool's k = 10 and k = 100 queries as one batch each
-    qk = np.repeat(ks, sizes)
+
+    def trace(n_req, rate):
+        sizes = np.minimum(1024, np.floor(np.exp(rng.uniform(0, np.log(1025), n_req)))).astype(np.int64)
+        ks = rng.choice([10, 100], n_req).astype(np.int32)
+        starts = rng.integers(0, len(pool) - 1024, n_req).astype(np.int64)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        return sizes, ks, starts, arrivals
+
+    # batch capacity on the request mix: the mix's queries as one k = 10 batch and one k = 100 batch
+    sizes, ks, _, _ = trace(20000, 1.0)
+    mean_q = float(sizes.mean())
     cap_s = 0.0
+    n10 = int(sizes[ks == 10].sum()) % len(pool)
+    n100 = int(sizes[ks == 100].sum()) % len(pool)
+    for k, nk in ((10, n10), (100, n100)):
+        sub_q = torch.from_numpy(np.ascontiguousarray(pool[:nk])).cuda()
+        itopk, T = setting[k]
+        cap_s += time_search(lambda: gx.search(sub_q, k, itopk, T, opts), reps=2)
+    cap_qps = (n10 + n100) / cap_s
+    mb = args.serve_batch
+    srv = miann.Server(gx, num_streams=4, max_batch_queries=mb, max_inflight_queries=4 * mb,
+                       memory_budget_bytes=8 << 30)
     for k, (itopk, T) in setting.items():
-        sub_q = torch.from_numpy(np.ascontiguousarray(pool[qk == k])).cuda()
-        if len(sub_q):
-            cap_s += time_search(lambda: gx.search(sub_q, k, itopk, T, opts), reps=2)
-    cap_qps = len(pool) / cap_s
-    # latency floor: single-query requests one at a time on an idle server
-    srv = miann.Server(gx, num_streams=4, max_batch_queries=8192, max_inflight_queries=65536)
-    idle = []
-    for j in range(60):
-        tk = srv.submit(pool[j:j + 1], 10, *setting[10], opts)
-        idle.append(srv.wait(tk, 1, 10)[2])
-    srv.close()
-    idle = np.array(idle[10:])
+        srv.warm(mb, k, itopk, T, opts)
+    # latency floor: single-query requests 2 ms apart on an idle server
+    n_idle = 200
+    lat, _ = srv.replay(pool, np.arange(n_idle), np.ones(n_idle), np.full(n_idle, 10), np.full(n_idle, setting[10][0]),
+                        np.full(n_idle, setting[10][1]), 0.002 * np.arange(n_idle), opts)
+    idle = lat[20:]
     log(f"idle single-query latency p50 {np.percentile(idle, 50):.3f} ms p99 {np.percentile(idle, 99):.3f} ms")
+    # the server's own capacity on the mix: a burst of requests all due at once
+    sizes, ks, starts, _ = trace(int(0.5 * cap_qps / mean_q), 1.0)
+    its = np.where(ks == 10, setting[10][0], setting[100][0])
+    Ts = np.where(ks == 10, setting[10][1], setting[100][1])
+    _, wall = srv.replay(pool, starts, sizes, ks, its, Ts, np.zeros(len(sizes)), opts)
+    srv_qps = float(sizes.sum()) / wall
+    log(f"server capacity (burst of {len(sizes)} requests): {srv_qps:,.0f} queries/s; offline batches {cap_qps:,.0f}")
     results = []
-    for load_frac in (0.25, 0.5, 0.75):
-        mean_q = float(sizes.mean())
+    for load_frac in (0.1, 0.3, 0.5, 0.7, 0.9):
         rate = load_frac * cap_qps / mean_q  # requests per second
-        gaps = rng.exponential(1.0 / rate, n_req)
-        srv = miann.Server(gx, num_streams=4, max_batch_queries=8192, max_inflight_queries=65536)
-        # first use of each stream and search shape, outside the measured stream of requests
-        for kk in (10, 100):
-            warm = [srv.submit(pool[:1024], kk, *setting[kk], opts) for _ in range(4)]
-            for tk in warm:
-                srv.wait(tk, 1024, kk)
-        batches0 = srv.stats()["batches"]
-        tickets = [None] * n_req
-        lat = np.zeros(n_req)
-
-        def collector():
-            for j in range(n_req):
-                while tickets[j] is None:
-                    time.sleep(0.0002)
-                _, _, lat[j] = srv.wait(tickets[j], int(sizes[j]), int(ks[j]))
-
-        th = threading.Thread(target=collector)
-        th.start()
-        t_start = time.perf_counter()
-        nxt = t_start
-        for j in range(n_req):
-            nxt += gaps[j]
-            dt = nxt - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            itopk, T = setting[int(ks[j])]
-            tickets[j] = srv.submit(pool[offs[j]:offs[j + 1]], int(ks[j]), itopk, T, opts)
-        th.join()
-        wall = time.perf_counter() - t_start
+        n_req = int(rate * args.serve_seconds)
+        sizes, ks, starts, arrivals = trace(n_req, rate)
+        its = np.where(ks == 10, setting[10][0], setting[100][0])
+        Ts = np.where(ks == 10, setting[10][1], setting[100][1])
+        b0 = srv.stats()["batches"]
+        lat, wall = srv.replay(pool, starts, sizes, ks, its, Ts, arrivals, opts)
         st = srv.stats()
-        srv.close()
-        results.append(dict(offered_load=load_frac, request_rate=rate, qps=float(sizes.sum()) / wall,
+        results.append(dict(offered_load=load_frac, request_rate=rate, requests=n_req,
+                            duration_s=float(arrivals[-1]), qps=float(sizes.sum()) / wall,
                             p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                            batches=st["batches"] - batches0, peak_inflight_queries=st["peak_inflight_queries"]))
-        log(f"  load {load_frac:.2f} rate {rate:,.0f} req/s: qps {results[-1]['qps']:,.0f} "
-            f"p50 {results[-1]['p50_ms']:.2f} ms p99 {results[-1]['p99_ms']:.2f} ms batches {st['batches'] - batches0}")
+                            p999_ms=float(np.percentile(lat, 99.9)), batches=st["batches"] - b0,
+                            peak_inflight_queries=st["peak_inflight_queries"]))
+        r = results[-1]
+        log(f"  load {load_frac:.2f} rate {rate:,.0f} req/s over {r['duration_s']:.1f} s: qps {r['qps']:,.0f} "
+            f"p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms p99.9 {r['p999_ms']:.2f} ms batches {r['batches']}")
+    srv.close()
     head = results[-1]
     out = {
-        "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
-        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
+        "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": head["requests"],
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"serving1m: N={W['N']} d={W['d']} uint8 ({W['C']}-component mixture), degree "
-                               f"{W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; Poisson arrivals, requests of "
-                               f"1-1024 queries (log-uniform), k in {{10, 100}}"},
+                               f"{W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; Poisson "
+                               f"arrivals replayed by the library's thread, {args.serve_seconds} s per load, "
+                               f"requests of 1-1024 queries (log-uniform), k in {{10, 100}}"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
-        "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps, "rates": results,
+        "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps,
+        "server_capacity_qps": srv_qps, "max_batch_queries": mb, "rates": results,
         "idle_single_query_ms": {"p50": float(np.percentile(idle, 50)), "p99": float(np.percentile(idle, 99))},
         "build_s": t_build,
     }
@@ -633,6 +629,9 @@ def main():
                          "rocprofv3 --stats csv to the profiles record")
     ap.add_argument("--gather-probe", action="store_true",
                     help="only measure the random-row gather ceiling (rows of 384, 512 and 1024 bytes)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="serving1m: seconds of Poisson arrivals per offered load")
+    ap.add_argument("--serve-batch", type=int, default=32768, help="serving1m: largest batch the server forms")
     ap.add_argument("--lut", type=int, default=1,
                     help="also compare the search-built shard-to-shard lookup table with the exact 1-NN map")
     args = ap.parse_args()

@@ -604,7 +604,9 @@ template <int DT, int CPL, int OCC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 void stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) char smem[];
-  const int wave = threadIdx.x >> 6;
+  // the wave index is the same on every lane: held in a scalar register, so that what follows from it (the
+  // query, its shard and the shard's arrays) is scalar too and leaves the vector registers to the search
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t q = (int64_t)blockIdx.x * a.waves_per_block + wave;
   if (q >= a.nq) return;
 

@@ -1,11 +1,12 @@
 // Continuous-batching serving loop over a resident index.
 //
 // Requests (host query rows + k, itopk, T and search parameters) are queued by
-// miann_server_submit from any thread. A scheduler thread forms batches: it
-// takes the oldest pending request and coalesces every pending request with the
-// same search shape (k, itopk, T, parameters) up to max_batch_queries, then
-// admits the batch only while the queries and device bytes already in flight
-// stay within the configured limits. Each admitted batch runs on one of
+// miann_server_submit from any thread. Pending requests wait in one FIFO per
+// search shape (k, itopk, T, parameters). A scheduler thread forms batches: it
+// takes the shape whose first request is the oldest and coalesces that FIFO's
+// requests in arrival order up to max_batch_queries, admitting each only while
+// the queries and device bytes already in flight stay within the configured
+// limits (forming a batch costs time in its size, not in the queue's length). Each admitted batch runs on one of
 // num_streams HIP streams (default priority), so batches that arrive while
 // others are running overlap on the device. Every query is searched with its
 // index inside its own request as the query key, so a result is the same
@@ -84,7 +85,12 @@ struct miann_server {
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Request>> pending;
+  struct ShapeQueue {
+    std::shared_ptr<Request> rep;  // a request of this shape (the key)
+    std::deque<std::shared_ptr<Request>> q;
+  };
+  std::vector<ShapeQueue> pending;  // one FIFO per search shape
+  int64_t n_pending = 0;
   std::map<uint64_t, std::shared_ptr<Request>> all;
   uint64_t next_ticket = 1;
   int64_t inflight_q = 0;
@@ -204,30 +210,32 @@ void miann_server::loop() {
     std::vector<std::pair<Slot*, std::vector<std::shared_ptr<Request>>>> todo;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (stop && pending.empty()) {
+      if (stop && n_pending == 0) {
         bool any = false;
         for (auto& s : slots) any |= s.busy;
         if (!any) return;
       }
       for (auto& s : slots) {
-        if (s.busy || pending.empty()) continue;
+        if (s.busy || n_pending == 0) continue;
         bool claimed = false;
         for (auto& t : todo) claimed |= (t.first == &s);
         if (claimed) continue;
-        auto head = pending.front();
+        // the shape whose first request is the oldest
+        ShapeQueue* g = nullptr;
+        for (auto& x : pending)
+          if (!x.q.empty() && (!g || x.q.front()->ticket < g->q.front()->ticket)) g = &x;
+        auto head = g->q.front();
         std::vector<std::shared_ptr<Request>> batch;
         int64_t nq = 0;
-        for (auto it = pending.begin(); it != pending.end();) {
-          const auto& r = *it;
-          if (same_shape(*r, *head) && nq + r->nq <= cfg.max_batch_queries &&
-              inflight_q + nq + r->nq <= cfg.max_inflight_queries &&
-              inflight_b + batch_bytes(nq + r->nq, *head) <= (size_t)cfg.memory_budget_bytes) {
-            nq += r->nq;
-            batch.push_back(r);
-            it = pending.erase(it);
-          } else {
-            ++it;
-          }
+        while (!g->q.empty()) {
+          const auto& r = g->q.front();
+          if (nq + r->nq > cfg.max_batch_queries || inflight_q + nq + r->nq > cfg.max_inflight_queries ||
+              inflight_b + batch_bytes(nq + r->nq, *head) > (size_t)cfg.memory_budget_bytes)
+            break;
+          nq += r->nq;
+          batch.push_back(r);
+          g->q.pop_front();
+          n_pending--;
         }
         if (batch.empty()) break;  // the oldest request must wait for capacity
         inflight_q += nq;
@@ -237,6 +245,8 @@ void miann_server::loop() {
         stats.batches++;
         todo.emplace_back(&s, std::move(batch));
       }
+      pending.erase(std::remove_if(pending.begin(), pending.end(), [](const ShapeQueue& x) { return x.q.empty(); }),
+                    pending.end());
     }
     for (auto& t : todo) {
       if (!launch(*t.first, t.second)) {
@@ -258,7 +268,7 @@ void miann_server::loop() {
     for (auto& s : slots) busy |= s.busy;
     std::unique_lock<std::mutex> lk(mu);
     if (busy) cv_work.wait_for(lk, std::chrono::microseconds(50));
-    else if (pending.empty() && !stop) cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    else if (n_pending == 0 && !stop) cv_work.wait_for(lk, std::chrono::milliseconds(5));
   }
 }
 
@@ -355,7 +365,11 @@ miann_status miann_server_submit(miann_server* s, const void* queries, int64_t n
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return miann_fail(MIANN_ESTATE, "miann_server_submit: server is shutting down");
     r->ticket = s->next_ticket++;
-    s->pending.push_back(r);
+    auto g = std::find_if(s->pending.begin(), s->pending.end(),
+                          [&](const miann_server::ShapeQueue& x) { return same_shape(*x.rep, *r); });
+    if (g == s->pending.end()) g = s->pending.insert(s->pending.end(), miann_server::ShapeQueue{r, {}});
+    g->q.push_back(r);
+    s->n_pending++;
     s->all[r->ticket] = r;
   }
   s->cv_work.notify_one();
@@ -396,7 +410,7 @@ miann_status miann_server_warm(miann_server* s, int64_t nq, int32_t k, int32_t i
   s->cv_done.wait(lk, [&] {
     for (auto& sl : s->slots)
       if (sl.busy) return false;
-    return s->pending.empty();
+    return s->n_pending == 0;
   });
   for (auto& sl : s->slots) {
     if (!s->reserve(sl, nq, k)) return miann_fail(MIANN_ENOMEM, "miann_server_warm: buffer allocation failed");
