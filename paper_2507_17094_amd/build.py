@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmiann.so")
-SOURCES = ["search_f32.hip", "search_f16.hip", "search_fp8.hip", "search_u8.hip", "search.hip", "build.hip", "knn.hip", "mlp.hip", "noalloc.hip", "probe.hip", "capi.cpp", "predictor.cpp", "serve.cpp", "pool.cpp", "persist.cpp"]
+SOURCES = ["search_f32.hip", "search_f16.hip", "search_fp8.hip", "search_u8.hip", "search.hip", "build.hip", "knn.hip", "knn_split.hip", "mlp.hip", "noalloc.hip", "probe.hip", "capi.cpp", "predictor.cpp", "serve.cpp", "pool.cpp", "persist.cpp"]
 ARCH = os.environ.get("MIANN_ARCH", "gfx950")
 
 FLAGS = [

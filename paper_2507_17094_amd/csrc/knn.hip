@@ -444,7 +444,12 @@ hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t
     hipLaunchKernelGGL(norms_kernel<float>, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, B_f32, nb, dpf, bn);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = launch_tiles<float>(A_f32, an, na, nullptr, nullptr, B_f32, bn, nb, dpf, kp, exclude_self, cand, st);
+  if (e == hipSuccess) {
+    if (knn_split_supported(dpf, kp))
+      e = knn_split_select(A_f32, na, B_f32, nb, dpf, kp, exclude_self, cand, st);
+    else
+      e = launch_tiles<float>(A_f32, an, na, nullptr, nullptr, B_f32, bn, nb, dpf, kp, exclude_self, cand, st);
+  }
   // rows of `cand` are indexed by position; rescoring reads query row qlist[r] (or r)
   if (e == hipSuccess) e = launch_rescore(raw_dt, cand, na, nullptr, kp, qlist, A_raw, B_raw, B_scale, b_raw_pad, k, out, st);
   if (an) hipFreeAsync(an, st);
