@@ -445,8 +445,9 @@ hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    if (knn_split_supported(dpf, kp))
-      e = knn_split_select(A_f32, na, B_f32, nb, dpf, kp, exclude_self, cand, st);
+    const int u8 = raw_dt == DT_U8;
+    if (knn_split_supported(dpf, kp, u8))
+      e = knn_split_select(A_f32, na, B_f32, nb, dpf, kp, exclude_self, u8, cand, st);
     else
       e = launch_tiles<float>(A_f32, an, na, nullptr, nullptr, B_f32, bn, nb, dpf, kp, exclude_self, cand, st);
   }

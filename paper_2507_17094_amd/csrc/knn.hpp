@@ -63,12 +63,13 @@ hipError_t knn_exact(const float* A_f32, int64_t na, const float* B_f32, int64_t
                      int raw_dt, const void* A_raw, int a_raw_pad, const void* B_raw, const float* B_scale,
                      int b_raw_pad, int k, int exclude_self, const uint32_t* qlist, uint64_t* out, hipStream_t st);
 
-// Candidate selection of the exact k-NN on the bf16 matrix cores (split operands, knn_split.hip): the kp
-// smallest GEMM-form keys (dist bits << 32 | B row) of each A row, ascending, in out[na][kp]. Rows of dpf
-// elements, dpf a multiple of 32 up to 256, and kp up to 192.
-bool knn_split_supported(int dpf, int kp);
+// Candidate selection of the exact k-NN on the matrix cores (knn_split.hip): the kp smallest GEMM-form keys
+// (dist bits << 32 | B row) of each A row, ascending, in out[na][kp]. Float rows go through split bf16
+// operands (dpf a multiple of 32 up to 256); uint8 rows (u8 != 0: the f32 copies hold integers 0..255) through
+// exact int8 products (dpf up to 256). kp up to 192.
+bool knn_split_supported(int dpf, int kp, int u8);
 hipError_t knn_split_select(const float* A_f32, int64_t na, const float* B_f32, int64_t nb, int dpf, int kp,
-                            int exclude_self, uint64_t* out, hipStream_t st);
+                            int exclude_self, int u8, uint64_t* out, hipStream_t st);
 
 // Prepares padded f32 copies of queries (f32 or u8 rows of length d).
 hipError_t queries_to_f32(const void* q, int q_dt, int64_t nq, int d, int dpf, float* out, hipStream_t st);
