@@ -307,14 +307,21 @@ def gather_probe(args):
 
 
 FORMS = {
-    # FP16 / FP8-e4m3 traversal with FP32 rerank (N reduced from 5M so the exact-kNN build fits a run)
-    "lowprec1m": dict(N=1_000_000, d=256, C=2000, sigma=0.2, nq=100_000, deg=64, knn_k0=96, ghost_ratio=0.01,
-                      deg_g=32),
-    # learned entry / budget predictor (N reduced from 10M; 4,096 ghosts, MLP 96-256-256-4097)
-    "learned1m": dict(N=1_000_000, d=96, C=4000, sigma=0.25, n_train=500_000, nq=100_000, deg=32, R=4096, deg_g=32,
-                      hidden=256),
-    # continuous-batching server on uint8 data (N reduced from 20M)
-    "serving1m": dict(N=1_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32, pool=200_000),
+    # FP16 / FP8-e4m3 traversal with FP32 rerank: the stated size (5M x 256, degree 64) and a 1M cut of it
+    "lowprec5m": dict(kind="lowprec", N=5_000_000, d=256, C=2000, sigma=0.2, nq=100_000, deg=64, knn_k0=128,
+                      ghost_ratio=0.01, deg_g=32),
+    "lowprec1m": dict(kind="lowprec", N=1_000_000, d=256, C=2000, sigma=0.2, nq=100_000, deg=64, knn_k0=128,
+                      ghost_ratio=0.01, deg_g=32),
+    # learned entry / budget predictor (4,096 ghosts, MLP 96-256-256-4097): the stated 10M and a 1M cut
+    "learned10m": dict(kind="learned", N=10_000_000, d=96, C=4000, sigma=0.25, n_train=500_000, nq=100_000, deg=32,
+                       R=4096, deg_g=32, hidden=256),
+    "learned1m": dict(kind="learned", N=1_000_000, d=96, C=4000, sigma=0.25, n_train=500_000, nq=100_000, deg=32,
+                      R=4096, deg_g=32, hidden=256),
+    # continuous-batching server on uint8 data: the stated 20M x 128 and a 1M cut
+    "serving20m": dict(kind="serving", N=20_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32,
+                       pool=200_000),
+    "serving1m": dict(kind="serving", N=1_000_000, d=128, C=1000, sigma=0.3, deg=64, ghost_ratio=0.01, deg_g=32,
+                      pool=200_000),
 }
 
 
@@ -356,12 +363,35 @@ def time_search(fn, reps=3):
     return (time.perf_counter() - t) / reps
 
 
-def form_lowprec(args):
-    """Recall and QPS of FP32, FP16 and FP8 traversal (FP32 rerank) at k = 10 and k = 100."""
+def cpu_gt_check(X, Q, gt_gpu, k, nq):
+    """The GPU ground truth of the first nq queries against a CPU brute force (float64 GEMM form over row
+    chunks): the fraction of identical top-k id lists and the recall of the GPU lists against the CPU's."""
+    Qs = Q[:nq].astype(np.float64)
+    qn = (Qs * Qs).sum(1)
+    best_d = np.full((nq, k), np.inf)
+    best_i = np.zeros((nq, k), np.int64)
+    step = 262_144
+    for r0 in range(0, len(X), step):
+        Xc = X[r0:r0 + step].astype(np.float64)
+        D = qn[:, None] + (Xc * Xc).sum(1)[None, :] - 2.0 * (Qs @ Xc.T)
+        part = np.argpartition(D, k - 1, axis=1)[:, :k] if D.shape[1] > k else np.argsort(D, axis=1)
+        cd = np.take_along_axis(D, part, 1)
+        ad = np.concatenate([best_d, cd], 1)
+        ai = np.concatenate([best_i, part + r0], 1)
+        o = np.lexsort((ai, ad), axis=1)[:, :k]
+        best_d, best_i = np.take_along_axis(ad, o, 1), np.take_along_axis(ai, o, 1)
+    g = gt_gpu[:nq, :k].astype(np.int64)
+    same = float(np.mean([np.array_equal(np.sort(a), np.sort(b)) for a, b in zip(g, best_i)]))
+    return {"queries": nq, "k": k, "id_sets_identical": same, "recall_vs_cpu": recall(best_i, g, k)}
+
+
+def form_lowprec(args, name="lowprec1m", quick=False):
+    """Recall and QPS of FP32, FP16 and FP8 traversal (FP32 rerank) at k = 10 and k = 100 (quick: one queue
+    length and budget per k, no CPU check of the ground truth)."""
     import torch
     import paper_2507_17094_amd as miann
     import synth
-    W = FORMS["lowprec1m"]
+    W = FORMS[name]
     X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE)
     Q = make_data(W["nq"], W["d"], W["C"], W["sigma"], synth.SEED_QUERIES)
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
@@ -372,18 +402,27 @@ def form_lowprec(args):
     t_build = time.time() - t0
     log(f"build {t_build:.1f}s")
     idx = {"f32": g32, "f16": reimport(g32, Xd, "f16"), "fp8": reimport(g32, Xd, "fp8")}
+    t0 = time.time()
     gt100, _ = g32.exact_knn(Qd, 100)
     gt100 = gt100.cpu().numpy().view(np.uint32)
+    t_gt = time.time() - t0
+    gt_check = None
+    if args.gt_check and not quick:
+        t0 = time.time()
+        gt_check = cpu_gt_check(X, Q, gt100, 100, args.gt_check)
+        log(f"ground truth {t_gt:.1f}s; CPU check of {args.gt_check} queries {time.time() - t0:.1f}s: {gt_check}")
     # exact nearest ghosts as the entry: the mixture's k-NN graph splits into one component per mixture
     # component, so the entry must land in the query's component
     opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
     res = {}
-    for k, itopks in ((10, (32, 64, 128)), (100, (128, 256, 512))):
+    grid = ((10, (32,), (32,)), (100, (256,), (64,))) if quick else \
+        ((10, (32, 64, 128), (32, 64, 128)), (100, (128, 256, 512), (32, 64, 128)))
+    for k, itopks, Ts in grid:
         gt = gt100[:, :k]
         for name, gx in idx.items():
             rows = []
             for itopk in itopks:
-                for T in (32, 64, 128):
+                for T in Ts:
                     if T > 2 * itopk:
                         continue
                     ids, _ = gx.search(Qd, k, itopk, T, opts)
@@ -405,25 +444,25 @@ def form_lowprec(args):
         "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
         "ms_per_step": W["nq"] / head["qps"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
-        "config": {"workload": f"lowprec1m: N={W['N']} d={W['d']} f32 vectors ({W['C']}-component mixture, std "
+        "config": {"workload": f"{name}: N={W['N']} d={W['d']} f32 vectors ({W['C']}-component mixture, std "
                                f"{W['sigma']}) traversed as FP16 / FP8-e4m3 with per-vector scale, FP32 rerank of "
                                f"4k; degree {W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; "
                                f"{W['nq']} queries",
                    "headline": "fp8, k=10"},
         "forms": {f"{n}_k{k}": {"best": res[(n, k)]["best"], "sweep": res[(n, k)]["rows"]}
                   for n in ("f32", "f16", "fp8") for k in (10, 100)},
-        "build_s": t_build,
+        "build_s": t_build, "ground_truth_s": t_gt, "ground_truth_cpu_check": gt_check,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def form_learned(args):
+def form_learned(args, name="learned1m"):
     """Ghost staging versus the learned entry / budget predictor at recall@10 >= 0.95."""
     import torch
     import paper_2507_17094_amd as miann
     from paper_2507_17094_amd import learned
     import synth
-    W = FORMS["learned1m"]
+    W = FORMS[name]
     X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE)
     Qtr = make_data(W["n_train"], W["d"], W["C"], W["sigma"], synth.SEED_HELDOUT)
     Q = make_data(W["nq"], W["d"], W["C"], W["sigma"], synth.SEED_QUERIES)
@@ -494,7 +533,7 @@ def form_learned(args):
         "metric": METRIC, "value": bl["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
         "ms_per_step": W["nq"] / bl["qps"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"learned1m: N={W['N']} d={W['d']} f32 ({W['C']}-component mixture), degree "
+        "config": {"workload": f"{name}: N={W['N']} d={W['d']} f32 ({W['C']}-component mixture), degree "
                                f"{W['deg']}, {W['R']} ghosts; BF16 MLP {W['d']}-{W['hidden']}-{W['hidden']}-"
                                f"{W['R'] + 1} trained on {W['n_train']} queries, {W['nq']} held-out queries"},
         "matched_recall": r_match, "ghost_staging": bg, "ghost_staging_dense": bd, "learned": bl,
@@ -502,16 +541,17 @@ def form_learned(args):
         "train": {"labels_s": t_labels, "train_s": t_train, "losses": losses}, "predict_ms": t_predict * 1e3,
         "sweep": rows, "build_s": t_build,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def form_serving(args):
+def form_serving(args, name="serving1m", quick=False):
     """Poisson request stream into the continuous-batching server, replayed open-loop by the library's own
-    thread: QPS and p50 / p99 latency (from each request's scheduled arrival) per offered load."""
+    thread: QPS and p50 / p99 latency (from each request's scheduled arrival) per offered load (quick: three
+    loads of a few seconds each)."""
     import torch
     import paper_2507_17094_amd as miann
     import synth
-    W = FORMS["serving1m"]
+    W = FORMS[name]
     X = make_data(W["N"], W["d"], W["C"], W["sigma"], synth.SEED_BASE, u8=True)
     Xd = torch.from_numpy(X).cuda()
     t0 = time.time()
@@ -570,9 +610,10 @@ def form_serving(args):
     srv_qps = float(sizes.sum()) / wall
     log(f"server capacity (burst of {len(sizes)} requests): {srv_qps:,.0f} queries/s; offline batches {cap_qps:,.0f}")
     results = []
-    for load_frac in (0.1, 0.3, 0.5, 0.7, 0.9):
+    seconds = min(args.serve_seconds, 4.0) if quick else args.serve_seconds
+    for load_frac in (0.1, 0.5, 0.9) if quick else (0.1, 0.3, 0.5, 0.7, 0.9):
         rate = load_frac * cap_qps / mean_q  # requests per second
-        n_req = int(rate * args.serve_seconds)
+        n_req = int(rate * seconds)
         sizes, ks, starts, arrivals = trace(n_req, rate)
         its = np.where(ks == 10, setting[10][0], setting[100][0])
         Ts = np.where(ks == 10, setting[10][1], setting[100][1])
@@ -593,9 +634,9 @@ def form_serving(args):
         "metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": head["requests"],
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"serving1m: N={W['N']} d={W['d']} uint8 ({W['C']}-component mixture), degree "
+        "config": {"workload": f"{name}: N={W['N']} d={W['d']} uint8 ({W['C']}-component mixture), degree "
                                f"{W['deg']}, ghost staging 1% (exact nearest ghosts), direction filter; Poisson "
-                               f"arrivals replayed by the library's thread, {args.serve_seconds} s per load, "
+                               f"arrivals replayed by the library's thread, {seconds} s per load, "
                                f"requests of 1-1024 queries (log-uniform), k in {{10, 100}}"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "recall": {f"recall@{k}": v for k, v in rec.items()}, "batch_capacity_qps": cap_qps,
@@ -603,7 +644,7 @@ def form_serving(args):
         "idle_single_query_ms": {"p50": float(np.percentile(idle, 50)), "p99": float(np.percentile(idle, 99))},
         "build_s": t_build,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -632,6 +673,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="serving1m: seconds of Poisson arrivals per offered load")
     ap.add_argument("--serve-batch", type=int, default=32768, help="serving1m: largest batch the server forms")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="default workload: also run the low-precision and serving forms (1M cuts, short)")
+    ap.add_argument("--gt-check", type=int, default=1000,
+                    help="lowprec workloads: queries whose GPU ground truth is checked against a CPU brute force")
     ap.add_argument("--lut", type=int, default=1,
                     help="also compare the search-built shard-to-shard lookup table with the exact 1-NN map")
     args = ap.parse_args()
@@ -660,7 +705,10 @@ def main():
         sys.exit(2)
 
     if args.workload in FORMS:
-        {"lowprec1m": form_lowprec, "learned1m": form_learned, "serving1m": form_serving}[args.workload](args)
+        if FORMS[args.workload]["N"] > 2_000_000:
+            os.environ["MIANN_PROGRESS"] = "1"  # the k-NN selection reports each launch of a long build
+        fn = {"lowprec": form_lowprec, "learned": form_learned, "serving": form_serving}[FORMS[args.workload]["kind"]]
+        print(json.dumps(fn(args, args.workload)), flush=True)
         return
 
     import torch
@@ -909,6 +957,19 @@ def main():
         out["cpu_baseline"] = {"value": m / t_cpu, "unit": "queries/s", "cores": oracle.threads(), "kind": "oracle",
                                "sample": f"first {m} of the {nq} queries, same index and parameters"}
         out["parity_full_size"] = {"queries": m, "id_lists_identical": float(np.all(gi == oi, axis=1).mean())}
+    if args.forms and not args.fixed:
+        # the low-precision and serving forms on their 1M cuts, in short form (`--workload lowprec5m` and
+        # `--workload serving20m` run them at full size); the headline index is released first
+        del gx
+        torch.cuda.synchronize()
+        forms = {}
+        for fname, fn in (("lowprec1m", form_lowprec), ("serving1m", form_serving)):
+            log(f"form {fname} (short)")
+            r = fn(args, fname, quick=True)
+            keep = ("value", "dtype", "config", "forms", "latency_ms", "recall", "rates", "server_capacity_qps",
+                    "batch_capacity_qps", "idle_single_query_ms", "build_s")
+            forms[fname] = {k_: r[k_] for k_ in keep if k_ in r}
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 

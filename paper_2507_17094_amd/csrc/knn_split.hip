@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <type_traits>
 
@@ -366,7 +369,15 @@ hipError_t knn_split_select(const float* A_f32, int64_t na, const float* B_f32, 
   const float* An = same ? bnrm : an;
   const void* Al = u8 || !Ab ? nullptr : (const void*)((const uint16_t*)Ab + (size_t)(same ? nb_pad : na_pad) * dk);
   const void* Bl = u8 || !bb ? nullptr : (const void*)((const uint16_t*)bb + (size_t)nb_pad * dk);
+  // MIANN_PROGRESS set: a line on stderr after each launch of a selection that takes several (the stream is
+  // waited on for it)
+  static const bool progress = std::getenv("MIANN_PROGRESS") != nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
   for (int64_t row0 = 0; row0 < na_pad && e == hipSuccess; row0 += rows_per) {
+    if (progress && row0 > 0 && hipStreamSynchronize(st) == hipSuccess)
+      std::fprintf(stderr, "k-NN selection: %lld of %lld rows against %lld in %.1f s\n", (long long)row0,
+                   (long long)na, (long long)nb,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
     const int64_t rows = std::min<int64_t>(rows_per, na_pad - row0);
     const dim3 grid((unsigned)(rows / KR));
     const int key = dk * 2 + (u8 ? 1 : 0);
