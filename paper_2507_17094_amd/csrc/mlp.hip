@@ -2,6 +2,8 @@
 // d_in -> hidden -> hidden -> (R entry logits + 1 budget) trained on traces of
 // the search itself. GEMMs run on the gfx950 BF16 matrix cores
 // (v_mfma_f32_32x32x16_bf16) with FP32 accumulation and FP32 master weights.
+#include <type_traits>
+
 #include "common.hpp"
 #include "mlp.hpp"
 
@@ -377,6 +379,282 @@ hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_
   else
     hipLaunchKernelGGL(readout_kernel<0>, g, dim3(256), 0, st, Z, n, R, t, tau, gmap, t_min, t_max, budget_scale,
                        seeds, iters, conf, top_idx);
+  return hipGetLastError();
+}
+
+// The output layer and the read-out without storing the logits (inference): Z = H2 W3 + b3 is formed tile by
+// tile on the matrix cores (the same products, in the same order, as the output-layer GEMM) and consumed in
+// registers. A block owns 128 rows (a wave 32, with their H2 fragments in registers) and sweeps the output
+// columns twice in tiles of 64 through LDS (the next tile read while the current one is multiplied). The
+// first sweep keeps, per row, the maximum entry logit and a list of candidate keys (value descending, index
+// ascending) in global memory: a logit joins when it is above the t-th largest kept so far (later columns
+// have larger indices, so an equal logit never ranks above it), and a list within 64 keys of its 256 is cut.
+// The second sweep sums exp(z - maximum) (confidence = 1 / sum). Columns past the entry logits get bias
+// -inf (so they drop out of both); column R's logit sets the budget. The outputs are those of the read-out
+// kernel. lists: [blocks * 128][256] scratch.
+__device__ __forceinline__ uint64_t logit_key(uint32_t j, float v) {
+  const uint32_t fb = __float_as_uint(v);
+  const uint32_t ord = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);  // order-preserving
+  return ((uint64_t)(~ord) << 32) | (uint64_t)j;
+}
+__device__ __forceinline__ float key_logit(uint64_t key) {
+  const uint32_t ord = ~(uint32_t)(key >> 32);
+  return __uint_as_float((ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord);
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Cuts one row's list (n <= 256 keys, written by this wave) without sorting it: the t-th best of the 64 lanes'
+// best keys bounds the t-th best key of the list from below in rank, so every key at or before it in key order
+// is kept (the true t best among them, at most 4 t keys in all); when more than 128 stay, the list is sorted
+// and cut to its t best. The kept keys are written back in place; returns their number, and the key a new
+// logit must beat (in kth).
+__device__ __forceinline__ int cut_logits(uint64_t* __restrict__ L, int n, int t, int lane, uint64_t& kth) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // the wave's own appends are visible
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < n ? L[r * 64 + lane] : ~0ull;
+  uint64_t mk = v[0];
+#pragma unroll
+  for (int r = 1; r < 4; r++) mk = v[r] < mk ? v[r] : mk;
+  const uint64_t srt = bitonic_sort_u64<64>(mk);
+  uint64_t bound = t <= 64 ? readlane64(srt, t - 1) : ~0ull;
+  int keep = 0;
+#pragma unroll
+  for (int r = 0; r < 4; r++) keep += __popcll(__ballot(v[r] <= bound && v[r] != ~0ull));
+  if (keep > 128) {
+    bitonic_sort_regs<4>(v);
+    bound = ~0ull;
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+      if (((t - 1) >> 6) == r) bound = readlane64(v[r], (t - 1) & 63);
+    keep = n < t ? n : t;
+  }
+  int at = 0;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const bool in = v[r] <= bound && v[r] != ~0ull;
+    const uint64_t bm = __ballot(in);
+    if (in) L[at + lanes_below(bm)] = v[r];
+    at += __popcll(bm);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  kth = n < t ? ~0ull : bound;
+  return at;
+}
+
+// The t best of one row's list (n <= 256 keys), ascending, to lanes 0 .. t - 1 (one key per lane).
+__device__ __forceinline__ uint64_t best_logits(const uint64_t* __restrict__ L, int n, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  if (n <= 64) return bitonic_sort_u64<64>(lane < n ? L[lane] : ~0ull);
+  if (n <= 128) {
+    uint64_t w[2] = {L[lane], 64 + lane < n ? L[64 + lane] : ~0ull};
+    bitonic_sort_regs<2>(w);
+    return w[0];
+  }
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) v[r] = r * 64 + lane < n ? L[r * 64 + lane] : ~0ull;
+  bitonic_sort_regs<4>(v);
+  return v[0];
+}
+
+template <int H>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void out_readout_kernel(
+    const uint16_t* __restrict__ H2, int n, const uint16_t* __restrict__ W3t, const float* __restrict__ b3, int R,
+    int no_tiles, int t, float tau, const uint32_t* __restrict__ gmap, int t_min, int t_max, float budget_scale,
+    uint64_t* __restrict__ lists, uint32_t* __restrict__ seeds, int32_t* __restrict__ iters,
+    float* __restrict__ conf, uint32_t* __restrict__ top_idx) {
+  constexpr int P = H + 8;
+  constexpr int KB = H / 16;
+  constexpr int NCH = H / 32;
+  constexpr int LCAP = 256;
+  extern __shared__ __align__(16) char osm[];
+  uint16_t* Sw = (uint16_t*)osm;
+  float* thr_s = (float*)(Sw + 64 * P);
+  int* cnt_s = (int*)(thr_s + 128);
+  float* zr_s = (float*)(cnt_s + 128);
+  float* mx_s = zr_s + 128;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int h = lane >> 5, col = lane & 31, wr = wave * 32;
+  const int64_t r0 = (int64_t)blockIdx.x * 128;
+  uint64_t* wl = lists + (r0 + wr) * LCAP;  // the wave's row r: wl + r * LCAP
+  bf16x8 a[KB];
+  {
+    const bf16x8* ap = (const bf16x8*)(H2 + (r0 + wr + col) * H + h * 8);
+#pragma unroll
+    for (int kb = 0; kb < KB; kb++) a[kb] = ap[2 * kb];
+  }
+  if (tid < 128) {
+    thr_s[tid] = -INFINITY;
+    cnt_s[tid] = 0;
+    zr_s[tid] = 0.f;
+  }
+  const int sr = tid >> 2, c0 = tid & 3;
+  auto bias_of = [&](int j) { return j < R ? b3[j] : -INFINITY; };
+  // one sweep over the output tiles; f(tt, acc) consumes each tile's two 32 x 32 accumulator blocks
+  auto sweep = [&](auto&& f) {
+    u32x4_t wst[NCH];
+    {
+      const u32x4_t* wp = (const u32x4_t*)(W3t + (int64_t)sr * H) + c0;
+#pragma unroll
+      for (int q = 0; q < NCH; q++) wst[q] = wp[4 * q];
+    }
+    float bnx[2] = {bias_of(col), bias_of(32 + col)};
+    for (int tt = 0; tt < no_tiles; tt++) {
+      const float bias[2] = {bnx[0], bnx[1]};
+      const int nt = tt + 1 < no_tiles ? tt + 1 : tt;  // (the last tile reloads itself)
+      bnx[0] = bias_of(nt * 64 + col);
+      bnx[1] = bias_of(nt * 64 + 32 + col);
+      __syncthreads();  // the previous tile is consumed
+#pragma unroll
+      for (int q = 0; q < NCH; q++) *(u32x4_t*)&Sw[sr * P + (c0 + 4 * q) * 8] = wst[q];
+      {
+        const u32x4_t* wp = (const u32x4_t*)(W3t + ((int64_t)nt * 64 + sr) * H) + c0;
+#pragma unroll
+        for (int q = 0; q < NCH; q++) wst[q] = wp[4 * q];
+      }
+      __syncthreads();
+      f32x16 acc[2];
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc[c][j] = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < KB; kb++) {
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+          const bf16x8 bv = *(const bf16x8*)&Sw[(32 * c + col) * P + kb * 16 + h * 8];
+          acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], bv, acc[c], 0, 0, 0);
+        }
+      }
+      f(tt, acc, bias);
+    }
+  };
+  // sweep 1: maxima, candidate lists, the budget logit
+  float mx[16], tz[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    mx[j] = -INFINITY;
+    tz[j] = -INFINITY;
+  }
+  sweep([&](int tt, const f32x16 (&acc)[2], const float (&bias)[2]) {
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const int jc = tt * 64 + 32 * c + col;
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        const int r = 8 * (j >> 2) + 4 * h + (j & 3);  // row within the wave
+        const float z = acc[c][j] + bias[c];
+        mx[j] = fmaxf(mx[j], z);
+        const bool cand = z > tz[j];
+        const uint64_t bm = __ballot(cand);
+        if (bm) {
+          const uint32_t hm = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
+          const int base = cnt_s[wr + r];
+          if (cand) wl[r * LCAP + base + __popc(hm & ((1u << col) - 1u))] = logit_key((uint32_t)jc, z);
+          if (col == 0) cnt_s[wr + r] = base + __popc(hm);
+        }
+      }
+    }
+    if (tt == R / 64) {
+      // column R (its bias was replaced by -inf above): the budget logit
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+          if (tt * 64 + 32 * c + col == R) zr_s[wr + 8 * (j >> 2) + 4 * h + (j & 3)] = acc[c][j] + b3[R];
+    }
+    // lists that could overflow in the next tile (64 more keys at most) are cut
+    const int cr = cnt_s[wr + (lane & 31)];
+    uint64_t need = __ballot(lane < 32 && cr > LCAP - 64);
+    if (need) {
+      while (need) {
+        const int rr = __builtin_ctzll(need);
+        need &= need - 1;
+        uint64_t kth;
+        const int nn = cut_logits(wl + rr * LCAP, cnt_s[wr + rr], t, lane, kth);
+        if (lane == 0) {
+          cnt_s[wr + rr] = nn;
+          thr_s[wr + rr] = kth == ~0ull ? -INFINITY : key_logit(kth);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; j++) tz[j] = thr_s[wr + 8 * (j >> 2) + 4 * h + (j & 3)];
+    }
+  });
+  // the rows' maxima over the 32 lanes of each half
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) mx[j] = fmaxf(mx[j], __shfl_xor(mx[j], o, 64));
+  }
+  // sweep 2: the sums of exp(z - maximum)
+  float sm[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) sm[j] = 0.f;
+  sweep([&](int, const f32x16 (&acc)[2], const float (&bias)[2]) {
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+      for (int j = 0; j < 16; j++) sm[j] += __expf(acc[c][j] + bias[c] - mx[j]);
+  });
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) sm[j] += __shfl_xor(sm[j], o, 64);
+    if (col == 0) mx_s[wr + 8 * (j >> 2) + 4 * h + (j & 3)] = 1.f / sm[j];  // the confidence
+  }
+  __builtin_amdgcn_wave_barrier();
+  // every row of the wave: its t best, the confidence and the budget
+  for (int rr = 0; rr < 32; rr++) {
+    const int64_t b = r0 + wr + rr;
+    if (b >= n) break;
+    const uint64_t best = best_logits(wl + rr * LCAP, cnt_s[wr + rr], lane);
+    const float c = mx_s[wr + rr];
+    if (lane < t) {
+      const uint32_t j = (uint32_t)best;
+      if (top_idx) top_idx[b * t + lane] = j;
+      seeds[b * t + lane] = (lane == 0 && c < tau) ? kNone : gmap[j];
+    }
+    if (lane == 0) {
+      float tb = ceilf(budget_scale * (expf(zr_s[wr + rr]) - 1.f));
+      if (!(tb >= (float)t_min)) tb = (float)t_min;
+      if (tb > (float)t_max) tb = (float)t_max;
+      iters[b] = c < tau ? t_max : (int32_t)tb;  // a fallback query keeps the full budget
+      conf[b] = c;
+    }
+  }
+}
+
+bool out_readout_supported(int hidden) { return hidden == 64 || hidden == 128 || hidden == 256; }
+
+size_t out_readout_lists_bytes(int n) { return (size_t)((n + 127) / 128) * 128 * 256 * 8; }
+
+hipError_t out_readout(const uint16_t* H2, int n, int hidden, const uint16_t* W3t, const float* b3, int R, int t,
+                       float tau, const uint32_t* gmap, int t_min, int t_max, float budget_scale, uint64_t* lists,
+                       uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!out_readout_supported(hidden) || t < 1 || t > 64 || t > R) return hipErrorInvalidValue;
+  const int no_tiles = (R + 1 + 63) / 64;
+  const dim3 g((unsigned)((n + 127) / 128));
+  const size_t lds = (size_t)64 * (hidden + 8) * 2 + 128 * 16;
+  switch (hidden) {
+#define MIANN_OUT_READOUT(HH)                                                                                         \
+  case HH:                                                                                                           \
+    hipLaunchKernelGGL(out_readout_kernel<HH>, g, dim3(256), lds, st, H2, n, W3t, b3, R, no_tiles, t, tau, gmap, t_min, \
+                       t_max, budget_scale, lists, seeds, iters, conf, top_idx);                                      \
+    break;
+    MIANN_OUT_READOUT(64)
+    MIANN_OUT_READOUT(128)
+    MIANN_OUT_READOUT(256)
+#undef MIANN_OUT_READOUT
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -22,5 +22,13 @@ hipError_t readout(const float* Z, int n, int R, int t, float tau, const uint32_
                    float budget_scale,
                    uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st);
 hipError_t zero_f32(float* p, int64_t n, hipStream_t st);
+// Output layer and read-out in one pass (no logits stored): the read-out's outputs from H2 [n][hidden] bf16 and
+// the output layer's weights column by column (W3t [no_pad][hidden], no_pad a multiple of 64 with zero rows past
+// R + 1). hidden in {64, 128, 256}; lists: out_readout_lists_bytes(n) of scratch.
+bool out_readout_supported(int hidden);
+size_t out_readout_lists_bytes(int n);
+hipError_t out_readout(const uint16_t* H2, int n, int hidden, const uint16_t* W3t, const float* b3, int R, int t,
+                       float tau, const uint32_t* gmap, int t_min, int t_max, float budget_scale, uint64_t* lists,
+                       uint32_t* seeds, int32_t* iters, float* conf, uint32_t* top_idx, hipStream_t st);
 
 }  // namespace miann

@@ -261,26 +261,36 @@ miann_status miann_predictor_predict(const miann_predictor* P, const float* x, i
   if (!(budget_scale > 0.f) || budget_scale > 1000.f)
     return miann_fail(MIANN_EINVAL, "miann_predictor_predict: budget_scale must be in (0, 1000]");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t chunk = 16384;
   Work w(st);
   uint16_t *xb, *H1, *H2, *W3t;
-  float* Z;
   const int h = P->hidden, no = P->n_out, no_pad = (no + 63) / 64 * 64;
+  // hidden widths the fused output layer covers: the logits are consumed where they are formed; others write
+  // them to memory and read them back
+  const bool fused = out_readout_supported(h);
+  const int64_t chunk = fused ? 65536 : 16384;
   PTRY(w.get(&xb, (size_t)chunk * P->d_in * 2));
   PTRY(w.get(&H1, (size_t)chunk * h * 2));
   PTRY(w.get(&H2, (size_t)chunk * h * 2));
-  PTRY(w.get(&Z, (size_t)chunk * no * 4));
-  // the output layer's weights column by column, so its GEMM stages them in 16-byte vectors (the same products)
+  // the output layer's weights column by column, so its tiles are staged in 16-byte vectors (the same products)
   PTRY(w.get(&W3t, (size_t)no_pad * h * 2));
   PTRY(transpose_bf16(P->wb[2], h, no, no_pad, W3t, st));
+  float* Z = nullptr;
+  uint64_t* lists = nullptr;
+  if (fused) PTRY(w.get(&lists, out_readout_lists_bytes((int)chunk)));
+  else PTRY(w.get(&Z, (size_t)chunk * no * 4));
   for (int64_t b0 = 0; b0 < n; b0 += chunk) {
     const int B = (int)std::min<int64_t>(chunk, n - b0);
     PTRY(gather_batch(x + b0 * P->d_in, P->d_in, nullptr, B, nullptr, nullptr, xb, nullptr, nullptr, st));
     PTRY(gemm_bf16(B, h, P->d_in, xb, P->d_in, 1, P->wb[0], h, 1, P->w[1], 1, nullptr, nullptr, H1, h, st));
     PTRY(gemm_bf16(B, h, h, H1, h, 1, P->wb[1], h, 1, P->w[3], 1, nullptr, nullptr, H2, h, st));
-    PTRY(gemm_bf16(B, no, h, H2, h, 1, W3t, 1, h, P->w[5], 0, nullptr, Z, nullptr, no, st));
-    PTRY(readout(Z, B, P->R, t, tau, ghost_map, t_min, t_max, budget_scale, seeds + b0 * t, iters + b0, conf + b0,
-                 top_entry ? top_entry + b0 * t : nullptr, st));
+    if (fused) {
+      PTRY(out_readout(H2, B, h, W3t, P->w[5], P->R, t, tau, ghost_map, t_min, t_max, budget_scale, lists,
+                       seeds + b0 * t, iters + b0, conf + b0, top_entry ? top_entry + b0 * t : nullptr, st));
+    } else {
+      PTRY(gemm_bf16(B, no, h, H2, h, 1, W3t, 1, h, P->w[5], 0, nullptr, Z, nullptr, no, st));
+      PTRY(readout(Z, B, P->R, t, tau, ghost_map, t_min, t_max, budget_scale, seeds + b0 * t, iters + b0, conf + b0,
+                   top_entry ? top_entry + b0 * t : nullptr, st));
+    }
   }
   return MIANN_OK;
 }
