@@ -617,9 +617,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void o
     const uint64_t best = best_logits(wl + rr * LCAP, cnt_s[wr + rr], lane);
     const float c = mx_s[wr + rr];
     if (lane < t) {
-      const uint32_t j = (uint32_t)best;
+      // a row whose logits are not numbers holds fewer than t keys: its missing seeds are none
+      const bool ok = best != ~0ull;
+      const uint32_t j = ok ? (uint32_t)best : kNone;
       if (top_idx) top_idx[b * t + lane] = j;
-      seeds[b * t + lane] = (lane == 0 && c < tau) ? kNone : gmap[j];
+      seeds[b * t + lane] = (!ok || (lane == 0 && c < tau)) ? kNone : gmap[j];
     }
     if (lane == 0) {
       float tb = ceilf(budget_scale * (expf(zr_s[wr + rr]) - 1.f));
