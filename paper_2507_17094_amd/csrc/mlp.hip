@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "mlp.hpp"
+#include "pool.hpp"
 
 namespace miann {
 
@@ -198,17 +199,42 @@ hipError_t loss_grad(const float* Z, int B, int R, const int32_t* lab, const flo
 }
 
 // db[j] = sum_b G[b][j] (bf16 gradient rows -> f32 column sums).
-__global__ void colsum_kernel(const uint16_t* __restrict__ G, int B, int N, float* __restrict__ db) {
+// Column sums of a [B][N] bf16 matrix (bias gradients), deterministic: block (x, y) sums columns
+// 64 x .. 64 x + 63 over the rows y, y + CS, y + 2 CS, ... (four row lanes per column, reduced in LDS in a
+// fixed order) into partial[y][N]; a second kernel adds the CS partials of every column in order.
+constexpr int CS = 16;  // row splits
+__global__ __launch_bounds__(256) void colsum_part_kernel(const uint16_t* __restrict__ G, int B, int N,
+                                                          float* __restrict__ partial) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  float s = 0.f;
+  if (j < N)
+    for (int b = blockIdx.y + CS * q; b < B; b += 4 * CS) s += bf2f(G[(int64_t)b * N + j]);
+  red[q][c] = s;
+  __syncthreads();
+  if (q == 0 && j < N) partial[(int64_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ partial, int N, float* __restrict__ db) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
   float s = 0.f;
-  for (int b = 0; b < B; b++) s += bf2f(G[(int64_t)b * N + j]);
+#pragma unroll
+  for (int y = 0; y < CS; y++) s += partial[(int64_t)y * N + j];
   db[j] = s;
 }
 
 hipError_t colsum(const uint16_t* G, int B, int N, float* db, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, G, B, N, db);
-  return hipGetLastError();
+  if (N == 0) return hipSuccess;
+  float* partial = nullptr;
+  hipError_t e = pool_malloc_async(&partial, (size_t)CS * N * 4, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)((N + 63) / 64), CS), dim3(256), 0, st, G, B, N, partial);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, partial, N, db);
+  e = hipGetLastError();
+  (void)hipFreeAsync(partial, st);
+  return e;
 }
 
 // Adam (Kingma and Ba, 2015) on FP32 master weights; refreshes the bf16 copy.
