@@ -684,6 +684,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="serving1m: seconds of Poisson arrivals per offered load")
     ap.add_argument("--serve-batch", type=int, default=32768, help="serving1m: largest batch the server forms")
+    ap.add_argument("--short", type=int, default=0,
+                    help="low-precision and serving workloads: the short form the default run reports")
     ap.add_argument("--forms", type=int, default=1,
                     help="default workload: also run the low-precision and serving forms (1M cuts, short)")
     ap.add_argument("--gt-check", type=int, default=1000,
@@ -719,7 +721,8 @@ def main():
         if FORMS[args.workload]["N"] > 2_000_000:
             os.environ["MIANN_PROGRESS"] = "1"  # the k-NN selection reports each launch of a long build
         fn = {"lowprec": form_lowprec, "learned": form_learned, "serving": form_serving}[FORMS[args.workload]["kind"]]
-        print(json.dumps(fn(args, args.workload)), flush=True)
+        print(json.dumps(fn(args, args.workload, quick=bool(args.short)) if FORMS[args.workload]["kind"] != "learned"
+                         else fn(args, args.workload)), flush=True)
         return
 
     import torch
