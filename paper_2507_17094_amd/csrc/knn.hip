@@ -15,6 +15,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cfloat>
 
 #include "common.hpp"
 #include "pool.hpp"
@@ -767,13 +768,15 @@ __global__ __launch_bounds__(256) void dense_queries_kernel(const void* __restri
   if (lane == 0) norm[r] = (float)s;
 }
 
-constexpr int DG = 8;     // columns per group minimum (pass 1)
 constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
+constexpr int KEEP = 4;   // pass 1: GEMM-form distances a lane keeps per block (its smallest)
 
 // LDS of the tile kernels: hi and lo bf16 copies of 64 query rows and of 64
 // ghost columns, each row padded by 8 elements (16 bytes) against bank conflicts.
 __host__ __device__ constexpr int dense_lds_stride(int dk) { return dk + 8; }
 inline size_t dense_tiles_lds(int dk) { return (size_t)4 * 64 * dense_lds_stride(dk) * 2; }
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // 64 rows x DK bf16 (hi and lo) staged by 256 threads: thread t owns row t / 4
 // and the 16-byte chunks c = t % 4 + 4 m of it (DK / 32 chunks per array).
@@ -801,30 +804,68 @@ struct Stage64 {
   }
 };
 
-// GEMM-form distances qn + gn - 2 q.g (three bf16 products: hi.hi + hi.lo + lo.hi)
-// of a block's 64 query rows against a run of 64-column tiles of one shard;
-// each wave owns a 32 x 32 quarter of every tile, and the accumulators are
-// consumed where the MFMA leaves them (lane = column, register = row):
-//   MODE 0: the minimum of every 8 columns (three DPP steps over 8 lanes) -> M;
-//   MODE 1: the mask of the columns at or below the row's bound, one 32-bit
-//   ballot half per (row, shard, 32-column half tile) -> cmask.
-// The next tile's columns are loaded into registers while the current one is
-// multiplied. Distances are clamped at 0 and handled as their bit patterns
-// (non-negative floats order like unsigned ints). Padding columns carry norm
-// +inf, so they never enter a minimum; MODE 1 also excludes them by index (the
-// bound may be +inf). Rows without a query get a NaN norm and never qualify.
+// The accumulators of a 32-ghost half tile start at -gn/2 of their ghosts: register j of the lanes of half
+// h = lane / 32 holds ghost 8 (j / 4) + 4 h + j % 4 of the half, four consecutive ghosts per 16-byte LDS read.
+__device__ __forceinline__ void init_acc(f32x16_t& acc, const float* ngl, int h) {
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const f32x4_t v = *(const f32x4_t*)&ngl[8 * q + 4 * h];
+#pragma unroll
+    for (int r = 0; r < 4; r++) acc[4 * q + r] = v[r];
+  }
+}
+
+// Inserts x into k, kept in descending order.
+__device__ __forceinline__ void keep_largest(float (&k)[KEEP], float x) {
+#pragma unroll
+  for (int i = 0; i < KEEP - 1; i++) {
+    const float hi = fmaxf(k[i], x);
+    x = fminf(k[i], x);
+    k[i] = hi;
+  }
+  k[KEEP - 1] = fmaxf(k[KEEP - 1], x);
+}
+
+// Writes a lane's KEEP smallest GEMM-form distances G = qn - 2 a from its per-register maxima of a (16-byte
+// aligned destination).
+__device__ __forceinline__ void write_kept(float* __restrict__ dst, const float (&mx)[16], float qv) {
+  float k[KEEP];
+#pragma unroll
+  for (int i = 0; i < KEEP; i++) k[i] = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < 16; j++) keep_largest(k, mx[j]);
+  f32x4_t o;
+#pragma unroll
+  for (int i = 0; i < KEEP; i++) o[i] = fmaxf(qv - 2.f * k[i], 0.f);
+  *(f32x4_t*)dst = o;
+}
+
+// GEMM-form distances of a block's 64 query rows against a run of 64-column tiles of one shard, both operands
+// staged through LDS (rows of more than 128 elements). G = qn - 2 a with a = q.x - gn/2, three bf16 products
+// (hi.hi + hi.lo + lo.hi) accumulated in float32 onto -gn/2. Each wave owns 32 query rows and 32 ghosts of every
+// tile; the ghosts are the first operand, so the accumulators leave one query per lane (lane & 31) and 16 ghosts
+// per lane (register j: ghost wc + 8 (j / 4) + 4 (lane / 32) + j % 4):
+//   MODE 0: per lane and register, the largest a over the block's tiles; at the end each lane writes its KEEP
+//   smallest G (clamped at 0), each the GEMM form of a distinct ghost, to
+//   M[row][shard][group][wave & 1][lane / 32][KEEP];
+//   MODE 1: the bits of the lane's 16 ghosts with a >= the row's threshold, as half word wave & 1 of the mask word
+//   of (row, shard, tile, lane / 32) -> cmask (bit 16 c + j is ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4 of
+//   the tile).
+// The next tile's columns are loaded into registers while the current one is multiplied. Padding columns carry
+// norm +inf, so their a is -inf: never a maximum or a candidate (thresholds are finite). Rows without a query get
+// a NaN threshold and never qualify; their pass-1 values land in the chunk's buffers and are never read.
 template <int MODE, int DK>
 __global__ __launch_bounds__(256) void dense_tiles_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
-    const float* __restrict__ gn, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0, int nseg,
-    int gps, int cg, int nht, int64_t mcols, int64_t mcol0, float* __restrict__ M, const float* __restrict__ bound,
-    uint32_t* __restrict__ cmask) {
+    const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
+    float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
   constexpr int P = dense_lds_stride(DK);
   extern __shared__ __align__(16) char dsm[];
   __shared__ int64_t qrow[64];
-  __shared__ float qnl[64], bnl[64];
+  __shared__ float qvl[64];
+  __shared__ __align__(16) float ngl[64];
   uint16_t* Ah = (uint16_t*)dsm;
   uint16_t* Al = Ah + 64 * P;
   uint16_t* Bh = Al + 64 * P;
@@ -838,18 +879,18 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
   const int ntiles = (int)((off[s + 1] - cb) / 64);
   const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
   if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
-  const int64_t R = Rs[s];
   if (tid < 64) {
     const int64_t gr = row0 + rl0 + tid;
     const bool ok = gr < n_rows && rl0 + tid < rows_chunk;
     const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
     qrow[tid] = q;
-    qnl[tid] = ok ? qn[q] : __builtin_nanf("");
-    if constexpr (MODE == 1) bnl[tid] = ok ? bound[(rl0 + tid) * nseg + sl] : 0.f;
+    // MODE 0: the row's norm; MODE 1: its threshold on a (NaN for rows without a query)
+    qvl[tid] = !ok ? __builtin_nanf("") : (MODE == 0 ? qn[q] : thr[(rl0 + tid) * nseg + sl]);
   }
   const int sr = tid >> 2, sc0 = tid & 3;
   Stage64<DK> nb;
   nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
+  float ng = sc0 == 0 ? -0.5f * gn[cb + (int64_t)tt0 * 64 + sr] : 0.f;
   __syncthreads();
   {
     Stage64<DK> a;
@@ -859,80 +900,66 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
   }
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int h = lane >> 5, col = lane & 31;
-  // this lane's 16 output rows: wr + 8 (j / 4) + 4 h + j % 4 (rows without a query still write M and counts:
-  // inside the chunk's buffers, never read)
-  float qr[16], br[16];
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int row = wr + 8 * (j >> 2) + 4 * h + (j & 3);
-    qr[j] = qnl[row];
-    br[j] = MODE == 1 ? bnl[row] : 0.f;
-  }
+  const int64_t rl = rl0 + wr + col;  // this lane's row of the chunk
+  const float qv = qvl[wr + col];
   const int ra = (wr + col) * P + h * 8, rb = (wc + col) * P + h * 8;
+  float mx[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) mx[j] = -INFINITY;
   for (int tt = tt0; tt < tt1; tt++) {
-    __syncthreads();  // the previous tile's B is consumed
+    __syncthreads();  // the previous tile is consumed
     nb.store(Bh, Bl, sr, sc0);
-    nb.load(Gh, Gl, cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr, sc0);  // (the last tile reloads itself)
+    if (sc0 == 0) ngl[sr] = ng;
+    {
+      const int64_t nxt = cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr;  // (the last tile reloads itself)
+      nb.load(Gh, Gl, nxt, sc0);
+      if (sc0 == 0) ng = -0.5f * gn[nxt];
+    }
     __syncthreads();
     f32x16_t acc;
-#pragma unroll
-    for (int j = 0; j < 16; j++) acc[j] = 0.f;
+    init_acc(acc, ngl + wc, h);
 #pragma unroll
     for (int kk = 0; kk < DK; kk += 16) {
-      const bf16x8_t ah = *(const bf16x8_t*)&Ah[ra + kk], al = *(const bf16x8_t*)&Al[ra + kk];
-      const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb + kk], bl = *(const bf16x8_t*)&Bl[rb + kk];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+      const bf16x8_t qh = *(const bf16x8_t*)&Ah[ra + kk], ql = *(const bf16x8_t*)&Al[ra + kk];
+      const bf16x8_t gh = *(const bf16x8_t*)&Bh[rb + kk], gl = *(const bf16x8_t*)&Bl[rb + kk];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql, acc, 0, 0, 0);
     }
-    const int jc = tt * 64 + wc + col;  // ghost index of this lane's column
-    const float gcol = gn[cb + jc];
     if constexpr (MODE == 0) {
-      float* mrow = M + (rl0 + wr + 4 * h) * mcols + (cb - mcol0 + tt * 64 + wc) / DG + (col >> 3);
 #pragma unroll
-      for (int j = 0; j < 16; j++) {
-        const float v = qr[j] + gcol - 2.f * acc[j];
-        uint32_t u = (uint32_t)max(__float_as_int(v), 0);
-        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0xB1, 0xF, 0xF, false));
-        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x4E, 0xF, 0xF, false));
-        u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x141, 0xF, 0xF, false));
-        if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
-      }
+      for (int j = 0; j < 16; j++) mx[j] = fmaxf(mx[j], acc[j]);
     } else {
-      const bool cok = jc < R;
-      const int ht = tt * 2 + (wc >> 5);
-      uint32_t* mrow = cmask + ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
+      uint32_t w = 0;
 #pragma unroll
-      for (int j = 0; j < 16; j++) {
-        const float v = qr[j] + gcol - 2.f * acc[j];
-        const bool cand = cok && v <= br[j];
-        const uint64_t bm = __ballot(cand);
-        const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
-        if (col == 0) mrow[(int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht] = half;
-      }
+      for (int j = 0; j < 16; j++) w |= acc[j] >= qv ? 1u << j : 0u;
+      ((uint16_t*)(cmask + (rl * nseg + sl) * nht + 2 * tt + h))[wave & 1] = (uint16_t)w;
     }
   }
+  if constexpr (MODE == 0)
+    write_kept(M + ((rl * nseg + sl) * gps + grp) * (4 * KEEP) + ((wave & 1) * 2 + h) * KEEP, mx, qv);
 }
 
-// The same passes for rows of at most 128 elements, with twice the rows per
-// staged ghost tile: a block of 4 waves owns 128 query rows, each wave keeps its
-// 32 rows' hi and lo fragments in registers for the whole run of tiles and
-// multiplies them with both 32-column halves of every 64-column tile (six
-// MFMAs per 16-element k step). Only the ghost tile goes through LDS.
+// The same passes for rows of at most 128 elements, with twice the rows per staged ghost tile: a block of 4 waves
+// owns 128 query rows, each wave keeps its 32 rows' hi and lo fragments in registers for the whole run of tiles
+// and multiplies them with both 32-ghost halves of every 64-column tile (six MFMAs per 16-element k step). Only
+// the ghost tile goes through LDS. Register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4.
+//   MODE 0: one maximum per register over both halves and the block's tiles; each lane writes its KEEP smallest
+//   G to M[row][shard][group][lane / 32][KEEP];
+//   MODE 1: the mask word of (row, shard, tile, lane / 32), bit 16 c + j.
 // (3 waves per SIMD fit without spills up to 96-element rows; wider rows keep the compiler's budget)
 template <int MODE, int DK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 3 : 1))) void dense_tiles_wide_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
-    const float* __restrict__ gn, const int64_t* __restrict__ off, const int64_t* __restrict__ Rs, int s0, int nseg,
-    int gps, int cg, int nht, int64_t mcols, int64_t mcol0, float* __restrict__ M, const float* __restrict__ bound,
-    uint32_t* __restrict__ cmask) {
+    const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
+    float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
   static_assert(DK % 32 == 0 && DK <= 128, "DK");
   constexpr int P = dense_lds_stride(DK);
   constexpr int KB = DK / 16;
   __shared__ __align__(16) uint16_t Bh[64 * P], Bl[64 * P];
-  __shared__ float qnl[128], bnl[128];
+  __shared__ __align__(16) float ngl[64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   const int64_t rl0 = (int64_t)blockIdx.y * 128;
@@ -942,112 +969,81 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
   const int ntiles = (int)((off[s + 1] - cb) / 64);
   const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
   if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
-  const int64_t R = Rs[s];
-  const int h = lane >> 5, col = lane & 31, wr = wave * 32;
-  // this lane's A row (fragments of row wr + col) and the block's row norms and bounds
+  const int h = lane >> 5, col = lane & 31;
+  const int64_t rl = rl0 + wave * 32 + col;  // this lane's row of the chunk
   int64_t qa;
   {
-    const int64_t gr = row0 + rl0 + wr + col;
-    const bool ok = gr < n_rows && rl0 + wr + col < rows_chunk;
-    qa = ok ? (list ? (int64_t)list[gr] : gr) : -1;
+    const int64_t gr = row0 + rl;
+    qa = gr < n_rows && rl < rows_chunk ? (list ? (int64_t)list[gr] : gr) : -1;
   }
-  if (tid < 128) {
-    const int64_t gr = row0 + rl0 + tid;
-    const bool ok = gr < n_rows && rl0 + tid < rows_chunk;
-    const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
-    qnl[tid] = ok ? qn[q] : __builtin_nanf("");  // absent rows: NaN distances, never a candidate
-    if constexpr (MODE == 1) bnl[tid] = ok ? bound[(rl0 + tid) * nseg + sl] : 0.f;
-  }
-  bf16x8_t ah[KB], al[KB];
+  // MODE 0: the row's norm; MODE 1: its threshold on a (NaN for rows without a query)
+  const float qv = qa < 0 ? __builtin_nanf("") : (MODE == 0 ? qn[qa] : thr[rl * nseg + sl]);
+  bf16x8_t qh[KB], ql[KB];
   {
     const int64_t q = qa < 0 ? 0 : qa;  // rows without a query read row 0
     const bf16x8_t* hp = (const bf16x8_t*)(Qh + q * DK + h * 8);
     const bf16x8_t* lp = (const bf16x8_t*)(Ql + q * DK + h * 8);
 #pragma unroll
     for (int kb = 0; kb < KB; kb++) {
-      ah[kb] = hp[2 * kb];
-      al[kb] = lp[2 * kb];
+      qh[kb] = hp[2 * kb];
+      ql[kb] = lp[2 * kb];
     }
   }
   const int sr = tid >> 2, sc0 = tid & 3;
   Stage64<DK> nb;
   nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
-  __syncthreads();
-  // MODE 0: the row norms; MODE 1: per row, bound - norm (a column qualifies iff gn - 2 q.g <= it; NaN for
-  // absent rows, so they never qualify)
-  float qr[16];
+  float ng = sc0 == 0 ? -0.5f * gn[cb + (int64_t)tt0 * 64 + sr] : 0.f;
+  float mx[16];
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int row = wr + 8 * (j >> 2) + 4 * h + (j & 3);
-    qr[j] = MODE == 1 ? bnl[row] - qnl[row] : qnl[row];
-  }
+  for (int j = 0; j < 16; j++) mx[j] = -INFINITY;
   for (int tt = tt0; tt < tt1; tt++) {
     __syncthreads();  // the previous tile is consumed
     nb.store(Bh, Bl, sr, sc0);
-    nb.load(Gh, Gl, cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr, sc0);  // (the last tile reloads itself)
+    if (sc0 == 0) ngl[sr] = ng;
+    {
+      const int64_t nxt = cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr;  // (the last tile reloads itself)
+      nb.load(Gh, Gl, nxt, sc0);
+      if (sc0 == 0) ng = -0.5f * gn[nxt];
+    }
     __syncthreads();
-    // the tile's column norms, loaded while the products run
-    float gcols[2];
-#pragma unroll
-    for (int c = 0; c < 2; c++) gcols[c] = gn[cb + tt * 64 + 32 * c + col];
     f32x16_t acc[2];
 #pragma unroll
-    for (int c = 0; c < 2; c++)
-#pragma unroll
-      for (int j = 0; j < 16; j++) acc[c][j] = 0.f;
+    for (int c = 0; c < 2; c++) init_acc(acc[c], ngl + 32 * c, h);
 #pragma unroll
     for (int kb = 0; kb < KB; kb++) {
 #pragma unroll
       for (int c = 0; c < 2; c++) {
         const int rb = (32 * c + col) * P + kb * 16 + h * 8;
-        const bf16x8_t bh = *(const bf16x8_t*)&Bh[rb], bl = *(const bf16x8_t*)&Bl[rb];
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bh, acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bl, acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kb], bh, acc[c], 0, 0, 0);
+        const bf16x8_t gh = *(const bf16x8_t*)&Bh[rb], gl = *(const bf16x8_t*)&Bl[rb];
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh[kb], acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh[kb], acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql[kb], acc[c], 0, 0, 0);
       }
     }
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int c = 0; c < 2; c++) {
-      const int wc = 32 * c;
-      const int jc = tt * 64 + wc + col;  // ghost index of this lane's column
-      const float gcol = gcols[c];
-      if constexpr (MODE == 0) {
-        float* mrow = M + (rl0 + wr + 4 * h) * mcols + (cb - mcol0 + tt * 64 + wc) / DG + (col >> 3);
+      for (int j = 0; j < 16; j++) mx[j] = fmaxf(mx[j], fmaxf(acc[0][j], acc[1][j]));
+    } else {
+      uint32_t w = 0;
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
-          const float v = qr[j] + gcol - 2.f * acc[c][j];
-          uint32_t u = (uint32_t)max(__float_as_int(v), 0);
-          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0xB1, 0xF, 0xF, false));
-          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x4E, 0xF, 0xF, false));
-          u = min(u, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)u, 0x141, 0xF, 0xF, false));
-          if ((col & 7) == 0) mrow[(8 * (j >> 2) + (j & 3)) * mcols] = __uint_as_float(u);
-        }
-      } else {
-        const bool cok = jc < R;
-        const int ht = tt * 2 + c;
-        uint32_t* mrow = cmask + ((rl0 + wr + 4 * h) * nseg + sl) * nht + ht;
+      for (int c = 0; c < 2; c++)
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
-          const bool cand = cok && gcol - 2.f * acc[c][j] <= qr[j];
-          const uint64_t bm = __ballot(cand);
-          const uint32_t half = h ? (uint32_t)(bm >> 32) : (uint32_t)bm;
-          if (col == 0) mrow[(int64_t)(8 * (j >> 2) + (j & 3)) * nseg * nht] = half;
-        }
-      }
+        for (int j = 0; j < 16; j++) w |= acc[c][j] >= qv ? 1u << (16 * c + j) : 0u;
+      cmask[(rl * nseg + sl) * nht + 2 * tt + h] = w;
     }
   }
+  if constexpr (MODE == 0) write_kept(M + ((rl * nseg + sl) * gps + grp) * (2 * KEEP) + h * KEEP, mx, qv);
 }
 
 template <int MODE>
 static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
                                const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
                                int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
-                               int64_t mcols, int64_t mcol0, float* Mg, const float* bnd, uint32_t* cmask) {
+                               float* Mg, const float* thr, uint32_t* cmask) {
 #define MIANN_DENSE_WIDE(KC)                                                                                         \
   case KC:                                                                                                           \
     hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
-                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, \
-                       bnd, cmask);                                                                                  \
+                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, Mg, thr, cmask);          \
     break;
 #define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
@@ -1057,8 +1053,7 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
     });                                                                                                              \
     hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
-                       chunk, G.hi, G.lo, G.norm, G.off_dev, G.R_dev, s0, nseg, gps, cg, nht, mcols, mcol0, Mg, bnd,  \
-                       cmask);                                                                                       \
+                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, Mg, thr, cmask);                \
     break;                                                                                                           \
   }
   switch (dk / 32) {
@@ -1076,32 +1071,28 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
 #undef MIANN_DENSE_WIDE
 }
 
-// Rows per block of the tile passes for rows of dk elements.
+// Rows per block of the tile passes for rows of dk elements, and the values pass 1 keeps per row and block.
 static int dense_block_rows(int dk) { return dk <= 128 ? 128 : 64; }
+static int dense_kept_per_block(int dk) { return dk <= 128 ? 2 * KEEP : 4 * KEEP; }
 
-// One wave per (row, shard): the bound b of pass 2, which keeps every exact
-// top-t ghost of the shard. G_j = qn + gn_j - 2 q.x_j is the GEMM form of the
-// distance to ghost j (split-bf16 products, float32 accumulation), D_j the
-// exact distance (the search's definition), E >= |G_j - D_j|. Every lane keeps
-// the two smallest of its 8-column minima (each the G of a distinct ghost), so
-// the t-th smallest b_t of those values has t ghosts with G <= b_t, hence
-// D <= b_t + E for t ghosts and tau_D (the t-th smallest D) <= b_t + E; an
-// exact top-t ghost j then has G_j <= D_j + E <= tau_D + E <= b_t + 2E = b.
-// E = eps (qn + max_j gn_j): with |q.x| <= (qn + gn) / 2, eps covers the
-// dropped lo.lo term and the residual of the two-term bf16 split (about
-// 3.03 2^-16 |q||x|), the float32 accumulation of 3 dk products (6 dk 2^-24,
-// twice the usual bound in case the matrix cores truncate), the rounding of
-// the norms, of the GEMM form's additions and of the exact distance, with a
-// factor of 2 on the whole. +inf when the shard has fewer than t groups.
-__global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int64_t ncols,
+// One wave per (row, shard): the threshold of pass 2, which keeps every exact top-t ghost of the shard.
+// G_j = qn + gn_j - 2 q.x_j is the GEMM form of the distance to ghost j, computed as qn - 2 a_j with
+// a_j = q.x_j - gn_j / 2 (split-bf16 products accumulated in float32), D_j the exact distance (the search's
+// definition), E >= |G_j - D_j|. Pass 1 left, per block of the shard's tiles, every lane's KEEP smallest G, each
+// the G of a distinct ghost; so the t-th smallest b_t of those values has t ghosts with G <= b_t, hence D <= b_t + E
+// for t ghosts and tau_D (the t-th smallest D) <= b_t + E; an exact top-t ghost j then has
+// G_j <= D_j + E <= tau_D + E <= b_t + 2E, that is a_j >= (qn - b_t - 2E) / 2, the threshold (rounded down).
+// Fewer than t values (a shard with fewer than t ghosts, or t above what pass 1 keeps) give -FLT_MAX: every real
+// ghost qualifies, and no padding column (a = -inf). E = eps (qn + max_j gn_j), see dense_eps.
+__global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int nvb, int gps, int cg,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ Rs, int s0, int nseg,
-                                                          int64_t col0, const int* __restrict__ nrows_dev,
-                                                          int64_t nrows_max, int64_t row0, int64_t rows_chunk, int t,
+                                                          const int* __restrict__ nrows_dev, int64_t nrows_max,
+                                                          int64_t row0, int64_t rows_chunk, int t,
                                                           const uint32_t* __restrict__ list,
                                                           const float* __restrict__ qn,
                                                           const float* __restrict__ gmax, float eps,
-                                                          float* __restrict__ bound) {
+                                                          float* __restrict__ thr) {
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t item = (int64_t)blockIdx.x * 4 + wave;
   const int64_t rl = item / nseg;
@@ -1111,18 +1102,19 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   const int s = s0 + sl;
   const int64_t R = Rs[s];
   const int kp = (int)(t < R ? t : R);
-  const int64_t ng = (R + DG - 1) / DG;
-  const float* m = M + rl * (ncols / DG) + (off[s] - col0) / DG;
+  const int ntiles = (int)((off[s + 1] - off[s]) / 64);
+  const int64_t nv = (int64_t)((ntiles + cg - 1) / cg) * nvb;  // the values of the blocks that ran
+  const float* m = M + (rl * nseg + sl) * (int64_t)gps * nvb;
   // float bits of non-negative values order like the values; 0xFFFFFFFF = none
   // all of a lane's loads of one round are issued before the first is consumed (one memory latency per round)
   constexpr int U = 8;
   uint32_t v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
-  for (int64_t g0 = lane; g0 < ng; g0 += 64 * U) {
+  for (int64_t g0 = lane; g0 < nv; g0 += 64 * U) {
     uint32_t x[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int64_t g = g0 + (int64_t)u * 64;
-      x[u] = g < ng ? __float_as_uint(m[g]) : 0xFFFFFFFFu;
+      x[u] = g < nv ? __float_as_uint(m[g]) : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -1142,8 +1134,15 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
     b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (kp - 1) & 63);
   }
   const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
-  const float E = eps * (qn[qi] + gmax[s]);
-  if (lane == 0) bound[rl * nseg + sl] = b == 0xFFFFFFFFu ? INFINITY : __uint_as_float(b) + 2.f * E;
+  float th = -FLT_MAX;
+  if (b < 0x7F800000u) {  // a finite b_t
+    const double qd = (double)qn[qi];
+    const double E = (double)eps * (qd + (double)gmax[s]);
+    const double x = 0.5 * (qd - ((double)__uint_as_float(b) + 2.0 * E));
+    th = (float)x;
+    if ((double)th > x) th = nextafterf(th, -INFINITY);
+  }
+  if (lane == 0) thr[rl * nseg + sl] = th;
 }
 
 // Exact distance (the search's definition) of query row q to a stored row, by an 8-lane team; every lane of the
@@ -1275,8 +1274,9 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   const DenseShardDev sh = shd[s];
   uint64_t* ebuf = ebufs + wave * CAPG;
   const size_t row_bytes = (size_t)d_pad * ESZ;
-  // candidate columns: half tile i (one per lane and round) contributes the set bits of its mask
-  const int nt = (int)((R + 31) / 32);
+  // candidate columns: mask word i (one per lane and round) of tile i / 2 contributes the set bits of its lane
+  // half i % 2: bit b is column 64 (i / 2) + 32 (b / 16) + 8 (b / 4 % 4) + 4 (i % 2) + b % 4
+  const int nt = (int)(2 * ((R + 63) / 64));
   const uint32_t* mrow = cmask + (rl * nseg + sl) * nht;
   int n = 0;
   for (int i0 = 0; i0 < nt; i0 += 64) {
@@ -1293,7 +1293,7 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
     while (m) {
       const int b = __ffs(m) - 1;
       m &= m - 1;
-      if (at < CAPG) ebuf[at] = (uint64_t)(i * 32 + b);
+      if (at < CAPG) ebuf[at] = (uint64_t)((i >> 1) * 64 + 32 * (b >> 4) + 8 * ((b >> 2) & 3) + 4 * (i & 1) + (b & 3));
       at++;
     }
     n += (int)shfl_u32((uint32_t)pre, 63);
@@ -1355,8 +1355,13 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
 namespace {
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 // eps of the dense entry's error bound E = eps (qn + max gn) for rows of dk elements (see dense_bound_kernel).
+// E bounds |G - D| with G = qn - 2 a computed from a = q.x - gn/2 and D the exact distance. It covers the dropped
+// lo.lo term and the residual of the two-term bf16 split (about 3.03 2^-16 |q||x|, and 2 |q||x| <= qn + gn), the
+// float32 accumulation of 3 dk products onto -gn/2 (partial sums at most qn + gn; 2^-23 per addition in case the
+// matrix cores truncate: (3 dk + 1) 2^-23 (qn + gn) in a, twice that in G), the rounding of the norms, of G and of
+// the exact distance (12 2^-24 (qn + gn)), with a factor of 2 on the whole.
 float dense_eps(int dk) {
-  return (float)(2.0 * (3.03 * std::ldexp(1.0, -16) + (6.0 * dk + 10.0) * std::ldexp(1.0, -24)));
+  return (float)(2.0 * (3.03 * std::ldexp(1.0, -16) + (12.0 * dk + 16.0) * std::ldexp(1.0, -24)));
 }
 // Bytes of the per-query buffers (split query rows, norms, raw rows, start-shard list, counter).
 size_t dense_query_bytes(int store_dt, int64_t nq, int d_pad, int dk) {
@@ -1364,12 +1369,12 @@ size_t dense_query_bytes(int store_dt, int64_t nq, int d_pad, int dk) {
   return 2 * al256((size_t)nq * dk * 2) + al256((size_t)nq * 4) + al256((size_t)nq * d_pad * raw) +
          al256((size_t)nq * 4) + 256;
 }
-// Scratch bytes per row of a chunk in the pass over shards [s0, s1): 8-column minima, bounds and candidate masks.
+// Scratch bytes per row of a chunk in the pass over shards [s0, s1): candidate masks, the values pass 1 keeps
+// (at most one block per tile and 4 KEEP values per block) and thresholds.
 size_t dense_row_bytes(const DenseGhosts& G, int s0, int s1) {
   int64_t ntmax = 0;
   for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
-  const int64_t ncols = G.off[s1] - G.off[s0];
-  return (size_t)(ncols / DG) * 4 + (size_t)(s1 - s0) * (4 + (size_t)(2 * ntmax) * 4);
+  return (size_t)(s1 - s0) * ((size_t)(2 * ntmax) * 4 + (size_t)ntmax * 4 * KEEP * 4 + 4);
 }
 }  // namespace
 
@@ -1418,7 +1423,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
   for (int ps = 0; ps < npass && e == hipSuccess; ps++) {
     const int s0 = start_only ? ps : 0, s1 = start_only ? ps + 1 : S;
     const int nseg = s1 - s0;
-    const int64_t col0 = G.off[s0], ncols = G.off[s1] - G.off[s0];
+    const int64_t ncols = G.off[s1] - G.off[s0];
     if (ncols == 0) continue;
     const uint32_t* rl = nullptr;
     const int* rc = nullptr;
@@ -1429,7 +1434,8 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       rl = list;
       rc = qcnt;
     }
-    // per chunk of rows: group minima [rows][ncols / 8], bounds [rows][nseg], candidate masks [rows][nseg][nht]
+    // per chunk of rows: candidate masks [rows][nseg][nht], kept values [rows][nseg][gps][nvb], thresholds
+    // [rows][nseg]
     int64_t ntmax = 0;
     for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
     const int64_t nht = 2 * ntmax;
@@ -1446,26 +1452,27 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     else e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
     wb = (char*)lw.p;
     if (e != hipSuccess) break;
-    uint32_t* cmask = (uint32_t*)wb;
-    float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
-    float* bnd = Mg + (size_t)chunk * (ncols / DG);
     // column groups of cg tiles per block: enough blocks to fill the chip, each reusing its staged rows
     const int64_t rtiles = chunk / brows;
     int64_t gps = (2048 + rtiles * nseg - 1) / (rtiles * nseg);
     gps = std::max<int64_t>(1, std::min<int64_t>(gps, ntmax));
     const int cg = (int)((ntmax + gps - 1) / gps);
     gps = (ntmax + cg - 1) / cg;
+    const int nvb = dense_kept_per_block(dk);
+    uint32_t* cmask = (uint32_t*)wb;
+    float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
+    float* thr = Mg + (size_t)chunk * nseg * gps * nvb;
     const dim3 gg((unsigned)(nseg * gps), (unsigned)rtiles);
     const size_t lds = dense_tiles_lds(dk);
     const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
     const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
-      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
-                            ncols / DG, col0, Mg, bnd, cmask);
-      hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, ncols, G.off_dev, G.R_dev, s0, nseg,
-                         col0, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, dense_eps(dk), bnd);
-      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
-                            ncols / DG, col0, Mg, bnd, cmask);
+      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
+                            thr, cmask);
+      hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, (int)gps, cg, G.off_dev, G.R_dev,
+                         s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, dense_eps(dk), thr);
+      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
+                            thr, cmask);
       switch (store_dt) {
         case DT_F32:
           hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
