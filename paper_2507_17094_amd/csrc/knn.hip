@@ -958,8 +958,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
   static_assert(DK % 32 == 0 && DK <= 128, "DK");
   constexpr int P = dense_lds_stride(DK);
   constexpr int KB = DK / 16;
-  __shared__ __align__(16) uint16_t Bh[64 * P], Bl[64 * P];
-  __shared__ __align__(16) float ngl[64];
+  // two tile buffers where three blocks per CU still fit (the next tile is stored while this one is multiplied,
+  // one barrier per tile), else one
+  constexpr int NBUF = DK <= 96 ? 2 : 1;
+  __shared__ __align__(16) uint16_t Bh[NBUF][64 * P], Bl[NBUF][64 * P];
+  __shared__ __align__(16) float ngl[NBUF][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   const int64_t rl0 = (int64_t)blockIdx.y * 128;
@@ -996,25 +999,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
   float mx[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) mx[j] = -INFINITY;
-  for (int tt = tt0; tt < tt1; tt++) {
-    __syncthreads();  // the previous tile is consumed
-    nb.store(Bh, Bl, sr, sc0);
-    if (sc0 == 0) ngl[sr] = ng;
-    {
-      const int64_t nxt = cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr;  // (the last tile reloads itself)
+  if constexpr (NBUF == 2) {
+    nb.store(Bh[0], Bl[0], sr, sc0);
+    if (sc0 == 0) ngl[0][sr] = ng;
+    if (tt0 + 1 < tt1) {
+      const int64_t nxt = cb + (int64_t)(tt0 + 1) * 64 + sr;
       nb.load(Gh, Gl, nxt, sc0);
       if (sc0 == 0) ng = -0.5f * gn[nxt];
     }
-    __syncthreads();
+  }
+  for (int tt = tt0; tt < tt1; tt++) {
+    const int cur = NBUF == 2 ? (tt - tt0) & 1 : 0;
+    if constexpr (NBUF == 2) {
+      __syncthreads();  // tile tt is stored in buffer cur, and the other buffer's tile is consumed
+      if (tt + 1 < tt1) {
+        nb.store(Bh[cur ^ 1], Bl[cur ^ 1], sr, sc0);
+        if (sc0 == 0) ngl[cur ^ 1][sr] = ng;
+        if (tt + 2 < tt1) {
+          const int64_t nxt = cb + (int64_t)(tt + 2) * 64 + sr;
+          nb.load(Gh, Gl, nxt, sc0);
+          if (sc0 == 0) ng = -0.5f * gn[nxt];
+        }
+      }
+    } else {
+      __syncthreads();  // the previous tile is consumed
+      nb.store(Bh[0], Bl[0], sr, sc0);
+      if (sc0 == 0) ngl[0][sr] = ng;
+      {
+        const int64_t nxt = cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr;  // (the last tile reloads itself)
+        nb.load(Gh, Gl, nxt, sc0);
+        if (sc0 == 0) ng = -0.5f * gn[nxt];
+      }
+      __syncthreads();
+    }
+    const uint16_t* bh = Bh[cur];
+    const uint16_t* bl = Bl[cur];
     f32x16_t acc[2];
 #pragma unroll
-    for (int c = 0; c < 2; c++) init_acc(acc[c], ngl + 32 * c, h);
+    for (int c = 0; c < 2; c++) init_acc(acc[c], ngl[cur] + 32 * c, h);
 #pragma unroll
     for (int kb = 0; kb < KB; kb++) {
 #pragma unroll
       for (int c = 0; c < 2; c++) {
         const int rb = (32 * c + col) * P + kb * 16 + h * 8;
-        const bf16x8_t gh = *(const bf16x8_t*)&Bh[rb], gl = *(const bf16x8_t*)&Bl[rb];
+        const bf16x8_t gh = *(const bf16x8_t*)&bh[rb], gl = *(const bf16x8_t*)&bl[rb];
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh[kb], acc[c], 0, 0, 0);
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh[kb], acc[c], 0, 0, 0);
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql[kb], acc[c], 0, 0, 0);
@@ -1075,6 +1103,8 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
 static int dense_block_rows(int dk) { return dk <= 128 ? 128 : 64; }
 static int dense_kept_per_block(int dk) { return dk <= 128 ? 2 * KEEP : 4 * KEEP; }
 
+__device__ __forceinline__ float dense_threshold(float b, float qf, float gf, float eps);
+
 // One wave per (row, shard): the threshold of pass 2, which keeps every exact top-t ghost of the shard.
 // G_j = qn + gn_j - 2 q.x_j is the GEMM form of the distance to ghost j, computed as qn - 2 a_j with
 // a_j = q.x_j - gn_j / 2 (split-bf16 products accumulated in float32), D_j the exact distance (the search's
@@ -1105,6 +1135,9 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   const int ntiles = (int)((off[s + 1] - off[s]) / 64);
   const int64_t nv = (int64_t)((ntiles + cg - 1) / cg) * nvb;  // the values of the blocks that ran
   const float* m = M + (rl * nseg + sl) * (int64_t)gps * nvb;
+  // the row's norm and the shard's largest ghost norm, loaded before the values are sorted
+  const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+  const float qf = qn[qi], gf = gmax[s];
   // float bits of non-negative values order like the values; 0xFFFFFFFF = none
   // all of a lane's loads of one round are issued before the first is consumed (one memory latency per round)
   constexpr int U = 8;
@@ -1133,16 +1166,69 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
     const uint64_t x = (kp - 1) >= 64 ? w[1] : w[0];
     b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (kp - 1) & 63);
   }
-  const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+  const float th = dense_threshold(b < 0x7F800000u ? __uint_as_float(b) : INFINITY, qf, gf, eps);
+  if (lane == 0) thr[rl * nseg + sl] = th;
+}
+
+// Threshold of pass 2 from a finite b_t (see dense_bound_kernel), rounded down; -FLT_MAX without one.
+__device__ __forceinline__ float dense_threshold(float b, float qf, float gf, float eps) {
   float th = -FLT_MAX;
-  if (b < 0x7F800000u) {  // a finite b_t
-    const double qd = (double)qn[qi];
-    const double E = (double)eps * (qd + (double)gmax[s]);
-    const double x = 0.5 * (qd - ((double)__uint_as_float(b) + 2.0 * E));
+  if (b < INFINITY) {
+    const double qd = (double)qf;
+    const double E = (double)eps * (qd + (double)gf);
+    const double x = 0.5 * (qd - ((double)b + 2.0 * E));
     th = (float)x;
     if ((double)th > x) th = nextafterf(th, -INFINITY);
   }
-  if (lane == 0) thr[rl * nseg + sl] = th;
+  return th;
+}
+
+// The same threshold with one (row, shard) per lane, for t <= KMAX: the lane streams the values pass 1 kept for
+// the row and shard (16-byte loads) through an ascending list of its KMAX smallest, and b_t is the t-th of them.
+template <int KMAX>
+__global__ __launch_bounds__(64) void dense_bound_lanes_kernel(const float* __restrict__ M, int nvb, int gps, int cg,
+                                                               const int64_t* __restrict__ off,
+                                                               const int64_t* __restrict__ Rs, int s0, int nseg,
+                                                               const int* __restrict__ nrows_dev, int64_t nrows_max,
+                                                               int64_t row0, int64_t rows_chunk, int t,
+                                                               const uint32_t* __restrict__ list,
+                                                               const float* __restrict__ qn,
+                                                               const float* __restrict__ gmax, float eps,
+                                                               float* __restrict__ thr) {
+  const int64_t item = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t rl = item / nseg;
+  const int sl = (int)(item % nseg);
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  if (rl >= rows_chunk || row0 + rl >= n_rows) return;
+  const int s = s0 + sl;
+  const int64_t R = Rs[s];
+  const int kp = (int)(t < R ? t : R);
+  const int ntiles = (int)((off[s + 1] - off[s]) / 64);
+  const int n4 = ((ntiles + cg - 1) / cg) * nvb / 4;  // 16-byte groups of the blocks that ran
+  const f32x4_t* m4 = (const f32x4_t*)(M + (rl * nseg + sl) * (int64_t)gps * nvb);
+  const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+  const float qf = qn[qi], gf = gmax[s];
+  float top[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; i++) top[i] = INFINITY;
+#pragma unroll 4
+  for (int g = 0; g < n4; g++) {
+    const f32x4_t x = m4[g];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      float v = x[r];
+#pragma unroll
+      for (int i = 0; i < KMAX; i++) {
+        const float lo = fminf(top[i], v);
+        v = fmaxf(top[i], v);
+        top[i] = lo;
+      }
+    }
+  }
+  float b = INFINITY;
+#pragma unroll
+  for (int i = 0; i < KMAX; i++) b = i == kp - 1 ? top[i] : b;
+  thr[rl * nseg + sl] = dense_threshold(b, qf, gf, eps);
 }
 
 // Exact distance (the search's definition) of query row q to a stored row, by an 8-lane team; every lane of the
@@ -1469,8 +1555,22 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
       launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
                             thr, cmask);
-      hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, (int)gps, cg, G.off_dev, G.R_dev,
-                         s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, dense_eps(dk), thr);
+      {
+        const float eps = dense_eps(dk);
+        const dim3 gl((unsigned)((chunk * nseg + 63) / 64));
+        if (t <= 8)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<8>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+                             G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
+        else if (t <= 16)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<16>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+                             G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
+        else if (t <= 32)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<32>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+                             G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
+        else
+          hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+                             G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
+      }
       launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
                             thr, cmask);
       switch (store_dt) {
