@@ -16,6 +16,9 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "common.hpp"
 #include "pool.hpp"
@@ -840,6 +843,26 @@ __device__ __forceinline__ void write_kept(float* __restrict__ dst, const float 
   *(f32x4_t*)dst = o;
 }
 
+// Work item of a tile-pass block: (shard, row block, column group), numbered shard-major, and handed out so that
+// the blocks the dispatcher sends to one XCD (block ids congruent mod nxcd) take one contiguous run of items: a
+// run spans few shards and row blocks, so an XCD's L2 holds those shards' ghost tiles and those rows' queries.
+struct TileItem {
+  int sl, grp;
+  int64_t rb;
+};
+__device__ __forceinline__ bool tile_item(int nxcd, int64_t rtiles, int nseg, int gps, TileItem& it) {
+  const int64_t nitems = rtiles * nseg * gps;
+  const int64_t per = (nitems + nxcd - 1) / nxcd;
+  const int64_t b = blockIdx.x;
+  const int64_t item = (b % nxcd) * per + b / nxcd;
+  if (item >= nitems) return false;
+  it.sl = (int)(item / (rtiles * gps));
+  const int64_t r = item % (rtiles * gps);
+  it.rb = r / gps;
+  it.grp = (int)(r % gps);
+  return true;
+}
+
 // GEMM-form distances of a block's 64 query rows against a run of 64-column tiles of one shard, both operands
 // staged through LDS (rows of more than 128 elements). G = qn - 2 a with a = q.x - gn/2, three bf16 products
 // (hi.hi + hi.lo + lo.hi) accumulated in float32 onto -gn/2. Each wave owns 32 query rows and 32 ghosts of every
@@ -860,7 +883,7 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
-    float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
+    int nxcd, int64_t rtiles, float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
   constexpr int P = dense_lds_stride(DK);
   extern __shared__ __align__(16) char dsm[];
   __shared__ int64_t qrow[64];
@@ -872,8 +895,10 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
   uint16_t* Bl = Bh + 64 * P;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
-  const int64_t rl0 = (int64_t)blockIdx.y * 64;
-  const int sl = (int)(blockIdx.x / (unsigned)gps), grp = (int)(blockIdx.x % (unsigned)gps);
+  TileItem it;
+  if (!tile_item(nxcd, rtiles, nseg, gps, it)) return;
+  const int64_t rl0 = it.rb * 64;
+  const int sl = it.sl, grp = it.grp;
   const int s = s0 + sl;
   const int64_t cb = off[s];  // first column of the shard's block
   const int ntiles = (int)((off[s + 1] - cb) / 64);
@@ -940,65 +965,72 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
     write_kept(M + ((rl * nseg + sl) * gps + grp) * (4 * KEEP) + ((wave & 1) * 2 + h) * KEEP, mx, qv);
 }
 
-// The same passes for rows of at most 128 elements, with twice the rows per staged ghost tile: a block of 4 waves
-// owns 128 query rows, each wave keeps its 32 rows' hi and lo fragments in registers for the whole run of tiles
-// and multiplies them with both 32-ghost halves of every 64-column tile (six MFMAs per 16-element k step). Only
-// the ghost tile goes through LDS. Register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4.
+// Query row sets of 32 a wave of the wide tile kernel keeps in registers for rows of dk elements.
+__host__ __device__ constexpr int dense_wide_sets(int dk) { return dk <= 96 ? 2 : 1; }
+
+// The same passes for rows of at most 128 elements, with the query rows in registers: each wave keeps NS sets of
+// 32 rows' hi and lo fragments for the whole run of tiles (a block of 4 waves owns 128 NS rows) and multiplies them
+// with both 32-ghost halves of every 64-column tile, so each ghost fragment read from LDS feeds 3 NS MFMAs. Only the
+// ghost tile goes through LDS. Register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4.
 //   MODE 0: one maximum per register over both halves and the block's tiles; each lane writes its KEEP smallest
-//   G to M[row][shard][group][lane / 32][KEEP];
-//   MODE 1: the mask word of (row, shard, tile, lane / 32), bit 16 c + j.
-// (3 waves per SIMD fit without spills up to 96-element rows; wider rows keep the compiler's budget)
+//   G of each set's row to M[row][shard][group][lane / 32][KEEP];
+//   MODE 1: the mask word of (row, shard, tile, lane / 32), bit 16 c + j, per set.
+// (two sets and 2 waves per SIMD up to 96-element rows; one set and the compiler's budget above)
 template <int MODE, int DK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 3 : 1))) void dense_tiles_wide_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 2 : 1))) void dense_tiles_wide_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
-    float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
+    int nxcd, int64_t rtiles, float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
   static_assert(DK % 32 == 0 && DK <= 128, "DK");
   constexpr int P = dense_lds_stride(DK);
   constexpr int KB = DK / 16;
-  // two tile buffers where three blocks per CU still fit (the next tile is stored while this one is multiplied,
+  constexpr int NS = dense_wide_sets(DK);
+  // two tile buffers where two blocks per CU still fit (the next tile is stored while this one is multiplied,
   // one barrier per tile), else one
   constexpr int NBUF = DK <= 96 ? 2 : 1;
   __shared__ __align__(16) uint16_t Bh[NBUF][64 * P], Bl[NBUF][64 * P];
   __shared__ __align__(16) float ngl[NBUF][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
-  const int64_t rl0 = (int64_t)blockIdx.y * 128;
-  const int sl = (int)(blockIdx.x / (unsigned)gps), grp = (int)(blockIdx.x % (unsigned)gps);
+  TileItem it;
+  if (!tile_item(nxcd, rtiles, nseg, gps, it)) return;
+  const int64_t rl0 = it.rb * (128 * NS);
+  const int sl = it.sl, grp = it.grp;
   const int s = s0 + sl;
   const int64_t cb = off[s];  // first column of the shard's block
   const int ntiles = (int)((off[s + 1] - cb) / 64);
   const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
   if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
   const int h = lane >> 5, col = lane & 31;
-  const int64_t rl = rl0 + wave * 32 + col;  // this lane's row of the chunk
-  int64_t qa;
-  {
-    const int64_t gr = row0 + rl;
-    qa = gr < n_rows && rl < rows_chunk ? (list ? (int64_t)list[gr] : gr) : -1;
-  }
-  // MODE 0: the row's norm; MODE 1: its threshold on a (NaN for rows without a query)
-  const float qv = qa < 0 ? __builtin_nanf("") : (MODE == 0 ? qn[qa] : thr[rl * nseg + sl]);
-  bf16x8_t qh[KB], ql[KB];
-  {
+  int64_t rl[NS];  // this lane's rows of the chunk, one per set
+  float qv[NS];    // MODE 0: the row's norm; MODE 1: its threshold on a (NaN for rows without a query)
+  bf16x8_t qh[NS][KB], ql[NS][KB];
+#pragma unroll
+  for (int si = 0; si < NS; si++) {
+    rl[si] = rl0 + (wave * NS + si) * 32 + col;
+    const int64_t gr = row0 + rl[si];
+    const int64_t qa = gr < n_rows && rl[si] < rows_chunk ? (list ? (int64_t)list[gr] : gr) : -1;
+    qv[si] = qa < 0 ? __builtin_nanf("") : (MODE == 0 ? qn[qa] : thr[rl[si] * nseg + sl]);
     const int64_t q = qa < 0 ? 0 : qa;  // rows without a query read row 0
     const bf16x8_t* hp = (const bf16x8_t*)(Qh + q * DK + h * 8);
     const bf16x8_t* lp = (const bf16x8_t*)(Ql + q * DK + h * 8);
 #pragma unroll
     for (int kb = 0; kb < KB; kb++) {
-      qh[kb] = hp[2 * kb];
-      ql[kb] = lp[2 * kb];
+      qh[si][kb] = hp[2 * kb];
+      ql[si][kb] = lp[2 * kb];
     }
   }
   const int sr = tid >> 2, sc0 = tid & 3;
   Stage64<DK> nb;
   nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
   float ng = sc0 == 0 ? -0.5f * gn[cb + (int64_t)tt0 * 64 + sr] : 0.f;
-  float mx[16];
+  float mx[NS][16];
 #pragma unroll
-  for (int j = 0; j < 16; j++) mx[j] = -INFINITY;
+  for (int si = 0; si < NS; si++)
+#pragma unroll
+    for (int j = 0; j < 16; j++) mx[si][j] = -INFINITY;
   if constexpr (NBUF == 2) {
     nb.store(Bh[0], Bl[0], sr, sc0);
     if (sc0 == 0) ngl[0][sr] = ng;
@@ -1034,44 +1066,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
     }
     const uint16_t* bh = Bh[cur];
     const uint16_t* bl = Bl[cur];
-    f32x16_t acc[2];
+    uint32_t w[NS];
 #pragma unroll
-    for (int c = 0; c < 2; c++) init_acc(acc[c], ngl[cur] + 32 * c, h);
+    for (int si = 0; si < NS; si++) w[si] = 0;
+    // the tile's two 32-ghost halves one after the other (half the accumulator registers, left to fragment reads)
 #pragma unroll
-    for (int kb = 0; kb < KB; kb++) {
+    for (int c = 0; c < 2; c++) {
+      f32x16_t acc[NS];
+      init_acc(acc[0], ngl[cur] + 32 * c, h);
 #pragma unroll
-      for (int c = 0; c < 2; c++) {
+      for (int si = 1; si < NS; si++) acc[si] = acc[0];
+#pragma unroll
+      for (int kb = 0; kb < KB; kb++) {
         const int rb = (32 * c + col) * P + kb * 16 + h * 8;
         const bf16x8_t gh = *(const bf16x8_t*)&bh[rb], gl = *(const bf16x8_t*)&bl[rb];
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh[kb], acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh[kb], acc[c], 0, 0, 0);
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql[kb], acc[c], 0, 0, 0);
+#pragma unroll
+        for (int si = 0; si < NS; si++) {
+          acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh[si][kb], acc[si], 0, 0, 0);
+          acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh[si][kb], acc[si], 0, 0, 0);
+          acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql[si][kb], acc[si], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int si = 0; si < NS; si++) {
+        if constexpr (MODE == 0) {
+#pragma unroll
+          for (int j = 0; j < 16; j++) mx[si][j] = fmaxf(mx[si][j], acc[si][j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; j++) w[si] |= acc[si][j] >= qv[si] ? 1u << (16 * c + j) : 0u;
+        }
       }
     }
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 1) {
 #pragma unroll
-      for (int j = 0; j < 16; j++) mx[j] = fmaxf(mx[j], fmaxf(acc[0][j], acc[1][j]));
-    } else {
-      uint32_t w = 0;
-#pragma unroll
-      for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int j = 0; j < 16; j++) w |= acc[c][j] >= qv ? 1u << (16 * c + j) : 0u;
-      cmask[(rl * nseg + sl) * nht + 2 * tt + h] = w;
+      for (int si = 0; si < NS; si++) cmask[(rl[si] * nseg + sl) * nht + 2 * tt + h] = w[si];
     }
   }
-  if constexpr (MODE == 0) write_kept(M + ((rl * nseg + sl) * gps + grp) * (2 * KEEP) + h * KEEP, mx, qv);
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int si = 0; si < NS; si++)
+      write_kept(M + ((rl[si] * nseg + sl) * gps + grp) * (2 * KEEP) + h * KEEP, mx[si], qv[si]);
+  }
 }
 
 template <int MODE>
 static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
                                const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
                                int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
-                               float* Mg, const float* thr, uint32_t* cmask) {
+                               int nxcd, int64_t rtiles, float* Mg, const float* thr, uint32_t* cmask) {
 #define MIANN_DENSE_WIDE(KC)                                                                                         \
   case KC:                                                                                                           \
     hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
-                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, Mg, thr, cmask);          \
+                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, Mg, thr,    \
+                       cmask);                                                                                       \
     break;
 #define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
@@ -1081,7 +1129,7 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
     });                                                                                                              \
     hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
-                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, Mg, thr, cmask);                \
+                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, Mg, thr, cmask);  \
     break;                                                                                                           \
   }
   switch (dk / 32) {
@@ -1099,8 +1147,80 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
 #undef MIANN_DENSE_WIDE
 }
 
+// Blocks of the pass-1 tile kernel for rows of dk elements one CU holds at once, times the device's CUs (per device
+// and dk, from the occupancy query).
+static int64_t dense_tile_slots(int dk) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({dev, dk});
+  if (it != cache.end()) return it->second;
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+  hipError_t e = hipErrorInvalidValue;
+#define MIANN_SLOTS_WIDE(KC)                                                                                         \
+  case KC:                                                                                                           \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_wide_kernel<0, 32 * KC>, 256, 0);            \
+    break;
+#define MIANN_SLOTS_TILES(KC)                                                                                        \
+  case KC:                                                                                                           \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_kernel<0, 32 * KC>, 256, dense_tiles_lds(dk)); \
+    break;
+  switch (dk / 32) {
+    MIANN_SLOTS_WIDE(1)
+    MIANN_SLOTS_WIDE(2)
+    MIANN_SLOTS_WIDE(3)
+    MIANN_SLOTS_WIDE(4)
+    MIANN_SLOTS_TILES(5)
+    MIANN_SLOTS_TILES(6)
+    MIANN_SLOTS_TILES(7)
+    MIANN_SLOTS_TILES(8)
+    default: break;
+  }
+#undef MIANN_SLOTS_TILES
+#undef MIANN_SLOTS_WIDE
+  if (e != hipSuccess || per < 1) per = 1;
+  const int64_t slots = (int64_t)ncu * per;
+  cache[{dev, dk}] = slots;
+  return slots;
+}
+
+// The current device's XCDs (dies with their own L2), 1 if the runtime does not say.
+static int device_xcds() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || n < 1) n = 1;
+  cache[dev] = n;
+  return n;
+}
+
+// Column groups per shard for the tile passes over rtiles row blocks and nseg shards of at most ntmax tiles: the
+// split with the least time by rounds of blocks over the chip's slots times the tiles per block (plus one for the
+// block's prologue). Returns gps and sets cg, the tiles per group.
+static int64_t dense_groups(int64_t rtiles, int nseg, int64_t ntmax, int64_t slots, int* cg_out) {
+  int64_t best_g = 1, best_cost = INT64_MAX;
+  for (int64_t g = 1; g <= ntmax; g++) {
+    const int64_t cg = (ntmax + g - 1) / g;
+    const int64_t gg = (ntmax + cg - 1) / cg;
+    if (gg != g) continue;  // the same split as a smaller g
+    const int64_t blocks = rtiles * nseg * gg;
+    const int64_t cost = (blocks + slots - 1) / slots * (cg + 1);
+    if (cost < best_cost) best_cost = cost, best_g = gg;
+  }
+  *cg_out = (int)((ntmax + best_g - 1) / best_g);
+  return best_g;
+}
+
 // Rows per block of the tile passes for rows of dk elements, and the values pass 1 keeps per row and block.
-static int dense_block_rows(int dk) { return dk <= 128 ? 128 : 64; }
+static int dense_block_rows(int dk) { return dk <= 128 ? 128 * dense_wide_sets(dk) : 64; }
 static int dense_kept_per_block(int dk) { return dk <= 128 ? 2 * KEEP : 4 * KEEP; }
 
 __device__ __forceinline__ float dense_threshold(float b, float qf, float gf, float eps);
@@ -1538,23 +1658,23 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     else e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
     wb = (char*)lw.p;
     if (e != hipSuccess) break;
-    // column groups of cg tiles per block: enough blocks to fill the chip, each reusing its staged rows
+    // column groups of cg tiles per block, split to keep the chip's block slots busy (dense_groups)
     const int64_t rtiles = chunk / brows;
-    int64_t gps = (2048 + rtiles * nseg - 1) / (rtiles * nseg);
-    gps = std::max<int64_t>(1, std::min<int64_t>(gps, ntmax));
-    const int cg = (int)((ntmax + gps - 1) / gps);
-    gps = (ntmax + cg - 1) / cg;
+    int cg = 1;
+    const int64_t gps = dense_groups(rtiles, nseg, ntmax, dense_tile_slots(dk), &cg);
     const int nvb = dense_kept_per_block(dk);
     uint32_t* cmask = (uint32_t*)wb;
     float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
     float* thr = Mg + (size_t)chunk * nseg * gps * nvb;
-    const dim3 gg((unsigned)(nseg * gps), (unsigned)rtiles);
+    const int nxcd = device_xcds();
+    const int64_t nitems = rtiles * nseg * gps;
+    const dim3 gg((unsigned)((nitems + nxcd - 1) / nxcd * nxcd));
     const size_t lds = dense_tiles_lds(dk);
     const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
     const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
-      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
-                            thr, cmask);
+      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, nxcd,
+                            rtiles, Mg, thr, cmask);
       {
         const float eps = dense_eps(dk);
         const dim3 gl((unsigned)((chunk * nseg + 63) / 64));
@@ -1571,8 +1691,8 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
           hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
       }
-      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, Mg,
-                            thr, cmask);
+      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, nxcd,
+                            rtiles, Mg, thr, cmask);
       switch (store_dt) {
         case DT_F32:
           hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
