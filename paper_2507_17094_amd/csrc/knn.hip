@@ -772,7 +772,8 @@ __global__ __launch_bounds__(256) void dense_queries_kernel(const void* __restri
 }
 
 constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall back to an exact scan
-constexpr int KEEP = 4;   // pass 1: GEMM-form distances a lane keeps per block (its smallest)
+// Pass 1 keeps, per lane slot and block, KEEP of the GEMM-form distances of its 16 register classes: the 4 smallest
+// (t <= 8) or all 16, in a row of mcap values per (row, shard) (at least 2 t where the split of the tiles allows).
 
 // LDS of the tile kernels: hi and lo bf16 copies of 64 query rows and of 64
 // ghost columns, each row padded by 8 elements (16 bytes) against bank conflicts.
@@ -819,6 +820,7 @@ __device__ __forceinline__ void init_acc(f32x16_t& acc, const float* ngl, int h)
 }
 
 // Inserts x into k, kept in descending order.
+template <int KEEP>
 __device__ __forceinline__ void keep_largest(float (&k)[KEEP], float x) {
 #pragma unroll
   for (int i = 0; i < KEEP - 1; i++) {
@@ -829,18 +831,30 @@ __device__ __forceinline__ void keep_largest(float (&k)[KEEP], float x) {
   k[KEEP - 1] = fmaxf(k[KEEP - 1], x);
 }
 
-// Writes a lane's KEEP smallest GEMM-form distances G = qn - 2 a from its per-register maxima of a (16-byte
-// aligned destination).
+// Writes a lane's KEEP smallest GEMM-form distances G = qn - 2 a (clamped at 0) from its per-register maxima of a
+// (all 16 when KEEP is 16; 16-byte aligned destination).
+template <int KEEP>
 __device__ __forceinline__ void write_kept(float* __restrict__ dst, const float (&mx)[16], float qv) {
-  float k[KEEP];
+  if constexpr (KEEP == 16) {
 #pragma unroll
-  for (int i = 0; i < KEEP; i++) k[i] = -INFINITY;
+    for (int q = 0; q < 4; q++) {
+      f32x4_t o;
 #pragma unroll
-  for (int j = 0; j < 16; j++) keep_largest(k, mx[j]);
-  f32x4_t o;
+      for (int i = 0; i < 4; i++) o[i] = fmaxf(qv - 2.f * mx[4 * q + i], 0.f);
+      ((f32x4_t*)dst)[q] = o;
+    }
+  } else {
+    static_assert(KEEP == 4, "KEEP");
+    float k[KEEP];
 #pragma unroll
-  for (int i = 0; i < KEEP; i++) o[i] = fmaxf(qv - 2.f * k[i], 0.f);
-  *(f32x4_t*)dst = o;
+    for (int i = 0; i < KEEP; i++) k[i] = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 16; j++) keep_largest<KEEP>(k, mx[j]);
+    f32x4_t o;
+#pragma unroll
+    for (int i = 0; i < KEEP; i++) o[i] = fmaxf(qv - 2.f * k[i], 0.f);
+    *(f32x4_t*)dst = o;
+  }
 }
 
 // Work item of a tile-pass block: (shard, row block, column group), numbered shard-major, and handed out so that
@@ -868,22 +882,23 @@ __device__ __forceinline__ bool tile_item(int nxcd, int64_t rtiles, int nseg, in
 // (hi.hi + hi.lo + lo.hi) accumulated in float32 onto -gn/2. Each wave owns 32 query rows and 32 ghosts of every
 // tile; the ghosts are the first operand, so the accumulators leave one query per lane (lane & 31) and 16 ghosts
 // per lane (register j: ghost wc + 8 (j / 4) + 4 (lane / 32) + j % 4):
-//   MODE 0: per lane and register, the largest a over the block's tiles; at the end each lane writes its KEEP
-//   smallest G (clamped at 0), each the GEMM form of a distinct ghost, to
-//   M[row][shard][group][wave & 1][lane / 32][KEEP];
+//   MODE 0: per lane and register, the largest a over the block's tiles; at the end each lane writes KEEP of its
+//   G (the smallest; clamped at 0), each the GEMM form of a distinct ghost, to
+//   M[row][shard][group][wave & 1][lane / 32][KEEP] (mcap values per row and shard);
 //   MODE 1: the bits of the lane's 16 ghosts with a >= the row's threshold, as half word wave & 1 of the mask word
 //   of (row, shard, tile, lane / 32) -> cmask (bit 16 c + j is ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4 of
 //   the tile).
 // The next tile's columns are loaded into registers while the current one is multiplied. Padding columns carry
 // norm +inf, so their a is -inf: never a maximum or a candidate (thresholds are finite). Rows without a query get
 // a NaN threshold and never qualify; their pass-1 values land in the chunk's buffers and are never read.
-template <int MODE, int DK>
+template <int MODE, int DK, int KEEP>
 __global__ __launch_bounds__(256) void dense_tiles_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
-    int nxcd, int64_t rtiles, float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
+    int nxcd, int64_t rtiles, int mcap, float* __restrict__ M, const float* __restrict__ thr,
+    uint32_t* __restrict__ cmask) {
   constexpr int P = dense_lds_stride(DK);
   extern __shared__ __align__(16) char dsm[];
   __shared__ int64_t qrow[64];
@@ -962,7 +977,7 @@ __global__ __launch_bounds__(256) void dense_tiles_kernel(
     }
   }
   if constexpr (MODE == 0)
-    write_kept(M + ((rl * nseg + sl) * gps + grp) * (4 * KEEP) + ((wave & 1) * 2 + h) * KEEP, mx, qv);
+    write_kept<KEEP>(M + (rl * nseg + sl) * mcap + (grp * 4 + (wave & 1) * 2 + h) * KEEP, mx, qv);
 }
 
 // Query row sets of 32 a wave of the wide tile kernel keeps in registers for rows of dk elements.
@@ -972,17 +987,18 @@ __host__ __device__ constexpr int dense_wide_sets(int dk) { return dk <= 96 ? 2 
 // 32 rows' hi and lo fragments for the whole run of tiles (a block of 4 waves owns 128 NS rows) and multiplies them
 // with both 32-ghost halves of every 64-column tile, so each ghost fragment read from LDS feeds 3 NS MFMAs. Only the
 // ghost tile goes through LDS. Register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4.
-//   MODE 0: one maximum per register over both halves and the block's tiles; each lane writes its KEEP smallest
-//   G of each set's row to M[row][shard][group][lane / 32][KEEP];
+//   MODE 0: one maximum per register over both halves and the block's tiles; each lane writes KEEP of the G of
+//   each set's row to M[row][shard][group][lane / 32][KEEP];
 //   MODE 1: the mask word of (row, shard, tile, lane / 32), bit 16 c + j, per set.
 // (two sets and 2 waves per SIMD up to 96-element rows; one set and the compiler's budget above)
-template <int MODE, int DK>
+template <int MODE, int DK, int KEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 2 : 1))) void dense_tiles_wide_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
-    int nxcd, int64_t rtiles, float* __restrict__ M, const float* __restrict__ thr, uint32_t* __restrict__ cmask) {
+    int nxcd, int64_t rtiles, int mcap, float* __restrict__ M, const float* __restrict__ thr,
+    uint32_t* __restrict__ cmask) {
   static_assert(DK % 32 == 0 && DK <= 128, "DK");
   constexpr int P = dense_lds_stride(DK);
   constexpr int KB = DK / 16;
@@ -1106,30 +1122,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
   if constexpr (MODE == 0) {
 #pragma unroll
     for (int si = 0; si < NS; si++)
-      write_kept(M + ((rl[si] * nseg + sl) * gps + grp) * (2 * KEEP) + h * KEEP, mx[si], qv[si]);
+      write_kept<KEEP>(M + (rl[si] * nseg + sl) * mcap + (grp * 2 + h) * KEEP, mx[si], qv[si]);
   }
 }
 
-template <int MODE>
+template <int MODE, int KEEP>
 static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
                                const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
                                int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
-                               int nxcd, int64_t rtiles, float* Mg, const float* thr, uint32_t* cmask) {
+                               int nxcd, int64_t rtiles, int mcap, float* Mg, const float* thr, uint32_t* cmask) {
 #define MIANN_DENSE_WIDE(KC)                                                                                         \
   case KC:                                                                                                           \
-    hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
-                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, Mg, thr,    \
-                       cmask);                                                                                       \
+    hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC, KEEP>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
+                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, mcap, Mg,   \
+                       thr, cmask);                                                                                  \
     break;
 #define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
     static std::once_flag set;                                                                                       \
     std::call_once(set, [] {                                                                                         \
-      (void)hipFuncSetAttribute((const void*)dense_tiles_kernel<MODE, 32 * KC>,                                      \
+      (void)hipFuncSetAttribute((const void*)dense_tiles_kernel<MODE, 32 * KC, KEEP>,                                      \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
     });                                                                                                              \
-    hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
-                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, Mg, thr, cmask);  \
+    hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC, KEEP>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
+                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, mcap, Mg, thr,    \
+                       cmask);                                                                                       \
     break;                                                                                                           \
   }
   switch (dk / 32) {
@@ -1162,11 +1179,12 @@ static int64_t dense_tile_slots(int dk) {
   hipError_t e = hipErrorInvalidValue;
 #define MIANN_SLOTS_WIDE(KC)                                                                                         \
   case KC:                                                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_wide_kernel<0, 32 * KC>, 256, 0);            \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_wide_kernel<0, 32 * KC, 4>, 256, 0);         \
     break;
 #define MIANN_SLOTS_TILES(KC)                                                                                        \
   case KC:                                                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_kernel<0, 32 * KC>, 256, dense_tiles_lds(dk)); \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_kernel<0, 32 * KC, 4>, 256,                  \
+                                                     dense_tiles_lds(dk));                                         \
     break;
   switch (dk / 32) {
     MIANN_SLOTS_WIDE(1)
@@ -1202,15 +1220,18 @@ static int device_xcds() {
   return n;
 }
 
-// Column groups per shard for the tile passes over rtiles row blocks and nseg shards of at most ntmax tiles: the
-// split with the least time by rounds of blocks over the chip's slots times the tiles per block (plus one for the
-// block's prologue). Returns gps and sets cg, the tiles per group.
-static int64_t dense_groups(int64_t rtiles, int nseg, int64_t ntmax, int64_t slots, int* cg_out) {
-  int64_t best_g = 1, best_cost = INT64_MAX;
-  for (int64_t g = 1; g <= ntmax; g++) {
+// Column groups per shard for the tile passes over rtiles row blocks and nseg shards of at most ntmax tiles, between
+// g_min and g_max groups: the split with the least time by rounds of blocks over the chip's slots times the tiles
+// per block (plus one for the block's prologue). Returns gps and sets cg, the tiles per group.
+static int64_t dense_groups(int64_t rtiles, int nseg, int64_t ntmax, int64_t slots, int64_t g_min, int64_t g_max,
+                            int* cg_out) {
+  g_max = std::max<int64_t>(1, std::min(g_max, ntmax));
+  g_min = std::max<int64_t>(1, std::min(g_min, g_max));
+  int64_t best_g = g_min, best_cost = INT64_MAX;
+  for (int64_t g = g_min; g <= g_max; g++) {
     const int64_t cg = (ntmax + g - 1) / g;
     const int64_t gg = (ntmax + cg - 1) / cg;
-    if (gg != g) continue;  // the same split as a smaller g
+    if (gg != g || gg < g_min) continue;  // the same split as a smaller g
     const int64_t blocks = rtiles * nseg * gg;
     const int64_t cost = (blocks + slots - 1) / slots * (cg + 1);
     if (cost < best_cost) best_cost = cost, best_g = gg;
@@ -1221,20 +1242,21 @@ static int64_t dense_groups(int64_t rtiles, int nseg, int64_t ntmax, int64_t slo
 
 // Rows per block of the tile passes for rows of dk elements, and the values pass 1 keeps per row and block.
 static int dense_block_rows(int dk) { return dk <= 128 ? 128 * dense_wide_sets(dk) : 64; }
-static int dense_kept_per_block(int dk) { return dk <= 128 ? 2 * KEEP : 4 * KEEP; }
+// Lane slots (query sets x lane halves, per row) of a block of the pass-1 kernel for rows of dk elements.
+static int dense_slots_per_block(int dk) { return dk <= 128 ? 2 : 4; }
 
 __device__ __forceinline__ float dense_threshold(float b, float qf, float gf, float eps);
 
 // One wave per (row, shard): the threshold of pass 2, which keeps every exact top-t ghost of the shard.
 // G_j = qn + gn_j - 2 q.x_j is the GEMM form of the distance to ghost j, computed as qn - 2 a_j with
 // a_j = q.x_j - gn_j / 2 (split-bf16 products accumulated in float32), D_j the exact distance (the search's
-// definition), E >= |G_j - D_j|. Pass 1 left, per block of the shard's tiles, every lane's KEEP smallest G, each
+// definition), E >= |G_j - D_j|. Pass 1 left, per block of the shard's tiles, KEEP G per lane slot (its smallest), each
 // the G of a distinct ghost; so the t-th smallest b_t of those values has t ghosts with G <= b_t, hence D <= b_t + E
 // for t ghosts and tau_D (the t-th smallest D) <= b_t + E; an exact top-t ghost j then has
 // G_j <= D_j + E <= tau_D + E <= b_t + 2E, that is a_j >= (qn - b_t - 2E) / 2, the threshold (rounded down).
 // Fewer than t values (a shard with fewer than t ghosts, or t above what pass 1 keeps) give -FLT_MAX: every real
 // ghost qualifies, and no padding column (a = -inf). E = eps (qn + max_j gn_j), see dense_eps.
-__global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int nvb, int gps, int cg,
+__global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restrict__ M, int nvb, int mcap, int cg,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ Rs, int s0, int nseg,
                                                           const int* __restrict__ nrows_dev, int64_t nrows_max,
@@ -1254,7 +1276,7 @@ __global__ __launch_bounds__(256) void dense_bound_kernel(const float* __restric
   const int kp = (int)(t < R ? t : R);
   const int ntiles = (int)((off[s + 1] - off[s]) / 64);
   const int64_t nv = (int64_t)((ntiles + cg - 1) / cg) * nvb;  // the values of the blocks that ran
-  const float* m = M + (rl * nseg + sl) * (int64_t)gps * nvb;
+  const float* m = M + (rl * nseg + sl) * mcap;
   // the row's norm and the shard's largest ghost norm, loaded before the values are sorted
   const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
   const float qf = qn[qi], gf = gmax[s];
@@ -1306,7 +1328,7 @@ __device__ __forceinline__ float dense_threshold(float b, float qf, float gf, fl
 // The same threshold with one (row, shard) per lane, for t <= KMAX: the lane streams the values pass 1 kept for
 // the row and shard (16-byte loads) through an ascending list of its KMAX smallest, and b_t is the t-th of them.
 template <int KMAX>
-__global__ __launch_bounds__(64) void dense_bound_lanes_kernel(const float* __restrict__ M, int nvb, int gps, int cg,
+__global__ __launch_bounds__(64) void dense_bound_lanes_kernel(const float* __restrict__ M, int nvb, int mcap, int cg,
                                                                const int64_t* __restrict__ off,
                                                                const int64_t* __restrict__ Rs, int s0, int nseg,
                                                                const int* __restrict__ nrows_dev, int64_t nrows_max,
@@ -1325,7 +1347,7 @@ __global__ __launch_bounds__(64) void dense_bound_lanes_kernel(const float* __re
   const int kp = (int)(t < R ? t : R);
   const int ntiles = (int)((off[s + 1] - off[s]) / 64);
   const int n4 = ((ntiles + cg - 1) / cg) * nvb / 4;  // 16-byte groups of the blocks that ran
-  const f32x4_t* m4 = (const f32x4_t*)(M + (rl * nseg + sl) * (int64_t)gps * nvb);
+  const f32x4_t* m4 = (const f32x4_t*)(M + (rl * nseg + sl) * mcap);
   const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
   const float qf = qn[qi], gf = gmax[s];
   float top[KMAX];
@@ -1455,30 +1477,27 @@ __device__ __forceinline__ void exact_dist_team2(const void* __restrict__ Q, int
   }
 }
 
-// One wave per (row, shard): expand the candidate masks of the shard's half tiles into a column list, compute
-// every candidate's exact distance, sort, and write the exact top-t seeds (dist bits << 32 | node id) to
-// out[(q * S + s) * t + i]. A list longer than CAPG is replaced by an exact scan of all the shard's ghosts;
-// both give the exact top-t.
+// Candidate column of bit b of mask word i of a (row, shard): word i covers tile i / 2 and lane half i % 2.
+__device__ __forceinline__ uint32_t mask_col(int i, int b) {
+  return (uint32_t)((i >> 1) * 64 + 32 * (b >> 4) + 8 * ((b >> 2) & 3) + 4 * (i & 1) + (b & 3));
+}
+
+// One wave per (row, shard) item: expand the candidate masks of the shard's tiles into a column list, compute every
+// candidate's exact distance, sort, and write the exact top-t seeds (dist bits << 32 | node id) to
+// out[(q * S + s) * t + i]. A list longer than CAPG is replaced by an exact scan of all the shard's ghosts; both
+// give the exact top-t. (The path of lists too long for an 8-lane team.)
 template <int DT>
-__global__ __launch_bounds__(256) void dense_final_kernel(
-    const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
-    const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
-    const int64_t* __restrict__ Rs, int s0, int nseg, int t, const DenseShardDev* __restrict__ shd,
-    const void* __restrict__ qraw, int d_pad, int S, uint64_t* __restrict__ out) {
+__device__ void final_item_wave(const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
+                                int64_t row0, int64_t rl, int sl, const int64_t* __restrict__ Rs, int s0, int nseg,
+                                int t, const DenseShardDev* __restrict__ shd, const void* __restrict__ qraw,
+                                int d_pad, int S, uint64_t* __restrict__ out, uint64_t* ebuf) {
   constexpr int ESZ = Fmt<DT>::esize;
   constexpr bool kScaled = DT == DT_F16 || DT == DT_FP8;
-  __shared__ uint64_t ebufs[4 * CAPG];
-  const int wave = threadIdx.x >> 6, lane = lane_id(), team = lane >> 3, tl = lane & 7;
-  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
-  const int64_t rl = item / nseg;
-  const int sl = (int)(item % nseg);
-  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
-  if (rl >= rows_chunk || row0 + rl >= n_rows) return;
+  const int lane = lane_id(), team = lane >> 3, tl = lane & 7;
   const int s = s0 + sl;
   const int64_t R = Rs[s];
   const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
   const DenseShardDev sh = shd[s];
-  uint64_t* ebuf = ebufs + wave * CAPG;
   const size_t row_bytes = (size_t)d_pad * ESZ;
   // candidate columns: mask word i (one per lane and round) of tile i / 2 contributes the set bits of its lane
   // half i % 2: bit b is column 64 (i / 2) + 32 (b / 16) + 8 (b / 4 % 4) + 4 (i % 2) + b % 4
@@ -1499,7 +1518,7 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
     while (m) {
       const int b = __ffs(m) - 1;
       m &= m - 1;
-      if (at < CAPG) ebuf[at] = (uint64_t)((i >> 1) * 64 + 32 * (b >> 4) + 8 * ((b >> 2) & 3) + 4 * (i & 1) + (b & 3));
+      if (at < CAPG) ebuf[at] = (uint64_t)mask_col(i, b);
       at++;
     }
     n += (int)shfl_u32((uint32_t)pre, 63);
@@ -1558,6 +1577,97 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   }
 }
 
+constexpr int CAPT = 64;  // candidates an 8-lane team rescores; longer lists go to the block's waves
+
+// Exact rescoring: 32 (row, shard) items per block, one 8-lane team each. The team expands the candidate masks of
+// its item into a column list in LDS (lane l takes words l, l + 8, ...; a team prefix sum places its bits),
+// computes the candidates' exact distances two at a time, and writes each candidate whose rank among the keys
+// (dist bits << 32 | ghost) is below t to out[(q * S + s) * t + rank] (slots from the list's length to t get no
+// seed). Lists longer than CAPT are collected and then rescored one per wave (final_item_wave). Both give the exact
+// top-t.
+template <int DT>
+__global__ __launch_bounds__(256) void dense_final_kernel(
+    const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
+    const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
+    const int64_t* __restrict__ Rs, int s0, int nseg, int t, const DenseShardDev* __restrict__ shd,
+    const void* __restrict__ qraw, int d_pad, int S, uint64_t* __restrict__ out) {
+  constexpr int ESZ = Fmt<DT>::esize;
+  constexpr bool kScaled = DT == DT_F16 || DT == DT_FP8;
+  __shared__ uint64_t tbuf[32 * CAPT];
+  __shared__ uint64_t ebufs[4 * CAPG];
+  __shared__ int nover;
+  __shared__ int64_t over[32];
+  const int tid = threadIdx.x, wave = tid >> 6, team = tid >> 3, tl = tid & 7;
+  if (tid == 0) nover = 0;
+  __syncthreads();
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  const int64_t item = (int64_t)blockIdx.x * 32 + team;
+  const int64_t rl = item / nseg;
+  const int sl = (int)(item % nseg);
+  if (rl < rows_chunk && row0 + rl < n_rows) {  // uniform over the team
+    const int s = s0 + sl;
+    const int64_t R = Rs[s];
+    const int64_t qi = list ? (int64_t)list[row0 + rl] : row0 + rl;
+    const DenseShardDev sh = shd[s];
+    const size_t row_bytes = (size_t)d_pad * ESZ;
+    uint64_t* tb = tbuf + team * CAPT;
+    const int nt = (int)(2 * ((R + 63) / 64));
+    const uint32_t* mrow = cmask + (rl * nseg + sl) * nht;
+    int c = 0;
+    for (int i = tl; i < nt; i += 8) c += __popc(mrow[i]);
+    int pre = c;  // inclusive prefix over the team
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      const int y = (int)shfl_u32((uint32_t)pre, tl >= o ? (int)threadIdx.x % 64 - o : (int)threadIdx.x % 64);
+      pre += tl >= o ? y : 0;
+    }
+    const int n = (int)shfl_u32((uint32_t)pre, ((int)threadIdx.x % 64) | 7);
+    if (n > CAPT) {
+      if (tl == 0) over[atomicAdd(&nover, 1)] = item;
+    } else {
+      int at = pre - c;
+      for (int i = tl; i < nt; i += 8) {
+        uint32_t m = mrow[i];
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          tb[at++] = (uint64_t)mask_col(i, b);
+        }
+      }
+      wsync();
+      // exact distances, two candidates per round
+      for (int r0 = 0; r0 < n; r0 += 2) {
+        const uint32_t j0 = (uint32_t)tb[r0], j1 = r0 + 1 < n ? (uint32_t)tb[r0 + 1] : j0;
+        const float sc0 = kScaled ? sh.g_scale[j0] : 1.f, sc1 = kScaled ? sh.g_scale[j1] : 1.f;
+        uint32_t d0, d1;
+        exact_dist_team2<DT>(qraw, qi, (const char*)sh.g_store + (size_t)j0 * row_bytes, sc0,
+                             (const char*)sh.g_store + (size_t)j1 * row_bytes, sc1, d_pad, tl, d0, d1);
+        wsync();
+        if (tl == 0) {
+          tb[r0] = ((uint64_t)d0 << 32) | j0;
+          if (r0 + 1 < n) tb[r0 + 1] = ((uint64_t)d1 << 32) | j1;
+        }
+        wsync();
+      }
+      // rank of each candidate among the item's keys (all distinct: one key per ghost)
+      uint64_t* o = out + ((size_t)qi * S + s) * t;
+      for (int r = tl; r < n; r += 8) {
+        const uint64_t key = tb[r];
+        int rank = 0;
+        for (int i = 0; i < n; i++) rank += tb[i] < key;
+        if (rank < t) o[rank] = (key & 0xFFFFFFFF00000000ull) | sh.g_map[(uint32_t)key];
+      }
+      for (int r = n + tl; r < t; r += 8) o[r] = kDummy;
+    }
+  }
+  __syncthreads();
+  for (int k = wave; k < nover; k += 4) {
+    const int64_t it = over[k];
+    final_item_wave<DT>(cmask, nht, list, row0, it / nseg, (int)(it % nseg), Rs, s0, nseg, t, shd, qraw, d_pad, S,
+                        out, ebufs + wave * CAPG);
+  }
+}
+
 namespace {
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 // eps of the dense entry's error bound E = eps (qn + max gn) for rows of dk elements (see dense_bound_kernel).
@@ -1575,12 +1685,18 @@ size_t dense_query_bytes(int store_dt, int64_t nq, int d_pad, int dk) {
   return 2 * al256((size_t)nq * dk * 2) + al256((size_t)nq * 4) + al256((size_t)nq * d_pad * raw) +
          al256((size_t)nq * 4) + 256;
 }
-// Scratch bytes per row of a chunk in the pass over shards [s0, s1): candidate masks, the values pass 1 keeps
-// (at most one block per tile and 4 KEEP values per block) and thresholds.
-size_t dense_row_bytes(const DenseGhosts& G, int s0, int s1) {
+// Tiles of the largest shard in [s0, s1).
+int64_t dense_max_tiles(const DenseGhosts& G, int s0, int s1) {
   int64_t ntmax = 0;
   for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
-  return (size_t)(s1 - s0) * ((size_t)(2 * ntmax) * 4 + (size_t)ntmax * 4 * KEEP * 4 + 4);
+  return ntmax;
+}
+// Scratch bytes per row of a chunk in the pass over shards [s0, s1): candidate masks, the mcap values pass 1 keeps
+// per shard, and thresholds. (mcap < 0: the most any split can keep, 16 per lane slot and tile.)
+size_t dense_row_bytes(const DenseGhosts& G, int s0, int s1, int dk, int64_t mcap) {
+  const int64_t ntmax = dense_max_tiles(G, s0, s1);
+  if (mcap < 0) mcap = std::max<int64_t>(4, ntmax * dense_slots_per_block(dk) * 16);
+  return (size_t)(s1 - s0) * ((size_t)(2 * ntmax) * 4 + (size_t)mcap * 4 + 4);
 }
 }  // namespace
 
@@ -1590,7 +1706,7 @@ size_t dense_entry_min_scratch(int store_dt, int64_t nq, int d_pad, int dk, int 
   const int npass = start_only ? S : 1;
   for (int ps = 0; ps < npass; ps++) {
     const int s0 = start_only ? ps : 0, s1 = start_only ? ps + 1 : S;
-    per_row = std::max(per_row, dense_row_bytes(G, s0, s1));
+    per_row = std::max(per_row, dense_row_bytes(G, s0, s1, dk, -1));
   }
   return dense_query_bytes(store_dt, nq, d_pad, dk) + (size_t)dense_block_rows(dk) * per_row + 4096;
 }
@@ -1640,13 +1756,23 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       rl = list;
       rc = qcnt;
     }
-    // per chunk of rows: candidate masks [rows][nseg][nht], kept values [rows][nseg][gps][nvb], thresholds
+    // per chunk of rows: candidate masks [rows][nseg][nht], kept values [rows][nseg][mcap], thresholds
     // [rows][nseg]
-    int64_t ntmax = 0;
-    for (int sx = s0; sx < s1; sx++) ntmax = std::max<int64_t>(ntmax, (G.off[sx + 1] - G.off[sx]) / 64);
+    const int64_t ntmax = dense_max_tiles(G, s0, s1);
     const int64_t nht = 2 * ntmax;
-    const size_t per_row = dense_row_bytes(G, s0, s1);
     const int brows = dense_block_rows(dk);
+    // pass 1 keeps the 4 smallest values per lane slot for t <= 8, else all 16, and at least 2 t values per (row,
+    // shard) where the tiles allow; the column groups of cg tiles per block are split to keep the chip's block
+    // slots busy (dense_groups). The split for all rows in one chunk fixes mcap; a smaller chunk splits within it.
+    const int keep = t <= 8 ? 4 : 16;
+    const int nvb = dense_slots_per_block(dk) * keep;
+    const int64_t g_min = (2 * t + nvb - 1) / nvb;
+    const int64_t tslots = dense_tile_slots(dk);
+    const int64_t rows_all = (nq + brows - 1) / brows * brows;
+    int cg = 1;
+    const int64_t g_all = dense_groups(rows_all / brows, nseg, ntmax, tslots, g_min, ntmax, &cg);
+    const int mcap = (int)((g_all * nvb + 3) / 4 * 4);
+    const size_t per_row = dense_row_bytes(G, s0, s1, dk, mcap);
     // at most 512 MB of scratch, or what the caller's buffer leaves after the query buffers
     const size_t work_cap = ext ? ext_bytes - total - 4096 : ((size_t)1 << 29);
     int64_t chunk = (int64_t)(work_cap / per_row);
@@ -1658,56 +1784,60 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     else e = scratch_lease(kSlotDenseWork, (size_t)chunk * per_row + 4096, st, &lw);
     wb = (char*)lw.p;
     if (e != hipSuccess) break;
-    // column groups of cg tiles per block, split to keep the chip's block slots busy (dense_groups)
     const int64_t rtiles = chunk / brows;
-    int cg = 1;
-    const int64_t gps = dense_groups(rtiles, nseg, ntmax, dense_tile_slots(dk), &cg);
-    const int nvb = dense_kept_per_block(dk);
+    const int64_t gps = dense_groups(rtiles, nseg, ntmax, tslots, g_min, mcap / nvb, &cg);
     uint32_t* cmask = (uint32_t*)wb;
     float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
-    float* thr = Mg + (size_t)chunk * nseg * gps * nvb;
+    float* thr = Mg + (size_t)chunk * nseg * mcap;
     const int nxcd = device_xcds();
     const int64_t nitems = rtiles * nseg * gps;
     const dim3 gg((unsigned)((nitems + nxcd - 1) / nxcd * nxcd));
     const size_t lds = dense_tiles_lds(dk);
     const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
+    const unsigned gf = (unsigned)((chunk * nseg + 31) / 32);
     const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
-      launch_dense_tiles<0>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, nxcd,
-                            rtiles, Mg, thr, cmask);
+      if (keep == 16)
+        launch_dense_tiles<0, 16>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+                                  nxcd, rtiles, mcap, Mg, thr, cmask);
+      else
+        launch_dense_tiles<0, 4>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+                                 nxcd, rtiles, mcap, Mg, thr, cmask);
       {
         const float eps = dense_eps(dk);
         const dim3 gl((unsigned)((chunk * nseg + 63) / 64));
-        if (t <= 8)
-          hipLaunchKernelGGL(dense_bound_lanes_kernel<8>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+        // one item per lane while its values are few; the wave per item (a few values per lane) otherwise
+        const bool lanes = (int64_t)gps * nvb <= 128;
+        if (lanes && t <= 8)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<8>, gl, dim3(64), 0, st, Mg, nvb, mcap, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
-        else if (t <= 16)
-          hipLaunchKernelGGL(dense_bound_lanes_kernel<16>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+        else if (lanes && t <= 16)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<16>, gl, dim3(64), 0, st, Mg, nvb, mcap, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
-        else if (t <= 32)
-          hipLaunchKernelGGL(dense_bound_lanes_kernel<32>, gl, dim3(64), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+        else if (lanes && t <= 32)
+          hipLaunchKernelGGL(dense_bound_lanes_kernel<32>, gl, dim3(64), 0, st, Mg, nvb, mcap, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
         else
-          hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, (int)gps, cg, G.off_dev,
+          hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, mcap, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
       }
-      launch_dense_tiles<1>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh, nxcd,
-                            rtiles, Mg, thr, cmask);
+      launch_dense_tiles<1, 4>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+                               nxcd, rtiles, mcap, Mg, thr, cmask);
       switch (store_dt) {
         case DT_F32:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_F16:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         case DT_FP8:
-          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
         default:
-          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq,
+          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
                              row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
           break;
       }

@@ -96,20 +96,21 @@ def test_dense_entry_equidistant_ghosts():
         compare(g, o, label=f"signs-{kw}", ndist_check=False)
 
 
-@pytest.mark.parametrize("t", [8, 20])
-def test_dense_entry_near_ties_inside_the_window(t):
-    """Near ties the GEMM form cannot separate: around each query, 30 ghosts at distances 1 + k 1e-6 (a spacing
+@pytest.mark.parametrize("t,n_near", [(8, 30), (20, 30), (8, 100)])
+def test_dense_entry_near_ties_inside_the_window(t, n_near):
+    """Near ties the GEMM form cannot separate: around each query, n_near ghosts at distances 1 + k 1e-6 (a spacing
     far below the GEMM form's error bound, but resolved by the exact distance), the other ghosts at distance 2 or
     more. With every node a ghost and T = 0, the result is the exact top-k of the t seeds, so the seeds must be
-    the exact top-t of the 30 (the window holds all of them and is rescored exactly)."""
+    the exact top-t of the n_near (the window holds all of them and is rescored exactly). 30 near ghosts fit one
+    8-lane team's list; 100 take the per-wave path for longer lists."""
     rng = np.random.default_rng(62)
     d, n_q = 64, 8
     Q = (10.0 * rng.standard_normal((n_q, d)) / np.sqrt(d)).astype(np.float32)
     rows = []
     for q in Q:
-        u = rng.standard_normal((30, d))
+        u = rng.standard_normal((n_near, d))
         u /= np.linalg.norm(u, axis=1, keepdims=True)
-        r = np.sqrt(1.0 + 1e-6 * rng.permutation(30))[:, None]
+        r = np.sqrt(1.0 + 1e-6 * rng.permutation(n_near))[:, None]
         rows.append(q + u * r)
         v = rng.standard_normal((30, d))
         v /= np.linalg.norm(v, axis=1, keepdims=True)
@@ -119,7 +120,7 @@ def test_dense_entry_near_ties_inside_the_window(t):
     gx = to_device_index(ox, dgs=False)
     opts = miann.SearchOptions(entry="ghost_dense", t_seeds=t)
     g, o = run_both(ox, gx, Q, t, 32, 0, opts)
-    compare(g, o, min_frac=1.0, label=f"near-ties-t{t}", ndist_check=False)
+    compare(g, o, min_frac=1.0, label=f"near-ties-t{t}-n{n_near}", ndist_check=False)
 
 
 @pytest.mark.parametrize("S", [2, 3])
