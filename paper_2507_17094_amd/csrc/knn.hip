@@ -1768,7 +1768,9 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     const int nvb = dense_slots_per_block(dk) * keep;
     const int64_t g_min = (2 * t + nvb - 1) / nvb;
     const int64_t tslots = dense_tile_slots(dk);
-    const int64_t rows_all = (nq + brows - 1) / brows * brows;
+    // (a pass over the queries that start on one shard holds about nq / S of them)
+    const int64_t rows_exp = start_only ? (nq + S - 1) / S : nq;
+    const int64_t rows_all = (rows_exp + brows - 1) / brows * brows;
     int cg = 1;
     const int64_t g_all = dense_groups(rows_all / brows, nseg, ntmax, tslots, g_min, ntmax, &cg);
     const int mcap = (int)((g_all * nvb + 3) / 4 * 4);
@@ -1785,11 +1787,13 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     wb = (char*)lw.p;
     if (e != hipSuccess) break;
     const int64_t rtiles = chunk / brows;
-    const int64_t gps = dense_groups(rtiles, nseg, ntmax, tslots, g_min, mcap / nvb, &cg);
+    const int64_t gps =
+        dense_groups(std::min(rtiles, rows_all / brows), nseg, ntmax, tslots, g_min, mcap / nvb, &cg);
     uint32_t* cmask = (uint32_t*)wb;
     float* Mg = (float*)(cmask + (size_t)chunk * nseg * nht);
     float* thr = Mg + (size_t)chunk * nseg * mcap;
-    const int nxcd = device_xcds();
+    // (rows counted on the device fill only the first row blocks: plain block order spreads them over the XCDs)
+    const int nxcd = rc ? 1 : device_xcds();
     const int64_t nitems = rtiles * nseg * gps;
     const dim3 gg((unsigned)((nitems + nxcd - 1) / nxcd * nxcd));
     const size_t lds = dense_tiles_lds(dk);
