@@ -1487,7 +1487,7 @@ __device__ __forceinline__ uint32_t mask_col(int i, int b) {
 // out[(q * S + s) * t + i]. A list longer than CAPG is replaced by an exact scan of all the shard's ghosts; both
 // give the exact top-t. (The path of lists too long for an 8-lane team.)
 template <int DT>
-__device__ void final_item_wave(const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
+__device__ __forceinline__ void final_item_wave(const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
                                 int64_t row0, int64_t rl, int sl, const int64_t* __restrict__ Rs, int s0, int nseg,
                                 int t, const DenseShardDev* __restrict__ shd, const void* __restrict__ qraw,
                                 int d_pad, int S, uint64_t* __restrict__ out, uint64_t* ebuf) {
@@ -1584,8 +1584,9 @@ constexpr int CAPT = 64;  // candidates an 8-lane team rescores; longer lists go
 // computes the candidates' exact distances two at a time, and writes each candidate whose rank among the keys
 // (dist bits << 32 | ghost) is below t to out[(q * S + s) * t + rank] (slots from the list's length to t get no
 // seed). Lists longer than CAPT are collected and then rescored one per wave (final_item_wave). Both give the exact
-// top-t.
-template <int DT>
+// top-t. With TEAM false (t above 16: lists of t and more, which a team rescores in too many dependent rounds)
+// each wave rescores one item of the block's four directly.
+template <int DT, bool TEAM>
 __global__ __launch_bounds__(256) void dense_final_kernel(
     const uint32_t* __restrict__ cmask, int nht, const uint32_t* __restrict__ list,
     const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0, int64_t rows_chunk,
@@ -1598,9 +1599,16 @@ __global__ __launch_bounds__(256) void dense_final_kernel(
   __shared__ int nover;
   __shared__ int64_t over[32];
   const int tid = threadIdx.x, wave = tid >> 6, team = tid >> 3, tl = tid & 7;
+  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
+  if constexpr (!TEAM) {
+    const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+    if (it / nseg < rows_chunk && row0 + it / nseg < n_rows)
+      final_item_wave<DT>(cmask, nht, list, row0, it / nseg, (int)(it % nseg), Rs, s0, nseg, t, shd, qraw, d_pad, S,
+                          out, ebufs + wave * CAPG);
+    return;
+  }
   if (tid == 0) nover = 0;
   __syncthreads();
-  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   const int64_t item = (int64_t)blockIdx.x * 32 + team;
   const int64_t rl = item / nseg;
   const int sl = (int)(item % nseg);
@@ -1827,24 +1835,21 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
       }
       launch_dense_tiles<1, 4>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                                nxcd, rtiles, mcap, Mg, thr, cmask);
+      // exact rescoring: one 8-lane team per item for t <= 16, one wave per item above
+#define MIANN_DENSE_FINAL(DTV)                                                                                       \
+  if (t <= 16)                                                                                                       \
+    hipLaunchKernelGGL((dense_final_kernel<DTV, true>), dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq, row0,     \
+                       chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);                               \
+  else                                                                                                               \
+    hipLaunchKernelGGL((dense_final_kernel<DTV, false>), dim3(gw), dim3(256), 0, st, cmask, nh, rl, rc, nq, row0,    \
+                       chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
       switch (store_dt) {
-        case DT_F32:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F32>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
-                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
-          break;
-        case DT_F16:
-          hipLaunchKernelGGL(dense_final_kernel<DT_F16>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
-                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
-          break;
-        case DT_FP8:
-          hipLaunchKernelGGL(dense_final_kernel<DT_FP8>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
-                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
-          break;
-        default:
-          hipLaunchKernelGGL(dense_final_kernel<DT_U8>, dim3(gf), dim3(256), 0, st, cmask, nh, rl, rc, nq,
-                             row0, chunk, G.R_dev, s0, nseg, t, G.shards_dev, qraw, d_pad, S, out);
-          break;
+        case DT_F32: MIANN_DENSE_FINAL(DT_F32) break;
+        case DT_F16: MIANN_DENSE_FINAL(DT_F16) break;
+        case DT_FP8: MIANN_DENSE_FINAL(DT_FP8) break;
+        default: MIANN_DENSE_FINAL(DT_U8) break;
       }
+#undef MIANN_DENSE_FINAL
       e = hipGetLastError();
     }
     if (!ext) scratch_release(kSlotDenseWork, lw, st);
