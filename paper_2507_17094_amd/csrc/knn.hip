@@ -775,10 +775,9 @@ constexpr int CAPG = 256; // candidates sorted per (query, shard); more fall bac
 // Pass 1 keeps, per lane slot and block, KEEP of the GEMM-form distances of its 16 register classes: the 4 smallest
 // (t <= 8) or all 16, in a row of mcap values per (row, shard) (at least 2 t where the split of the tiles allows).
 
-// LDS of the tile kernels: hi and lo bf16 copies of 64 query rows and of 64
-// ghost columns, each row padded by 8 elements (16 bytes) against bank conflicts.
+// LDS rows of the tile kernel: hi and lo bf16 copies of 64 ghost columns, each row padded by 8 elements (16 bytes)
+// against bank conflicts.
 __host__ __device__ constexpr int dense_lds_stride(int dk) { return dk + 8; }
-inline size_t dense_tiles_lds(int dk) { return (size_t)4 * 64 * dense_lds_stride(dk) * 2; }
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -877,137 +876,48 @@ __device__ __forceinline__ bool tile_item(int nxcd, int64_t rtiles, int nseg, in
   return true;
 }
 
-// GEMM-form distances of a block's 64 query rows against a run of 64-column tiles of one shard, both operands
-// staged through LDS (rows of more than 128 elements). G = qn - 2 a with a = q.x - gn/2, three bf16 products
-// (hi.hi + hi.lo + lo.hi) accumulated in float32 onto -gn/2. Each wave owns 32 query rows and 32 ghosts of every
-// tile; the ghosts are the first operand, so the accumulators leave one query per lane (lane & 31) and 16 ghosts
-// per lane (register j: ghost wc + 8 (j / 4) + 4 (lane / 32) + j % 4):
-//   MODE 0: per lane and register, the largest a over the block's tiles; at the end each lane writes KEEP of its
-//   G (the smallest; clamped at 0), each the GEMM form of a distinct ghost, to
-//   M[row][shard][group][wave & 1][lane / 32][KEEP] (mcap values per row and shard);
-//   MODE 1: the bits of the lane's 16 ghosts with a >= the row's threshold, as half word wave & 1 of the mask word
-//   of (row, shard, tile, lane / 32) -> cmask (bit 16 c + j is ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4 of
-//   the tile).
+// Query row sets of 32 a wave of the tile kernel keeps in registers for rows of dk elements, and the ghost tile
+// buffers in LDS (two where two blocks per CU still fit: the next tile is stored while this one is multiplied, one
+// barrier per tile).
+__host__ __device__ constexpr int dense_wide_sets(int dk) { return dk <= 96 ? 2 : 1; }
+__host__ __device__ constexpr int dense_wide_bufs(int dk) { return dk <= 96 ? 2 : 1; }
+// Dynamic LDS of the tile kernel: NBUF x (hi and lo tiles of 64 padded rows, 64 floats of -gn/2).
+inline size_t dense_wide_lds(int dk) {
+  return (size_t)dense_wide_bufs(dk) * ((size_t)2 * 64 * dense_lds_stride(dk) * 2 + 64 * 4);
+}
+
+// GEMM-form distances G = qn - 2 a with a = q.x - gn/2 (three bf16 products hi.hi + hi.lo + lo.hi accumulated in
+// float32 onto -gn/2) of a block's query rows against a run of 64-column ghost tiles of one shard. Each wave keeps
+// NS sets of 32 rows' hi and lo fragments in registers for the whole run of tiles (a block of 4 waves owns 128 NS
+// rows) and multiplies them with the two 32-ghost halves of every tile in turn, ghosts as the first operand, so an
+// accumulator leaves one query per lane (lane & 31), each ghost fragment read from LDS feeds 3 NS MFMAs, and
+// register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4. Only the ghost tile goes through LDS.
+//   MODE 0: one maximum of a per register over the block's tiles; each lane writes KEEP of the G of each set's
+//   row (the smallest; clamped at 0), each the GEMM form of a distinct ghost, to
+//   M[row][shard][group][lane / 32][KEEP] (mcap values per row and shard);
+//   MODE 1: the mask word of (row, shard, tile, lane / 32) of each set's row: bit 16 c + j for a at or above the
+//   row's threshold.
 // The next tile's columns are loaded into registers while the current one is multiplied. Padding columns carry
 // norm +inf, so their a is -inf: never a maximum or a candidate (thresholds are finite). Rows without a query get
 // a NaN threshold and never qualify; their pass-1 values land in the chunk's buffers and are never read.
+// (two sets and 2 waves per SIMD up to 96-element rows; one set above, at most 256 registers)
 template <int MODE, int DK, int KEEP>
-__global__ __launch_bounds__(256) void dense_tiles_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void dense_tiles_wide_kernel(
     const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
     const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
     int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
     const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
     int nxcd, int64_t rtiles, int mcap, float* __restrict__ M, const float* __restrict__ thr,
     uint32_t* __restrict__ cmask) {
-  constexpr int P = dense_lds_stride(DK);
-  extern __shared__ __align__(16) char dsm[];
-  __shared__ int64_t qrow[64];
-  __shared__ float qvl[64];
-  __shared__ __align__(16) float ngl[64];
-  uint16_t* Ah = (uint16_t*)dsm;
-  uint16_t* Al = Ah + 64 * P;
-  uint16_t* Bh = Al + 64 * P;
-  uint16_t* Bl = Bh + 64 * P;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
-  TileItem it;
-  if (!tile_item(nxcd, rtiles, nseg, gps, it)) return;
-  const int64_t rl0 = it.rb * 64;
-  const int sl = it.sl, grp = it.grp;
-  const int s = s0 + sl;
-  const int64_t cb = off[s];  // first column of the shard's block
-  const int ntiles = (int)((off[s + 1] - cb) / 64);
-  const int tt0 = grp * cg, tt1 = tt0 + cg < ntiles ? tt0 + cg : ntiles;
-  if (row0 + rl0 >= n_rows || rl0 >= rows_chunk || tt0 >= tt1) return;
-  if (tid < 64) {
-    const int64_t gr = row0 + rl0 + tid;
-    const bool ok = gr < n_rows && rl0 + tid < rows_chunk;
-    const int64_t q = ok ? (list ? (int64_t)list[gr] : gr) : -1;
-    qrow[tid] = q;
-    // MODE 0: the row's norm; MODE 1: its threshold on a (NaN for rows without a query)
-    qvl[tid] = !ok ? __builtin_nanf("") : (MODE == 0 ? qn[q] : thr[(rl0 + tid) * nseg + sl]);
-  }
-  const int sr = tid >> 2, sc0 = tid & 3;
-  Stage64<DK> nb;
-  nb.load(Gh, Gl, cb + (int64_t)tt0 * 64 + sr, sc0);
-  float ng = sc0 == 0 ? -0.5f * gn[cb + (int64_t)tt0 * 64 + sr] : 0.f;
-  __syncthreads();
-  {
-    Stage64<DK> a;
-    const int64_t q = qrow[sr];
-    a.load(Qh, Ql, q < 0 ? 0 : q, sc0);  // rows without a query read row 0
-    a.store(Ah, Al, sr, sc0);
-  }
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int h = lane >> 5, col = lane & 31;
-  const int64_t rl = rl0 + wr + col;  // this lane's row of the chunk
-  const float qv = qvl[wr + col];
-  const int ra = (wr + col) * P + h * 8, rb = (wc + col) * P + h * 8;
-  float mx[16];
-#pragma unroll
-  for (int j = 0; j < 16; j++) mx[j] = -INFINITY;
-  for (int tt = tt0; tt < tt1; tt++) {
-    __syncthreads();  // the previous tile is consumed
-    nb.store(Bh, Bl, sr, sc0);
-    if (sc0 == 0) ngl[sr] = ng;
-    {
-      const int64_t nxt = cb + (int64_t)(tt + 1 < tt1 ? tt + 1 : tt) * 64 + sr;  // (the last tile reloads itself)
-      nb.load(Gh, Gl, nxt, sc0);
-      if (sc0 == 0) ng = -0.5f * gn[nxt];
-    }
-    __syncthreads();
-    f32x16_t acc;
-    init_acc(acc, ngl + wc, h);
-#pragma unroll
-    for (int kk = 0; kk < DK; kk += 16) {
-      const bf16x8_t qh = *(const bf16x8_t*)&Ah[ra + kk], ql = *(const bf16x8_t*)&Al[ra + kk];
-      const bf16x8_t gh = *(const bf16x8_t*)&Bh[rb + kk], gl = *(const bf16x8_t*)&Bl[rb + kk];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, qh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gl, qh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gh, ql, acc, 0, 0, 0);
-    }
-    if constexpr (MODE == 0) {
-#pragma unroll
-      for (int j = 0; j < 16; j++) mx[j] = fmaxf(mx[j], acc[j]);
-    } else {
-      uint32_t w = 0;
-#pragma unroll
-      for (int j = 0; j < 16; j++) w |= acc[j] >= qv ? 1u << j : 0u;
-      ((uint16_t*)(cmask + (rl * nseg + sl) * nht + 2 * tt + h))[wave & 1] = (uint16_t)w;
-    }
-  }
-  if constexpr (MODE == 0)
-    write_kept<KEEP>(M + (rl * nseg + sl) * mcap + (grp * 4 + (wave & 1) * 2 + h) * KEEP, mx, qv);
-}
-
-// Query row sets of 32 a wave of the wide tile kernel keeps in registers for rows of dk elements.
-__host__ __device__ constexpr int dense_wide_sets(int dk) { return dk <= 96 ? 2 : 1; }
-
-// The same passes for rows of at most 128 elements, with the query rows in registers: each wave keeps NS sets of
-// 32 rows' hi and lo fragments for the whole run of tiles (a block of 4 waves owns 128 NS rows) and multiplies them
-// with both 32-ghost halves of every 64-column tile, so each ghost fragment read from LDS feeds 3 NS MFMAs. Only the
-// ghost tile goes through LDS. Register j of half c holds ghost 32 c + 8 (j / 4) + 4 (lane / 32) + j % 4.
-//   MODE 0: one maximum per register over both halves and the block's tiles; each lane writes KEEP of the G of
-//   each set's row to M[row][shard][group][lane / 32][KEEP];
-//   MODE 1: the mask word of (row, shard, tile, lane / 32), bit 16 c + j, per set.
-// (two sets and 2 waves per SIMD up to 96-element rows; one set and the compiler's budget above)
-template <int MODE, int DK, int KEEP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 2 : 1))) void dense_tiles_wide_kernel(
-    const uint16_t* __restrict__ Qh, const uint16_t* __restrict__ Ql, const float* __restrict__ qn,
-    const uint32_t* __restrict__ list, const int* __restrict__ nrows_dev, int64_t nrows_max, int64_t row0,
-    int64_t rows_chunk, const uint16_t* __restrict__ Gh, const uint16_t* __restrict__ Gl,
-    const float* __restrict__ gn, const int64_t* __restrict__ off, int s0, int nseg, int gps, int cg, int nht,
-    int nxcd, int64_t rtiles, int mcap, float* __restrict__ M, const float* __restrict__ thr,
-    uint32_t* __restrict__ cmask) {
-  static_assert(DK % 32 == 0 && DK <= 128, "DK");
+  static_assert(DK % 32 == 0 && DK <= 256, "DK");
   constexpr int P = dense_lds_stride(DK);
   constexpr int KB = DK / 16;
   constexpr int NS = dense_wide_sets(DK);
-  // two tile buffers where two blocks per CU still fit (the next tile is stored while this one is multiplied,
-  // one barrier per tile), else one
-  constexpr int NBUF = DK <= 96 ? 2 : 1;
-  __shared__ __align__(16) uint16_t Bh[NBUF][64 * P], Bl[NBUF][64 * P];
-  __shared__ __align__(16) float ngl[NBUF][64];
+  constexpr int NBUF = dense_wide_bufs(DK);
+  extern __shared__ __align__(16) char dsm[];
+  uint16_t(*Bh)[64 * P] = (uint16_t(*)[64 * P])dsm;
+  uint16_t(*Bl)[64 * P] = Bh + NBUF;
+  float(*ngl)[64] = (float(*)[64])(Bl + NBUF);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_rows = nrows_dev ? (int64_t)*nrows_dev : nrows_max;
   TileItem it;
@@ -1127,26 +1037,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 96 ? 
 }
 
 template <int MODE, int KEEP>
-static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
+static void launch_dense_tiles(int dk, dim3 grid, hipStream_t st, const uint16_t* qh, const uint16_t* ql,
                                const float* qn, const uint32_t* rl, const int* rc, int64_t nq, int64_t row0,
                                int64_t chunk, const DenseGhosts& G, int s0, int nseg, int gps, int cg, int nht,
                                int nxcd, int64_t rtiles, int mcap, float* Mg, const float* thr, uint32_t* cmask) {
+  const size_t lds = dense_wide_lds(dk);
 #define MIANN_DENSE_WIDE(KC)                                                                                         \
-  case KC:                                                                                                           \
-    hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC, KEEP>), grid, dim3(256), 0, st, qh, ql, qn, rl, rc, nq,     \
-                       row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, mcap, Mg,   \
-                       thr, cmask);                                                                                  \
-    break;
-#define MIANN_DENSE_TILES(KC)                                                                                        \
   case KC: {                                                                                                         \
     static std::once_flag set;                                                                                       \
     std::call_once(set, [] {                                                                                         \
-      (void)hipFuncSetAttribute((const void*)dense_tiles_kernel<MODE, 32 * KC, KEEP>,                                      \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);                              \
+      (void)hipFuncSetAttribute((const void*)dense_tiles_wide_kernel<MODE, 32 * KC, KEEP>,                           \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dense_wide_lds(32 * KC));            \
     });                                                                                                              \
-    hipLaunchKernelGGL((dense_tiles_kernel<MODE, 32 * KC, KEEP>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, nq, row0, \
-                       chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, mcap, Mg, thr,    \
-                       cmask);                                                                                       \
+    hipLaunchKernelGGL((dense_tiles_wide_kernel<MODE, 32 * KC, KEEP>), grid, dim3(256), lds, st, qh, ql, qn, rl, rc, \
+                       nq, row0, chunk, G.hi, G.lo, G.norm, G.off_dev, s0, nseg, gps, cg, nht, nxcd, rtiles, mcap, Mg, \
+                       thr, cmask);                                                                                  \
     break;                                                                                                           \
   }
   switch (dk / 32) {
@@ -1154,13 +1059,12 @@ static void launch_dense_tiles(int dk, dim3 grid, size_t lds, hipStream_t st, co
     MIANN_DENSE_WIDE(2)
     MIANN_DENSE_WIDE(3)
     MIANN_DENSE_WIDE(4)
-    MIANN_DENSE_TILES(5)
-    MIANN_DENSE_TILES(6)
-    MIANN_DENSE_TILES(7)
-    MIANN_DENSE_TILES(8)
+    MIANN_DENSE_WIDE(5)
+    MIANN_DENSE_WIDE(6)
+    MIANN_DENSE_WIDE(7)
+    MIANN_DENSE_WIDE(8)
     default: break;
   }
-#undef MIANN_DENSE_TILES
 #undef MIANN_DENSE_WIDE
 }
 
@@ -1179,25 +1083,22 @@ static int64_t dense_tile_slots(int dk) {
   hipError_t e = hipErrorInvalidValue;
 #define MIANN_SLOTS_WIDE(KC)                                                                                         \
   case KC:                                                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_wide_kernel<0, 32 * KC, 4>, 256, 0);         \
-    break;
-#define MIANN_SLOTS_TILES(KC)                                                                                        \
-  case KC:                                                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_kernel<0, 32 * KC, 4>, 256,                  \
-                                                     dense_tiles_lds(dk));                                         \
+    (void)hipFuncSetAttribute((const void*)dense_tiles_wide_kernel<0, 32 * KC, 4>,                                   \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dense_wide_lds(32 * KC));              \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, dense_tiles_wide_kernel<0, 32 * KC, 4>, 256,             \
+                                                     dense_wide_lds(32 * KC));                                       \
     break;
   switch (dk / 32) {
     MIANN_SLOTS_WIDE(1)
     MIANN_SLOTS_WIDE(2)
     MIANN_SLOTS_WIDE(3)
     MIANN_SLOTS_WIDE(4)
-    MIANN_SLOTS_TILES(5)
-    MIANN_SLOTS_TILES(6)
-    MIANN_SLOTS_TILES(7)
-    MIANN_SLOTS_TILES(8)
+    MIANN_SLOTS_WIDE(5)
+    MIANN_SLOTS_WIDE(6)
+    MIANN_SLOTS_WIDE(7)
+    MIANN_SLOTS_WIDE(8)
     default: break;
   }
-#undef MIANN_SLOTS_TILES
 #undef MIANN_SLOTS_WIDE
   if (e != hipSuccess || per < 1) per = 1;
   const int64_t slots = (int64_t)ncu * per;
@@ -1241,9 +1142,9 @@ static int64_t dense_groups(int64_t rtiles, int nseg, int64_t ntmax, int64_t slo
 }
 
 // Rows per block of the tile passes for rows of dk elements, and the values pass 1 keeps per row and block.
-static int dense_block_rows(int dk) { return dk <= 128 ? 128 * dense_wide_sets(dk) : 64; }
+static int dense_block_rows(int dk) { return 128 * dense_wide_sets(dk); }
 // Lane slots (query sets x lane halves, per row) of a block of the pass-1 kernel for rows of dk elements.
-static int dense_slots_per_block(int dk) { return dk <= 128 ? 2 : 4; }
+static int dense_slots_per_block(int) { return 2; }
 
 __device__ __forceinline__ float dense_threshold(float b, float qf, float gf, float eps);
 
@@ -1772,7 +1673,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     // pass 1 keeps the 4 smallest values per lane slot for t <= 8, else all 16, and at least 2 t values per (row,
     // shard) where the tiles allow; the column groups of cg tiles per block are split to keep the chip's block
     // slots busy (dense_groups). The split for all rows in one chunk fixes mcap; a smaller chunk splits within it.
-    const int keep = t <= 8 ? 4 : 16;
+    const int keep = t <= 8 || dk > 224 ? 4 : 16;  // (rows of 256 elements leave no registers for 16)
     const int nvb = dense_slots_per_block(dk) * keep;
     const int64_t g_min = (2 * t + nvb - 1) / nvb;
     const int64_t tslots = dense_tile_slots(dk);
@@ -1804,16 +1705,15 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
     const int nxcd = rc ? 1 : device_xcds();
     const int64_t nitems = rtiles * nseg * gps;
     const dim3 gg((unsigned)((nitems + nxcd - 1) / nxcd * nxcd));
-    const size_t lds = dense_tiles_lds(dk);
     const unsigned gw = (unsigned)((chunk * nseg + 3) / 4);
     const unsigned gf = (unsigned)((chunk * nseg + 31) / 32);
     const int nh = (int)nht;
     for (int64_t row0 = 0; row0 < nq && e == hipSuccess; row0 += chunk) {
       if (keep == 16)
-        launch_dense_tiles<0, 16>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+        launch_dense_tiles<0, 16>(dk, gg, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                                   nxcd, rtiles, mcap, Mg, thr, cmask);
       else
-        launch_dense_tiles<0, 4>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+        launch_dense_tiles<0, 4>(dk, gg, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                                  nxcd, rtiles, mcap, Mg, thr, cmask);
       {
         const float eps = dense_eps(dk);
@@ -1833,7 +1733,7 @@ hipError_t dense_entry_split(int store_dt, const void* queries, int64_t nq, int 
           hipLaunchKernelGGL(dense_bound_kernel, dim3(gw), dim3(256), 0, st, Mg, nvb, mcap, cg, G.off_dev,
                              G.R_dev, s0, nseg, rc, nq, row0, chunk, t, rl, qn, G.gmax_dev, eps, thr);
       }
-      launch_dense_tiles<1, 4>(dk, gg, lds, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
+      launch_dense_tiles<1, 4>(dk, gg, st, qh, ql, qn, rl, rc, nq, row0, chunk, G, s0, nseg, (int)gps, cg, nh,
                                nxcd, rtiles, mcap, Mg, thr, cmask);
       // exact rescoring: one 8-lane team per item for t <= 16, one wave per item above
 #define MIANN_DENSE_FINAL(DTV)                                                                                       \
