@@ -110,7 +110,8 @@ def check_readout(W, x, t, tau, gmap, t_min, t_max, scale, seeds, iters, conf, t
     assert np.array_equal(seeds[:, 1:], gmap[top[:, 1:]])
 
 
-@pytest.mark.parametrize("d,h,R,n,t", [(24, 48, 40, 300, 8), (96, 256, 4096, 2000, 16), (96, 256, 1500, 700, 40)])
+@pytest.mark.parametrize("d,h,R,n,t", [(24, 48, 40, 300, 8), (96, 256, 4096, 2000, 16), (96, 256, 1500, 700, 40),
+                                       (32, 64, 200, 600, 8), (48, 128, 700, 900, 24)])
 def test_readout_matches_reference(d, h, R, n, t):
     say(f"predictor read-out d={d} h={h} R={R} n={n} t={t}")
     P = miann.Predictor(d, h, R, seed=5)
