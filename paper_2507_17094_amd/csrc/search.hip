@@ -24,6 +24,26 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
   if (q >= nq) return;
   const int lane = lane_id();
   const uint64_t* row = so + (size_t)q * S * k;
+  auto put = [&](int i, uint64_t m) {
+    const bool ok = m != kDummy;
+    ids[(size_t)q * k + i] = ok ? (uint32_t)m : kNone;
+    if (is_u8) ((int32_t*)dists)[(size_t)q * k + i] = ok ? (int32_t)(m >> 32) : 0x7FFFFFFF;
+    else ((uint32_t*)dists)[(size_t)q * k + i] = ok ? (uint32_t)(m >> 32) : 0x7F800000u;
+  };
+  const int nk = S * k;
+  if (nk <= 128) {
+    // all the stages' keys at once (distinct: the shards hold distinct nodes), sorted in registers
+    uint64_t v[2] = {lane < nk ? row[lane] : kDummy, 64 + lane < nk ? row[64 + lane] : kDummy};
+    if (nk <= 64) {
+      v[0] = bitonic_sort_u64<64>(v[0]);
+    } else {
+      bitonic_sort_regs<2>(v);
+    }
+    if (lane < k) put(lane, v[0]);
+    if (64 + lane < k) put(64 + lane, v[1]);
+    return;
+  }
+  // longer lists: k rounds of the smallest head of the S lists
   int head = 0;
   uint64_t cur = lane < S ? row[(size_t)lane * k] : kDummy;
   for (int i = 0; i < k; i++) {
@@ -33,12 +53,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const uint64_t* so, int64_t 
       const uint64_t other = xor_lane_u64(m, o);
       m = other < m ? other : m;
     }
-    if (lane == 0) {
-      const bool ok = m != kDummy;
-      ids[(size_t)q * k + i] = ok ? (uint32_t)m : kNone;
-      if (is_u8) ((int32_t*)dists)[(size_t)q * k + i] = ok ? (int32_t)(m >> 32) : 0x7FFFFFFF;
-      else ((uint32_t*)dists)[(size_t)q * k + i] = ok ? (uint32_t)(m >> 32) : 0x7F800000u;
-    }
+    if (lane == 0) put(i, m);
     if (m != kDummy && cur == m && lane < S) {
       head++;
       cur = head < k ? row[(size_t)lane * k + head] : kDummy;
