@@ -352,15 +352,21 @@ def reimport(gx, Xd, store):
                                      in_dtype="f32", store=store, degree=v.degree, ghost_degree=v.ghost_degree)
 
 
-def time_search(fn, reps=3):
+def time_search(fn, reps=3, streams=1):
+    """Seconds per call of fn (a batch on the current stream), back to back; with streams > 1 the calls alternate
+    over that many streams (independent batches, one's dense entry beside another's stages), reps per stream."""
     import torch
-    fn()
+    sts = [torch.cuda.current_stream()] if streams <= 1 else [torch.cuda.Stream() for _ in range(streams)]
+    for st in sts:
+        with torch.cuda.stream(st):
+            fn()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(reps):
-        fn()
+    for i in range(reps * len(sts)):
+        with torch.cuda.stream(sts[i % len(sts)]):
+            fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t) / reps
+    return (time.perf_counter() - t) / (reps * len(sts))
 
 
 def cpu_gt_check(X, Q, gt_gpu, k, nq):
@@ -432,7 +438,7 @@ def form_lowprec(args, name="lowprec1m", quick=False):
                     if name == "f32":
                         res[("ref", k, itopk, T)] = ids
                     agree = recall(res[("ref", k, itopk, T)], ids, k)
-                    sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts))
+                    sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts), streams=2)
                     rows.append(dict(itopk=itopk, T=T, recall=rc, agree_f32=agree, qps=W["nq"] / sec))
                     log(f"  k={k:3d} {name:4s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} "
                         f"agree_f32={agree:.4f} qps={W['nq'] / sec:,.0f}")
@@ -498,7 +504,7 @@ def form_learned(args, name="learned1m"):
             for form, o in (("ghost", opts), ("ghost_dense", dense_opts)):
                 ids, _, c = gx.search(Qd, k, itopk, T, o, counters=True)
                 rc = recall(gt, ids.cpu().numpy().view(np.uint32), k)
-                sec = time_search(lambda: gx.search(Qd, k, itopk, T, o))
+                sec = time_search(lambda: gx.search(Qd, k, itopk, T, o), streams=2)
                 nd = float((c[:, 0] + c[:, 4]).double().mean())
                 rows.append(dict(form=form, itopk=itopk, T=T, recall=rc, qps=W["nq"] / sec, n_dist=nd))
                 log(f"  {form:11s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} qps={W['nq'] / sec:,.0f} "
@@ -508,7 +514,7 @@ def form_learned(args, name="learned1m"):
                                                                    counters=True, gmap=gmap, budget_scale=bs)
                 rp = recall(gt, pi.cpu().numpy().view(np.uint32), k)
                 secp = time_search(lambda: learned.predicted_search(gx, P, Qd, k, itopk, 32, tau, 4, T, opts,
-                                                                    gmap=gmap, budget_scale=bs))
+                                                                    gmap=gmap, budget_scale=bs), streams=2)
                 ndp = float((pc[:, 0] + pc[:, 4]).double().mean())
                 fb = float((conf < tau).float().mean())
                 rows.append(dict(form=f"learned tau={tau} scale={bs}", itopk=itopk, T=T, recall=rp,
