@@ -140,6 +140,32 @@ def test_path_extension_parity(S):
         compare(g, o, label=f"S{S}-{kw}", ndist_check=not ghost_entry(opts))
 
 
+def test_batches_on_two_streams():
+    """Independent batches alternating over two streams, back to back (the benchmark's timing form: one batch's
+    dense entry beside another's stages on 4 resident shards): every batch's ids and distance bits equal the
+    single-stream search, whose ids match the oracle."""
+    say("two streams, S=4, dense entry on every stage")
+    X = mix(4000, 96, 8, 0.25, 33)
+    Q = mix(400, 96, 8, 0.25, 34)
+    ox = oracle.build_index(X, deg=32, S=4, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True, t_seeds=8)
+    g, o = run_both(ox, gx, Q, K, 32, 9, opts)
+    compare(g, o, label="S4-dense-every-stage", ndist_check=False)
+    qd = dev(Q)
+    ref_i, ref_d = gx.search(qd, K, 32, 9, opts)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    outs = []
+    for i in range(8):
+        with torch.cuda.stream(streams[i % 2]):
+            outs.append(gx.search(qd, K, 32, 9, opts))
+    torch.cuda.synchronize()
+    for i, (gi, gd) in enumerate(outs):
+        assert torch.equal(gi, ref_i), i
+        assert torch.equal(gd.view(torch.int32), ref_d.view(torch.int32)), i
+
+
 @pytest.mark.parametrize("store", ["f16", "fp8"])
 def test_low_precision_parity(store):
     say(f"low precision store={store}")
