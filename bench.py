@@ -17,6 +17,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -118,6 +119,12 @@ def oracle_from_device(gx, X):
     return ox
 
 
+def timed_stage_waves(args):
+    """The stage kernel's waves per SIMD in the timed batches: --stage-waves, else 6 when the batches alternate over
+    two or more streams (the other stream's batch fills the tail of a launch), else the library's choice (0)."""
+    return args.stage_waves if args.stage_waves >= 0 else (6 if args.streams > 1 else 0)
+
+
 def measured_traffic(workload, itopk, T, opts):
     """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE) per stage launch from the committed rocprofv3 records, when
     the stage kernel's sources and the setting are those the counters were taken on; None otherwise."""
@@ -134,7 +141,8 @@ def measured_traffic(workload, itopk, T, opts):
         st = rec["setting"]
         if (h.hexdigest() == rec["sources_sha256"] and workload == rec["workload"] and itopk == st["itopk"] and
                 T == st["T"] and opts.entry == st["entry"] and opts.search_width == st["search_width"] and
-                bool(opts.ghost_every_stage) == st["ghost_every_stage"] and opts.t_seeds == st.get("t_seeds", 0)):
+                bool(opts.ghost_every_stage) == st["ghost_every_stage"] and opts.t_seeds == st.get("t_seeds", 0) and
+                opts.stage_waves == st.get("stage_waves", 0)):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
 
@@ -175,7 +183,8 @@ def record_traffic(args):
     rec = {"kernel": "stage_kernel<f32, 3 chunks per row>", "sources": TRAFFIC_SOURCES,
            "sources_sha256": h.hexdigest(), "workload": args.workload,
            "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
-                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0},
+                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0,
+                       "stage_waves": timed_stage_waves(args)},
            "fetch_bytes_per_launch": fetch_kib * 1024 * f_scale, "write_bytes_per_launch": write_kib * 1024 * w_scale,
            "fetch_scale": f_scale, "write_scale": w_scale, "launches": min(n_f, n_w)}
     # one record per setting: a record of the same setting is replaced, records of other settings are kept while
@@ -211,9 +220,10 @@ def algorithmic_bytes(ctr, d, deg, deg_g, W, n_keep, S, k, row_bytes, ghost_in_s
     return float(hbm), float(vec), float(parent), float(ghost)
 
 
-def profiled_launch_us(workload, itopk, T, opts):
-    """The stage kernel's average launch duration (us) from the committed rocprofv3 kernel-trace record of this
-    setting, while the kernel's sources are the ones it was taken on; None otherwise."""
+def profiled_launch_us(workload, itopk, T, opts, streams):
+    """The stage kernel's launch duration (us) from the committed rocprofv3 kernel-trace record of this setting and
+    stream count, while the kernel's sources are the ones it was taken on: the union of its dispatch intervals per
+    dispatch (the live timing's definition), and the average dispatch duration; (None, None) otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_timing.json")
     if not os.path.exists(path):
@@ -226,21 +236,42 @@ def profiled_launch_us(workload, itopk, T, opts):
         st = rec["setting"]
         if (rec["sources_sha256"] == h.hexdigest() and rec["workload"] == workload and st["itopk"] == itopk and
                 st["T"] == T and st["entry"] == opts.entry and st["search_width"] == opts.search_width and
-                st["ghost_every_stage"] == bool(opts.ghost_every_stage) and st["t_seeds"] == opts.t_seeds):
-            return rec["stage_kernel_avg_us"]
-    return None
+                st["ghost_every_stage"] == bool(opts.ghost_every_stage) and st["t_seeds"] == opts.t_seeds and
+                st.get("stage_waves", 0) == opts.stage_waves and rec.get("streams", 1) == streams):
+            return rec.get("stage_kernel_union_us_per_launch", rec["stage_kernel_avg_us"]), rec["stage_kernel_avg_us"]
+    return None, None
 
 
 def record_timing(args):
-    """Writes the stage kernel's average launch duration for the --fixed setting from a rocprofv3 --stats csv
-    (kernel_stats.csv) to the profiles record, with the sources it was taken on."""
+    """Writes the stage kernel's launch duration for the --fixed setting from a rocprofv3 --kernel-trace --stats
+    run (its kernel_stats.csv, and the kernel_trace.csv beside it) to the profiles record, with the sources it was
+    taken on. Only the stage kernel build the timed batches use counts (--stage-waves 4, 5, 6: the 4-wave, 5-wave
+    or 6-wave register budget). Two durations are stored: the average over dispatches, and the time during which
+    some stage kernel ran (the union of the dispatch intervals) per dispatch, the definition of the live
+    timing: with batches on several streams, a dispatch that shares the GPU with another stream's work lasts
+    longer than the GPU time it takes."""
     import csv
     import hashlib
     f = args.fixed.split(",")
     rows = list(csv.DictReader(open(args.record_timing)))
-    stage = [r for r in rows if r["Name"].startswith("void miann::stage_kernel")]
+    occ = {4: 0, 5: 5, 6: 6}.get(timed_stage_waves(args))
+    suffix = f", {occ}>(miann::StageArgs)" if occ is not None else ""
+    stage = [r for r in rows if r["Name"].startswith("void miann::stage_kernel") and r["Name"].endswith(suffix)]
     calls = sum(int(r["Calls"]) for r in stage)
     avg = sum(float(r["TotalDurationNs"]) for r in stage) / calls / 1e3
+    names = {r["Name"] for r in stage}
+    trace = args.record_timing.replace("kernel_stats.csv", "kernel_trace.csv")
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(open(trace))
+                if r["Kernel_Name"] in names)
+    union_ns, a0, b0 = 0, None, None
+    for a, b in iv:
+        if b0 is None or a > b0:
+            union_ns += 0 if b0 is None else b0 - a0
+            a0, b0 = a, b
+        else:
+            b0 = max(b0, b)
+    union_ns += 0 if b0 is None else b0 - a0
+    assert len(iv) == calls, (len(iv), calls)
     h = hashlib.sha256()
     for src in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, src), "rb") as fh:
@@ -248,14 +279,17 @@ def record_timing(args):
     rec = {"kernel": "stage_kernel", "sources": TRAFFIC_SOURCES, "sources_sha256": h.hexdigest(),
            "workload": args.workload,
            "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
-                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0},
-           "stage_kernel_avg_us": avg, "calls": calls,
+                       "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0,
+                       "stage_waves": timed_stage_waves(args)},
+           "stage_kernel_avg_us": avg, "stage_kernel_union_us_per_launch": union_ns / calls / 1e3,
+           "streams": args.streams, "calls": calls,
            "other_kernels_avg_us": {r["Name"][:80]: float(r["AverageNs"]) / 1e3 for r in rows[:12]}}
     path = os.path.join(ROOT, "profiles", "stage_kernel_sharded1m_timing.json")
     recs = []
     if os.path.exists(path):
         recs = [r for r in json.load(open(path))
-                if r.get("sources_sha256") == rec["sources_sha256"] and r.get("setting") != rec["setting"]]
+                if r.get("sources_sha256") == rec["sources_sha256"] and
+                (r.get("setting"), r.get("streams", 1)) != (rec["setting"], rec["streams"])]
     recs.append(rec)
     with open(path, "w") as fh:
         json.dump(recs, fh, indent=1)
@@ -670,6 +704,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--streams", type=int, default=2,
                     help="streams the timed batches alternate over (1: back to back on one stream)")
+    ap.add_argument("--stage-waves", type=int, default=-1,
+                    help="waves per SIMD of the stage kernel in the timed batches (0 automatic, 4, 5, 6; default: "
+                         "6 with two or more streams, whose other batch fills the launch's tail, else automatic)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sharded1m", choices=sorted(WORKLOADS) + sorted(FORMS))
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -897,6 +934,9 @@ def main():
     # stream, the sum of the batches' stage phases.
     streams = ([torch.cuda.current_stream()] if args.streams <= 1 else
                [torch.cuda.Stream() for _ in range(args.streams)])
+    # the timed batches may take another register budget of the stage kernel; the results are checked equal
+    stage_waves = timed_stage_waves(args)
+    opts = dataclasses.replace(opts, stage_waves=stage_waves)
     for st_ in streams:
         with torch.cuda.stream(st_):
             for _ in range(args.warmup):
@@ -937,7 +977,7 @@ def main():
         ctr, W["d"], W["deg"], W["deg_g"], v0.W, n_keep, S, k, row_bytes, opts.entry == "ghost_graph")
     launch_ms = stage_union_ms / (S * args.steps)
     achieved = bytes_total / S / (launch_ms * 1e-3) / 1e9
-    prof_us = profiled_launch_us(args.workload, itopk, T, opts)
+    prof_us, prof_avg_us = profiled_launch_us(args.workload, itopk, T, opts, args.streams)
     probe = None
     probe_path = os.path.join(ROOT, "profiles", "gather_probe.json")
     if os.path.exists(probe_path):
@@ -956,7 +996,8 @@ def main():
                    "search_width": opts.search_width, "ghost_every_stage": bool(opts.ghost_every_stage),
                    "t_seeds": opts.t_seeds or min(opts.ghost_itopk, itopk),
                    "recall@10": best["recall"], "distance_accumulation": "f64 of f32 inputs",
-                   "streams": args.streams, "streams_identical": bool(streams_identical)},
+                   "streams": args.streams, "stage_waves": stage_waves,
+                   "streams_identical": bool(streams_identical)},
         "latency_ms": {"batch_p50": float(np.percentile(step_ms, 50)), "batch_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload, itopk, T, opts),
@@ -967,6 +1008,9 @@ def main():
                                                     "before stage 0 and after the last stage), per launch"),
                      "bytes_per_launch": bytes_total / S,
                      "rocprof_launch_us": prof_us,
+                     "rocprof_launch_us_definition": ("union of the traced stage-kernel dispatch intervals per "
+                                                      "dispatch, same streams and stage build as the timed batches"),
+                     "rocprof_dispatch_avg_us": prof_avg_us,
                      "frac_at_rocprof": (bytes_total / S / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBPS) if prof_us else None,
                      "gathered_vector_GBps": vec_bytes / S / (launch_ms * 1e-3) / 1e9,
                      "gathered_vector_frac": vec_bytes / S / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,

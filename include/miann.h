@@ -222,6 +222,14 @@ typedef struct {
                                mismatch is at most floor(theta * d) instead of the n_keep best (the
                                similarity-threshold variant of Sec. 6.3); a parent with a skipped slot is
                                re-expanded in the cool-down. 0 = top-n selection */
+  int32_t stage_waves;      /* waves per SIMD the stage kernel is built for: 0 = automatic (5 where the
+                               wave's LDS leaves room for 20 waves per CU, else 4; FP8 stores always 4);
+                               4 = the uncapped kernel; 6 = the 80-VGPR build, which exists for float32
+                               rows of at most 224 elements and is taken when the LDS leaves room for 24
+                               waves per CU (else the automatic choice); 5 = automatic. Results do not
+                               depend on it. 6 pays when another stream's work fills the launch's tail, as
+                               with independent batches on two streams; one stream alone runs 5 faster.
+                               Other values: MIANN_EINVAL */
   uint64_t seed;            /* random-stream seed */
   const uint64_t* qkeys;    /* device [nq] query keys (index within a request), NULL = row index */
   const uint32_t* seeds;    /* device [nq][n_seeds] local ids in each query's start shard */

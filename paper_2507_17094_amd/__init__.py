@@ -68,7 +68,7 @@ class SearchParams(C.Structure):
                 ("random_discard", C.c_int32), ("ppe", C.c_int32), ("forward_f", C.c_int32),
                 ("rerank_mult", C.c_int32), ("stop_on_no_change", C.c_int32), ("hash_log2", C.c_int32),
                 ("n_seeds", C.c_int32), ("ghost_every_stage", C.c_int32), ("dgs_threshold_permille", C.c_int32),
-                ("seed", C.c_uint64), ("qkeys", C.c_void_p), ("seeds", C.c_void_p),
+                ("stage_waves", C.c_int32), ("seed", C.c_uint64), ("qkeys", C.c_void_p), ("seeds", C.c_void_p),
                 ("max_iters_per_query", C.c_void_p), ("phase_ms", C.c_void_p),
                 ("phase_events", C.c_void_p)]
 
@@ -223,6 +223,7 @@ class SearchOptions:
     hash_log2: int = 0
     ghost_every_stage: bool = False
     dgs_threshold: float = 0.0  # theta of the similarity-threshold direction filter (0 = top-n selection)
+    stage_waves: int = 0  # stage kernel's waves per SIMD (0 automatic, 4, 5, 6); 6 pays with batches on two streams
     seed: int = 6
 
     def cstruct(self, qkeys=None, seeds=None, max_iters_per_query=None) -> SearchParams:
@@ -245,6 +246,7 @@ class SearchOptions:
         p.hash_log2 = self.hash_log2
         p.ghost_every_stage = int(bool(self.ghost_every_stage))
         p.dgs_threshold_permille = int(round(self.dgs_threshold * 1000))
+        p.stage_waves = self.stage_waves
         p.seed = self.seed & (2**64 - 1)
         p.qkeys = _ptr(qkeys)
         if seeds is not None:

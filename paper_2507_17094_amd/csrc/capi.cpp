@@ -468,6 +468,8 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
   if (sp.dgs && !ix->dgs) return fail(MIANN_ESTATE, "miann_search: the index has no direction table");
   if (sp.discard_permille < 0 || sp.discard_permille > 1000 || sp.cooldown_permille < 0 || sp.cooldown_permille > 1000)
     return fail(MIANN_EINVAL, "miann_search: discard/cooldown permille out of [0, 1000]");
+  if (sp.stage_waves != 0 && (sp.stage_waves < 4 || sp.stage_waves > 6))
+    return fail(MIANN_EINVAL, "miann_search: stage_waves = %d (0, 4, 5 or 6)", sp.stage_waves);
   if (sp.dgs_threshold_permille < 0 || sp.dgs_threshold_permille > 1000 ||
       (sp.dgs_threshold_permille > 0 && sp.random_discard))
     return fail(MIANN_EINVAL, "miann_search: dgs_threshold_permille out of [0, 1000] or combined with random_discard");
@@ -515,6 +517,7 @@ miann_status miann_search_impl(const miann_index* ix, const void* queries, int64
   a.entry = sp.entry;
   a.dgs = sp.dgs;
   a.n_keep = ix->deg - (sp.discard_permille * ix->deg) / 1000;
+  a.stage_waves = sp.stage_waves;
   a.dgs_thr = sp.dgs_threshold_permille > 0 ? (int)(((int64_t)sp.dgs_threshold_permille * ix->d) / 1000) : -1;
   a.cooldown_pm = sp.cooldown_permille;
   a.random_discard = sp.random_discard;

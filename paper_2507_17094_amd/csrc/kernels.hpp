@@ -40,6 +40,7 @@ struct StageArgs {
   int k, l, r, T, n_init, l_g, T_g, t_seeds;
   int entry, dgs, n_keep, cooldown_pm, random_discard, stop_on_no_change, ghost_every;
   int dgs_thr;              // similarity threshold on the sign mismatch (keep mm <= dgs_thr), -1 = top-n selection
+  int stage_waves;          // requested waves per SIMD of the stage kernel (0 = automatic, 4, 5, 6)
   int S, stage, ppe, f, rerank_m, lowp;
   int hash_log2, lp_pow2, waves_per_block;
   int per_wave_lds;         // bytes

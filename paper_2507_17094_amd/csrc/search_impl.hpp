@@ -592,14 +592,20 @@ struct Searcher {
   }
 };
 
-// Each stage kernel exists in two register budgets. OCC = 0 leaves the
+// Each stage kernel exists in several register budgets. OCC = 0 leaves the
 // VGPR count to the compiler (about 120 for f32 rows: 4 waves per SIMD).
 // OCC = 5 caps it at 96 VGPRs for 5 waves per SIMD, at the price of a few
 // spilled loop invariants; the launch takes it when the wave's LDS also
 // leaves room for 5 waves (small itopk), where the extra wave hides more
 // gather latency than the spills cost (f32, d = 96, itopk 64: 0.35 -> 0.32 ms
-// per stage launch). With large itopk the LDS caps occupancy anyway and the
-// uncapped kernel is faster.
+// per stage launch). OCC = 6 (80 VGPRs) exists for f32 rows of up to 7
+// chunks per lane (d <= 224), which fit it without spills; the caller asks
+// for it (stage_waves = 6). A launch of 10,000 queries fills 1.95 rounds of
+// the 5-wave slots but 1.63 of the 6-wave ones, so on one stream the longer
+// tail makes it slower; with independent batches on two streams the other
+// batch fills the tail and the extra wave hides more gather latency (itopk
+// 32, d = 96: 0.14-0.15 -> 0.12-0.14 ms per stage launch). With large itopk
+// the LDS caps occupancy anyway and the uncapped kernel is faster.
 template <int DT, int CPL, int OCC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 void stage_kernel(StageArgs a) {
@@ -789,7 +795,10 @@ static hipError_t launch_t(const StageArgs& a, hipStream_t st) {
   if constexpr (DT == DT_FP8) {
     return launch_occ<DT, CPL, 0>(a, st);
   } else {
-    // 5 waves per SIMD = 20 per CU must fit the CU's 160 KB of LDS
+    // 6 (5) waves per SIMD = 24 (20) per CU must fit the CU's 160 KB of LDS
+    if constexpr (DT == DT_F32 && CPL <= 7)
+      if (a.stage_waves == 6 && (int64_t)a.per_wave_lds * 24 <= 160 * 1024) return launch_occ<DT, CPL, 6>(a, st);
+    if (a.stage_waves == 4) return launch_occ<DT, CPL, 0>(a, st);
     if ((int64_t)a.per_wave_lds * 20 <= 160 * 1024) return launch_occ<DT, CPL, 5>(a, st);
     return launch_occ<DT, CPL, 0>(a, st);
   }

@@ -38,7 +38,9 @@ def test_version_and_host_side_validation():
     # argument validation happens before any device work: a null index is rejected
     p = miann.SearchParams()
     L.miann_search_params_default(ctypes.byref(p))
-    assert p.search_width == 1 and p.ghost_itopk == 32 and p.discard_permille == 500
+    assert p.search_width == 1 and p.ghost_itopk == 32 and p.discard_permille == 500 and p.stage_waves == 0
+    # the binding's layout follows the header: 19 int32 fields, then the 8-byte seed at the next 8-byte boundary
+    assert miann.SearchParams.stage_waves.offset == 72 and miann.SearchParams.seed.offset == 80
     rc = L.miann_search(None, None, 0, 10, 64, 10, ctypes.byref(p), None, None, None, None)
     assert rc == 1 and b"null index" in L.miann_last_error()
     rc = L.miann_index_info(None, None, None, None, None, None)

@@ -7,6 +7,8 @@ the id lists match on >= 99.9% of queries (float distances within 1e-5
 relative, uint8 distances bit-exact), and the per-query expansion, iteration,
 skipped-slot and rerank counts agree.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -143,7 +145,7 @@ def test_path_extension_parity(S):
 def test_batches_on_two_streams():
     """Independent batches alternating over two streams, back to back (the benchmark's timing form: one batch's
     dense entry beside another's stages on 4 resident shards): every batch's ids and distance bits equal the
-    single-stream search, whose ids match the oracle."""
+    single-stream search, whose ids match the oracle; so do the stage kernel's 4- and 6-wave builds."""
     say("two streams, S=4, dense entry on every stage")
     X = mix(4000, 96, 8, 0.25, 33)
     Q = mix(400, 96, 8, 0.25, 34)
@@ -164,6 +166,16 @@ def test_batches_on_two_streams():
     for i, (gi, gd) in enumerate(outs):
         assert torch.equal(gi, ref_i), i
         assert torch.equal(gd.view(torch.int32), ref_d.view(torch.int32)), i
+    for w in (4, 6):
+        ow = dataclasses.replace(opts, stage_waves=w)
+        outs = []
+        for i in range(4):
+            with torch.cuda.stream(streams[i % 2]):
+                outs.append(gx.search(qd, K, 32, 9, ow))
+        torch.cuda.synchronize()
+        for i, (gi, gd) in enumerate(outs):
+            assert torch.equal(gi, ref_i), (w, i)
+            assert torch.equal(gd.view(torch.int32), ref_d.view(torch.int32)), (w, i)
 
 
 @pytest.mark.parametrize("store", ["f16", "fp8"])
@@ -316,5 +328,9 @@ def test_validation_errors(small):
         gx.search(q, 10, 64, 10, miann.SearchOptions(search_width=3))  # 3 * 32 > 64
     with pytest.raises(miann.MiannError):
         gx.search(q, 10, 64, 10, miann.SearchOptions(hash_log2=7))
+    for w in (3, 7):
+        with pytest.raises(miann.MiannError) as e:
+            gx.search(q, 10, 64, 10, miann.SearchOptions(stage_waves=w))
+        assert "stage_waves" in str(e.value)
     ids, dists = gx.search(dev(Q[:0]), 10, 64, 10)
     assert ids.shape == (0, 10)
