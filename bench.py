@@ -142,6 +142,7 @@ def measured_traffic(workload, itopk, T, opts):
         if (h.hexdigest() == rec["sources_sha256"] and workload == rec["workload"] and itopk == st["itopk"] and
                 T == st["T"] and opts.entry == st["entry"] and opts.search_width == st["search_width"] and
                 bool(opts.ghost_every_stage) == st["ghost_every_stage"] and opts.t_seeds == st.get("t_seeds", 0) and
+                opts.discard == st.get("discard", 0.5) and opts.cooldown == st.get("cooldown", 0.3) and
                 opts.stage_waves == st.get("stage_waves", 0)):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
@@ -184,6 +185,7 @@ def record_traffic(args):
            "sources_sha256": h.hexdigest(), "workload": args.workload,
            "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
                        "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0,
+                       "discard": float(f[7]) if len(f) > 7 else 0.5, "cooldown": float(f[8]) if len(f) > 8 else 0.3,
                        "stage_waves": timed_stage_waves(args)},
            "fetch_bytes_per_launch": fetch_kib * 1024 * f_scale, "write_bytes_per_launch": write_kib * 1024 * w_scale,
            "fetch_scale": f_scale, "write_scale": w_scale, "launches": min(n_f, n_w)}
@@ -237,6 +239,7 @@ def profiled_launch_us(workload, itopk, T, opts, streams):
         if (rec["sources_sha256"] == h.hexdigest() and rec["workload"] == workload and st["itopk"] == itopk and
                 st["T"] == T and st["entry"] == opts.entry and st["search_width"] == opts.search_width and
                 st["ghost_every_stage"] == bool(opts.ghost_every_stage) and st["t_seeds"] == opts.t_seeds and
+                st.get("discard", 0.5) == opts.discard and st.get("cooldown", 0.3) == opts.cooldown and
                 st.get("stage_waves", 0) == opts.stage_waves and rec.get("streams", 1) == streams):
             return rec.get("stage_kernel_union_us_per_launch", rec["stage_kernel_avg_us"]), rec["stage_kernel_avg_us"]
     return None, None
@@ -280,6 +283,7 @@ def record_timing(args):
            "workload": args.workload,
            "setting": {"itopk": int(f[0]), "T": int(f[1]), "entry": f[2], "search_width": int(f[3]),
                        "ghost_every_stage": bool(int(f[4])), "t_seeds": int(f[6]) if len(f) > 6 else 0,
+                       "discard": float(f[7]) if len(f) > 7 else 0.5, "cooldown": float(f[8]) if len(f) > 8 else 0.3,
                        "stage_waves": timed_stage_waves(args)},
            "stage_kernel_avg_us": avg, "stage_kernel_union_us_per_launch": union_ns / calls / 1e3,
            "streams": args.streams, "calls": calls,
@@ -713,7 +717,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle leg (0 = all)")
     ap.add_argument("--plain", type=int, default=1, help="also sweep the plain (unsharded, random-entry) search")
     ap.add_argument("--fixed", default="",
-                    help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage[,ghost_iters[,t_seeds]]")
+                    help="skip the sweep: itopk,T,entry,search_width,ghost_every_stage[,ghost_iters[,t_seeds"
+                         "[,discard[,cooldown]]]] (discard rho and cool-down c of the direction filter: 0.5, 0.3)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the reference for the HBM "
                          "byte counters")
@@ -855,11 +860,18 @@ def main():
         ("gs-all+dgs r2", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True)),
         ("gs-all+dgs r2 Tg4", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True,
                                 ghost_iters=4)),
+        # the direction filter in every iteration (no cool-down, c = 0) with a larger discard fraction rho
+        ("gsdense-all+dgs r2 t8 rho.625 c0", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
+                                               t_seeds=8, discard=0.625, cooldown=0.0)),
+        ("gsdense-all+dgs r2 t8 rho.75 c0", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
+                                              t_seeds=8, discard=0.75, cooldown=0.0)),
     ]
     if args.fixed:
         f = args.fixed.split(",")
         fo = miann.SearchOptions(entry=f[2], dgs=True, search_width=int(f[3]), ghost_every_stage=bool(int(f[4])),
-                                 ghost_iters=int(f[5]) if len(f) > 5 else 8, t_seeds=int(f[6]) if len(f) > 6 else 0)
+                                 ghost_iters=int(f[5]) if len(f) > 5 else 8, t_seeds=int(f[6]) if len(f) > 6 else 0,
+                                 discard=float(f[7]) if len(f) > 7 else 0.5,
+                                 cooldown=float(f[8]) if len(f) > 8 else 0.3)
         ids, _ = run(gx, int(f[0]), int(f[1]), fo)
         torch.cuda.synchronize()
         best = dict(form="tuned", variant="fixed", itopk=int(f[0]), T=int(f[1]), opts=fo,
@@ -995,6 +1007,7 @@ def main():
                    "itopk": itopk, "max_iters": T, "entry": opts.entry, "dgs": bool(opts.dgs),
                    "search_width": opts.search_width, "ghost_every_stage": bool(opts.ghost_every_stage),
                    "t_seeds": opts.t_seeds or min(opts.ghost_itopk, itopk),
+                   "dgs_discard": opts.discard, "dgs_cooldown": opts.cooldown,
                    "recall@10": best["recall"], "distance_accumulation": "f64 of f32 inputs",
                    "streams": args.streams, "stage_waves": stage_waves,
                    "streams_identical": bool(streams_identical)},
@@ -1039,7 +1052,8 @@ def main():
         ox = oracle_from_device(gx, X)
         m = args.cpu_sample or nq
         okw = dict(k=k, l=itopk, T=T, entry=opts.entry, dgs_on=opts.dgs, l_g=opts.ghost_itopk, T_g=opts.ghost_iters,
-                   r=opts.search_width, ghost_every_stage=opts.ghost_every_stage, t_seeds=opts.t_seeds or None)
+                   r=opts.search_width, ghost_every_stage=opts.ghost_every_stage, t_seeds=opts.t_seeds or None,
+                   discard=opts.discard, cooldown=opts.cooldown)
         t0 = time.perf_counter()
         oi, od, _ = oracle.search(ox, Q[:m], **okw)
         t_cpu = time.perf_counter() - t0

@@ -52,6 +52,8 @@ CASES = [
     ("itopk_k", 10, 40, dict()),
     ("T0", 64, 0, dict(n_init=100)),
     ("discard_07", 64, 80, dict(dgs=True, discard=0.7, cooldown=0.1)),
+    ("discard_0625_c0_r2", 32, 8, dict(dgs=True, discard=0.625, cooldown=0.0, search_width=2)),
+    ("discard_075_c0_r2", 32, 9, dict(dgs=True, discard=0.75, cooldown=0.0, search_width=2)),
     ("dgs_threshold_040", 64, 80, dict(dgs=True, dgs_threshold=0.4)),
     ("dgs_threshold_035_r2", 64, 60, dict(dgs=True, dgs_threshold=0.35, search_width=2)),
 ]
@@ -140,6 +142,21 @@ def test_path_extension_parity(S):
         opts = miann.SearchOptions(**kw)
         g, o = run_both(ox, gx, Q, K, 64, 50, opts)
         compare(g, o, label=f"S{S}-{kw}", ndist_check=not ghost_entry(opts))
+
+
+@pytest.mark.parametrize("discard,T", [(0.625, 8), (0.75, 9)])
+def test_sharded_dense_every_stage_no_cooldown(discard, T):
+    """The direction filter in every iteration (c = 0) with a larger discard fraction, on 4 shards with the dense
+    entry on every stage: ids match the oracle."""
+    say(f"S=4 dense every stage, discard {discard}, cooldown 0, T {T}")
+    X = mix(4000, 96, 8, 0.25, 33)
+    Q = mix(400, 96, 8, 0.25, 34)
+    ox = oracle.build_index(X, deg=32, S=4, dgs=True, ghost_ratio=0.05, deg_g=16)
+    gx = to_device_index(ox)
+    opts = miann.SearchOptions(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True, t_seeds=8,
+                               discard=discard, cooldown=0.0)
+    g, o = run_both(ox, gx, Q, K, 32, T, opts)
+    compare(g, o, label=f"S4-dense-every-stage-c0-{discard}", ndist_check=False)
 
 
 def test_batches_on_two_streams():
