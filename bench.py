@@ -33,7 +33,7 @@ HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
     "sharded1m": dict(N=1_000_000, d=96, C=1000, sigma=0.25, nq=10_000, k=10, deg=32, S=4, ghost_ratio=0.01,
-                      deg_g=32, itopks=(32, 64, 128, 256), Ts=(8, 9, 10, 12, 16, 24)),
+                      deg_g=32, itopks=(32, 64, 128, 256), Ts=(7, 8, 9, 10, 12, 16, 24)),
     "tiny": dict(N=10_000, d=128, C=32, sigma=0.3, nq=1_000, k=10, deg=32, S=1, ghost_ratio=0.01, deg_g=32,
                  itopks=(32, 64, 128), Ts=(16, 32, 64)),
 }
@@ -860,7 +860,9 @@ def main():
         ("gs-all+dgs r2", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True)),
         ("gs-all+dgs r2 Tg4", O(entry="ghost_graph", dgs=True, search_width=2, ghost_every_stage=True,
                                 ghost_iters=4)),
-        # the direction filter in every iteration (no cool-down, c = 0) with a larger discard fraction rho
+        # the direction filter in every iteration (no cool-down, c = 0), at the default and larger discard fractions
+        ("gsdense-all+dgs r2 t8 rho.5 c0", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
+                                             t_seeds=8, discard=0.5, cooldown=0.0)),
         ("gsdense-all+dgs r2 t8 rho.625 c0", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
                                                t_seeds=8, discard=0.625, cooldown=0.0)),
         ("gsdense-all+dgs r2 t8 rho.75 c0", O(entry="ghost_dense", dgs=True, search_width=2, ghost_every_stage=True,
