@@ -33,7 +33,7 @@ HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
     "sharded1m": dict(N=1_000_000, d=96, C=1000, sigma=0.25, nq=10_000, k=10, deg=32, S=4, ghost_ratio=0.01,
-                      deg_g=32, itopks=(32, 64, 128, 256), Ts=(7, 8, 9, 10, 12, 16, 24)),
+                      deg_g=32, itopks=(32, 64, 128, 256), Ts=(6, 7, 8, 9, 10, 12, 16, 24)),
     "tiny": dict(N=10_000, d=128, C=32, sigma=0.3, nq=1_000, k=10, deg=32, S=1, ghost_ratio=0.01, deg_g=32,
                  itopks=(32, 64, 128), Ts=(16, 32, 64)),
 }

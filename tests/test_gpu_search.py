@@ -144,7 +144,7 @@ def test_path_extension_parity(S):
         compare(g, o, label=f"S{S}-{kw}", ndist_check=not ghost_entry(opts))
 
 
-@pytest.mark.parametrize("discard,T", [(0.5, 7), (0.625, 7), (0.625, 8), (0.75, 9)])
+@pytest.mark.parametrize("discard,T", [(0.5, 6), (0.5, 7), (0.625, 7), (0.625, 8), (0.75, 9)])
 def test_sharded_dense_every_stage_no_cooldown(discard, T):
     """The direction filter in every iteration (c = 0) with a larger discard fraction, on 4 shards with the dense
     entry on every stage: ids match the oracle."""
