@@ -119,6 +119,18 @@ def oracle_from_device(gx, X):
     return ox
 
 
+def interval_union(intervals):
+    """Total length of the union of (start, end) intervals: the time during which at least one of them ran."""
+    total, a0, b0 = 0, None, None
+    for a, b in sorted(intervals):
+        if b0 is None or a > b0:
+            total += 0 if b0 is None else b0 - a0
+            a0, b0 = a, b
+        else:
+            b0 = max(b0, b)
+    return total + (0 if b0 is None else b0 - a0)
+
+
 def timed_stage_waves(args):
     """The stage kernel's waves per SIMD in the timed batches: --stage-waves, else 6 when the batches alternate over
     two or more streams (the other stream's batch fills the tail of a launch), else the library's choice (0)."""
@@ -264,16 +276,9 @@ def record_timing(args):
     avg = sum(float(r["TotalDurationNs"]) for r in stage) / calls / 1e3
     names = {r["Name"] for r in stage}
     trace = args.record_timing.replace("kernel_stats.csv", "kernel_trace.csv")
-    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(open(trace))
-                if r["Kernel_Name"] in names)
-    union_ns, a0, b0 = 0, None, None
-    for a, b in iv:
-        if b0 is None or a > b0:
-            union_ns += 0 if b0 is None else b0 - a0
-            a0, b0 = a, b
-        else:
-            b0 = max(b0, b)
-    union_ns += 0 if b0 is None else b0 - a0
+    iv = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(open(trace))
+          if r["Kernel_Name"] in names]
+    union_ns = interval_union(iv)
     assert len(iv) == calls, (len(iv), calls)
     h = hashlib.sha256()
     for src in TRAFFIC_SOURCES:
@@ -966,17 +971,9 @@ def main():
     wall = time.perf_counter() - t0
     iv = np.array([[evs.elapsed(4 * i + j, 4 * i + j + 1) for j in range(3)] for i in range(args.steps)])
     step_ms = np.array([evs.elapsed(4 * i, 4 * i + 3) for i in range(args.steps)])
-    spans = sorted((evs.elapsed(0, 4 * i + 1), evs.elapsed(0, 4 * i + 2)) for i in range(args.steps))
+    spans = [(evs.elapsed(0, 4 * i + 1), evs.elapsed(0, 4 * i + 2)) for i in range(args.steps)]
     evs.close()
-    stage_union_ms, cur_a, cur_b = 0.0, None, None
-    for a, b in spans:
-        if cur_b is None or a > cur_b:
-            if cur_b is not None:
-                stage_union_ms += cur_b - cur_a
-            cur_a, cur_b = a, b
-        else:
-            cur_b = max(cur_b, b)
-    stage_union_ms += cur_b - cur_a
+    stage_union_ms = interval_union(spans)
     streams_identical = all(x is None or torch.equal(x, ids) for x in last_ids)
     assert streams_identical, "a stream's results differ from the single-stream search"
     ms_per_step = wall / args.steps * 1e3
