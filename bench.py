@@ -463,28 +463,32 @@ def form_lowprec(args, name="lowprec1m", quick=False):
     # exact nearest ghosts as the entry: the mixture's k-NN graph splits into one component per mixture
     # component, so the entry must land in the query's component
     opts = miann.SearchOptions(entry="ghost_dense", dgs=True)
+    # the direction filter with the paper's cool-down, and (full form) in every iteration (c = 0)
+    filters = (("c0.3", opts),) if quick else (("c0.3", opts), ("c0", dataclasses.replace(opts, cooldown=0.0)))
     res = {}
     grid = ((10, (32,), (32,)), (100, (256,), (64,))) if quick else \
-        ((10, (32, 64, 128), (32, 64, 128)), (100, (128, 256, 512), (32, 64, 128)))
+        ((10, (32, 64, 128), (16, 24, 32, 48, 64, 128)), (100, (128, 256, 512), (32, 48, 64, 128)))
     for k, itopks, Ts in grid:
         gt = gt100[:, :k]
         for name, gx in idx.items():
             rows = []
-            for itopk in itopks:
-                for T in Ts:
-                    if T > 2 * itopk:
-                        continue
-                    ids, _ = gx.search(Qd, k, itopk, T, opts)
-                    ids = ids.cpu().numpy().view(np.uint32)
-                    rc = recall(gt, ids, k)
-                    # agreement with the FP32 traversal at the same setting
-                    if name == "f32":
-                        res[("ref", k, itopk, T)] = ids
-                    agree = recall(res[("ref", k, itopk, T)], ids, k)
-                    sec = time_search(lambda: gx.search(Qd, k, itopk, T, opts), streams=2)
-                    rows.append(dict(itopk=itopk, T=T, recall=rc, agree_f32=agree, qps=W["nq"] / sec))
-                    log(f"  k={k:3d} {name:4s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} "
-                        f"agree_f32={agree:.4f} qps={W['nq'] / sec:,.0f}")
+            for fname, fo in filters:
+                for itopk in itopks:
+                    for T in Ts:
+                        if T > 2 * itopk:
+                            continue
+                        ids, _ = gx.search(Qd, k, itopk, T, fo)
+                        ids = ids.cpu().numpy().view(np.uint32)
+                        rc = recall(gt, ids, k)
+                        # agreement with the FP32 traversal at the same setting
+                        if name == "f32":
+                            res[("ref", fname, k, itopk, T)] = ids
+                        agree = recall(res[("ref", fname, k, itopk, T)], ids, k)
+                        sec = time_search(lambda: gx.search(Qd, k, itopk, T, fo), streams=2)
+                        rows.append(dict(filter=fname, itopk=itopk, T=T, recall=rc, agree_f32=agree,
+                                         qps=W["nq"] / sec))
+                        log(f"  k={k:3d} {name:4s} {fname:4s} itopk={itopk:3d} T={T:3d} recall={rc:.4f} "
+                            f"agree_f32={agree:.4f} qps={W['nq'] / sec:,.0f}")
             ok = [r for r in rows if r["recall"] >= 0.95]
             best = max(ok, key=lambda r: r["qps"]) if ok else max(rows, key=lambda r: r["recall"])
             res[(name, k)] = dict(best=best, rows=rows)
